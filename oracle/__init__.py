@@ -1,0 +1,231 @@
+"""ctypes binding of the CPU oracle (liboracle.so).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg.  The product package never imports it.
+
+Build with `python -m oracle.build` (or `__graft_entry__.build()`).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+FIXPOINT, FAILED = 0, 1
+SCHED_GS, SCHED_JACOBI, SCHED_PERM, SCHED_SELECT, SCHED_REVERSE = 0, 1, 2, 3, 4
+ENUMERATE, MINIMIZE = 0, 1
+FIRST_FAIL, INPUT_ORDER = 0, 1
+OUT_ALL, OUT_OPTIMAL, OUT_UNSAT, OUT_LIMIT = 0, 1, 2, 3
+OUTCOME_NAMES = {OUT_ALL: "all", OUT_OPTIMAL: "optimal", OUT_UNSAT: "unsat",
+                 OUT_LIMIT: "limit"}
+
+_P32 = C.POINTER(C.c_int32)
+
+
+class _Model(C.Structure):
+    _fields_ = [("nvars", C.c_int32), ("lb0", _P32), ("ub0", _P32),
+                ("nrows", C.c_int32), ("row_ptr", _P32), ("coef", _P32),
+                ("var", _P32), ("rhs", _P32), ("nreif", C.c_int32),
+                ("reif", _P32), ("ndec", C.c_int32), ("dec", _P32),
+                ("objective", C.c_int32)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("nodes", C.c_int64), ("fails", C.c_int64),
+                ("solutions", C.c_int64), ("max_depth", C.c_int64),
+                ("sweeps", C.c_int64), ("best", C.c_int32),
+                ("outcome", C.c_int32), ("sol_hash", C.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"oracle library not built: {LIB_PATH} "
+                               "(run `python -m oracle.build`)")
+        L = C.CDLL(LIB_PATH)
+        MP = C.POINTER(_Model)
+        L.orc_validate.argtypes = [MP]
+        L.orc_validate.restype = C.c_int32
+        L.orc_propagate.argtypes = [MP, _P32, _P32, C.c_int32, C.c_uint64,
+                                    C.POINTER(C.c_int64)]
+        L.orc_propagate.restype = C.c_int32
+        L.orc_jacobi_step.argtypes = [MP, _P32, _P32]
+        L.orc_jacobi_step.restype = C.c_int32
+        L.orc_gs_step.argtypes = [MP, _P32, _P32]
+        L.orc_gs_step.restype = C.c_int32
+        L.orc_solve.argtypes = [MP, C.c_int32, C.c_int32, C.c_int64, _P32,
+                                C.c_int64, _P32, C.POINTER(_Stats)]
+        L.orc_solve.restype = C.c_int32
+        L.orc_solution_hash.argtypes = [_P32, C.c_int32]
+        L.orc_solution_hash.restype = C.c_uint64
+        L.orc_brute_points.argtypes = [MP, _P32, C.c_int64, C.POINTER(C.c_uint64)]
+        L.orc_brute_points.restype = C.c_int64
+        L.orc_brute_rcpsp.argtypes = [C.c_int32, _P32, C.c_int32, _P32, C.c_int32,
+                                      _P32, _P32, C.c_int32, _P32]
+        L.orc_brute_rcpsp.restype = C.c_int32
+        L.orc_check_schedule.argtypes = [C.c_int32, _P32, C.c_int32, _P32,
+                                         C.c_int32, _P32, _P32, _P32, _P32]
+        L.orc_check_schedule.restype = C.c_int32
+        L.orc_floor_div.argtypes = [C.c_int64, C.c_int64]
+        L.orc_floor_div.restype = C.c_int64
+        L.orc_ceil_div.argtypes = [C.c_int64, C.c_int64]
+        L.orc_ceil_div.restype = C.c_int64
+        _lib = L
+    return _lib
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_P32)
+
+
+class OracleModel:
+    """Holds int32 copies of a `Model`'s arrays and the C struct over them."""
+
+    def __init__(self, model):
+        self.model = model
+        self._keep = [_i32(model.lb), _i32(model.ub), _i32(model.lin_ptr),
+                      _i32(model.lin_coef), _i32(model.lin_var), _i32(model.lin_rhs),
+                      _i32(model.reif).reshape(-1), _i32(model.decision)]
+        lb, ub, ptr, coef, var, rhs, reif, dec = self._keep
+        self.s = _Model(model.nvars, _ptr(lb), _ptr(ub), model.nrows, _ptr(ptr),
+                        _ptr(coef), _ptr(var), _ptr(rhs), model.nreif, _ptr(reif),
+                        int(dec.shape[0]), _ptr(dec), int(model.objective))
+
+    def ref(self):
+        return C.byref(self.s)
+
+
+def _om(model) -> OracleModel:
+    return model if isinstance(model, OracleModel) else OracleModel(model)
+
+
+def validate(model) -> int:
+    return int(lib().orc_validate(_om(model).ref()))
+
+
+def propagate(model, lb=None, ub=None, sched=SCHED_GS, seed=0):
+    """Fixed point above (lb, ub) (default: the model's initial box).
+    Returns (status, lb, ub, sweeps); status FIXPOINT or FAILED."""
+    om = _om(model)
+    m = om.model
+    lb = np.array(m.lb if lb is None else lb, dtype=np.int32, copy=True)
+    ub = np.array(m.ub if ub is None else ub, dtype=np.int32, copy=True)
+    sw = C.c_int64(0)
+    st = lib().orc_propagate(om.ref(), _ptr(lb), _ptr(ub), int(sched),
+                             C.c_uint64(seed & (2**64 - 1)), C.byref(sw))
+    if st < 0:
+        raise ValueError(f"orc_propagate error {st}")
+    return int(st), lb, ub, int(sw.value)
+
+
+def jacobi_step(model, lb, ub):
+    om = _om(model)
+    lb = np.array(lb, dtype=np.int32, copy=True)
+    ub = np.array(ub, dtype=np.int32, copy=True)
+    st = lib().orc_jacobi_step(om.ref(), _ptr(lb), _ptr(ub))
+    if st < 0:
+        raise ValueError(f"orc_jacobi_step error {st}")
+    return int(st), lb, ub
+
+
+def gs_step(model, lb, ub):
+    om = _om(model)
+    lb = np.array(lb, dtype=np.int32, copy=True)
+    ub = np.array(ub, dtype=np.int32, copy=True)
+    st = lib().orc_gs_step(om.ref(), _ptr(lb), _ptr(ub))
+    if st < 0:
+        raise ValueError(f"orc_gs_step error {st}")
+    return int(st), lb, ub
+
+
+def solve(model, mode=None, branching=FIRST_FAIL, node_limit=0, sol_cap=0):
+    """Depth-first search.  Returns a dict with nodes, fails, solutions,
+    max_depth, sweeps, best, outcome, sol_hash, solutions_list, best_assign."""
+    om = _om(model)
+    m = om.model
+    mode = m.mode if mode is None else mode
+    nd = int(m.decision.shape[0])
+    buf = np.zeros((max(sol_cap, 1), max(nd, 1)), dtype=np.int32)
+    best = np.zeros(max(nd, 1), dtype=np.int32)
+    st = _Stats()
+    rc = lib().orc_solve(om.ref(), int(mode), int(branching), int(node_limit),
+                         _ptr(buf) if sol_cap > 0 else None, int(sol_cap),
+                         _ptr(best), C.byref(st))
+    if rc < 0:
+        raise ValueError(f"orc_solve error {rc}")
+    nsol = int(min(st.solutions, sol_cap))
+    return dict(nodes=st.nodes, fails=st.fails, solutions=st.solutions,
+                max_depth=st.max_depth, sweeps=st.sweeps,
+                best=None if st.best == 2**31 - 1 else int(st.best),
+                outcome=int(st.outcome), sol_hash=int(st.sol_hash),
+                solutions_list=buf[:nsol, :nd].copy(),
+                best_assign=best[:nd].copy() if st.best != 2**31 - 1 else None)
+
+
+def solution_hash(vals) -> int:
+    v = _i32(vals)
+    return int(lib().orc_solution_hash(_ptr(v), int(v.shape[0])))
+
+
+def brute_points(model, cap=0):
+    """(count, hash, solutions[:cap]) of all points of the initial box."""
+    om = _om(model)
+    nd = int(om.model.decision.shape[0])
+    buf = np.zeros((max(cap, 1), max(nd, 1)), dtype=np.int32)
+    h = C.c_uint64(0)
+    n = lib().orc_brute_points(om.ref(), _ptr(buf) if cap > 0 else None, int(cap),
+                               C.byref(h))
+    if n < 0:
+        raise ValueError("orc_brute_points: invalid model")
+    return int(n), int(h.value), buf[:min(n, cap), :nd].copy()
+
+
+def _raw(meta):
+    n = len(meta["durations"])
+    dur = _i32(meta["durations"])
+    edges = _i32(np.asarray(meta["edges"], dtype=np.int32).reshape(-1))
+    dem = _i32(np.asarray(meta["demands"], dtype=np.int32).reshape(-1))
+    cap = _i32(meta["capacities"])
+    return n, dur, edges, dem, cap
+
+
+def brute_rcpsp(meta):
+    """Minimum makespan of the raw RCPSP in `meta` (None if infeasible)."""
+    n, dur, edges, dem, cap = _raw(meta)
+    best_s = np.zeros(max(n, 1), dtype=np.int32)
+    b = lib().orc_brute_rcpsp(n, _ptr(dur), int(edges.shape[0] // 2), _ptr(edges),
+                              len(meta["capacities"]), _ptr(dem), _ptr(cap),
+                              int(meta["horizon"]), _ptr(best_s))
+    if b == -2:
+        raise ValueError("edges must go from lower to higher task index")
+    return (None, None) if b < 0 else (int(b), best_s[:n].copy())
+
+
+def check_schedule(meta, s):
+    n, dur, edges, dem, cap = _raw(meta)
+    s = _i32(s)
+    ms = C.c_int32(0)
+    ok = lib().orc_check_schedule(n, _ptr(dur), int(edges.shape[0] // 2), _ptr(edges),
+                                  len(meta["capacities"]), _ptr(dem), _ptr(cap),
+                                  _ptr(s), C.cast(C.pointer(ms), _P32))
+    return bool(ok), int(ms.value)
+
+
+def floor_div(a: int, b: int) -> int:
+    return int(lib().orc_floor_div(a, b))
+
+
+def ceil_div(a: int, b: int) -> int:
+    return int(lib().orc_ceil_div(a, b))

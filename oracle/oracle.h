@@ -1,0 +1,148 @@
+/*
+ * CPU oracle for PCCP propagation and propagate-and-search.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is a plain, sequential, obviously
+ * correct statement of what the solver computes; it exists so that tests, the
+ * smoke check and the benchmark's CPU-baseline leg can check the HIP solver
+ * against it.  The product (libpccp and its Python binding) never links,
+ * loads or calls it, and it shares no source with the product.
+ *
+ * Paper: P. Talbot, F. Pinel, P. Bouvry, "A Variant of Concurrent Constraint
+ * Programming on GPU", AAAI 2022 (arXiv 2207.12116).
+ *
+ * What is computed (and where it is defined):
+ *   - Store: one interval (lb, ub) of the lattice IZ = ZInc x ZDec per
+ *     variable (§2, interval lattice); a store with an empty interval is the
+ *     failed store (top), detected at once (§5, fixed point loop: failure is
+ *     a fixed point on top).
+ *   - Linear row  sum_t a_t * x_t <= c: the bound tell of §2 (compilation of
+ *     x + y <= c), generalised to any nonzero integer coefficients with
+ *     rounding toward -inf / +inf.  The resource sums of §2 are such rows.
+ *   - Reified overlap  b <=> (si <= sj and sj < si + d): the four guarded
+ *     processes of §2 (compilation of phi <=> psi), with the entailment tests
+ *     of §2 extended to conjunction and negation, and disjunction propagated
+ *     by the usual "one disjunct disentailed" rule (the paper gives no
+ *     compilation of a disjunction or of negated entailment).
+ *   - propagate: the least fixed point above a store (§3, Theorem 2), computed
+ *     by the sequential composition of all guarded commands repeated until
+ *     nothing changes (§3, Proposition 3: seq P has the same fixed point).
+ *     Jacobi, random-permutation, random-selection and reversed schedules are
+ *     provided for the order-independence tests (§3, fairness and chaotic
+ *     iterations; Theorem 6).
+ *   - solve: depth-first propagate-and-search (§1), splitting a node into the
+ *     complementary subproblems x = lb(x) and x >= lb(x) + 1, first-fail
+ *     variable choice (smallest width, ties to the earliest decision
+ *     variable), and branch-and-bound on the objective for minimisation.
+ *
+ * Error codes: 0 OK; -1 invalid argument; -2 malformed model (index out of
+ * range, duplicate variable in a row, zero coefficient); -3 int32 overflow
+ * risk (sum |a| * max(|lb|,|ub|) + |c| >= 2^31).
+ */
+#ifndef PCCP_ORACLE_H
+#define PCCP_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t nvars;
+    const int32_t *lb0, *ub0;          /* initial box, nvars each            */
+    int32_t nrows;
+    const int32_t *row_ptr;            /* nrows + 1                          */
+    const int32_t *coef, *var;         /* row_ptr[nrows] terms               */
+    const int32_t *rhs;                /* nrows                              */
+    int32_t nreif;
+    const int32_t *reif;               /* 4 per item: b, si, sj, d           */
+    int32_t ndec;
+    const int32_t *dec;                /* decision variables, tie-break order*/
+    int32_t objective;                 /* -1 if none                          */
+} orc_model;
+
+enum { ORC_FIXPOINT = 0, ORC_FAILED = 1 };
+
+/* schedules of the propagation loop (all must reach the same result) */
+enum {
+    ORC_SCHED_GS = 0,       /* model order, tells applied at once           */
+    ORC_SCHED_JACOBI = 1,   /* every tell of a sweep reads the same snapshot */
+    ORC_SCHED_PERM = 2,     /* a fresh random propagator order every sweep  */
+    ORC_SCHED_SELECT = 3,   /* random single guarded commands, fair         */
+    ORC_SCHED_REVERSE = 4   /* reversed model order                         */
+};
+
+enum { ORC_ENUMERATE = 0, ORC_MINIMIZE = 1 };
+enum { ORC_FIRST_FAIL = 0, ORC_INPUT_ORDER = 1 };
+enum {
+    ORC_OUT_ALL = 0,        /* ENUMERATE: search tree exhausted             */
+    ORC_OUT_OPTIMAL = 1,    /* MINIMIZE: best solution proven optimal       */
+    ORC_OUT_UNSAT = 2,      /* MINIMIZE: no solution                        */
+    ORC_OUT_LIMIT = 3       /* node limit reached                           */
+};
+
+typedef struct {
+    int64_t nodes;          /* propagate calls, including failed ones/leaves */
+    int64_t fails;
+    int64_t solutions;
+    int64_t max_depth;
+    int64_t sweeps;         /* sweeps of the propagation loop, summed        */
+    int32_t best;           /* MINIMIZE: best objective (INT32_MAX if none) */
+    int32_t outcome;
+    uint64_t sol_hash;      /* order-independent hash of the solution set   */
+} orc_stats;
+
+int32_t orc_validate(const orc_model *m);
+
+/* Fixed point above (lb, ub), in place.  Returns ORC_FIXPOINT or ORC_FAILED,
+ * or a negative error.  On ORC_FAILED the contents of lb/ub are unspecified. */
+int32_t orc_propagate(const orc_model *m, int32_t *lb, int32_t *ub,
+                      int32_t sched, uint64_t seed, int64_t *sweeps);
+
+/* One parallel (Jacobi) application of every guarded command:
+ * s := s join tells(s).  Returns ORC_FIXPOINT if s is unchanged,
+ * 2 if s changed and is not failed, ORC_FAILED if s became failed. */
+int32_t orc_jacobi_step(const orc_model *m, int32_t *lb, int32_t *ub);
+
+/* One sequential (Gauss-Seidel) pass over every propagator in model order;
+ * same return convention as orc_jacobi_step. */
+int32_t orc_gs_step(const orc_model *m, int32_t *lb, int32_t *ub);
+
+/* Depth-first search.  sol_buf (may be NULL) receives up to sol_cap
+ * solutions of ndec values each, in discovery order; best_assign (may be
+ * NULL) receives the ndec decision values of the best solution. */
+int32_t orc_solve(const orc_model *m, int32_t mode, int32_t branching,
+                  int64_t node_limit, int32_t *sol_buf, int64_t sol_cap,
+                  int32_t *best_assign, orc_stats *st);
+
+/* Hash of one solution (FNV-1a 64 over the little-endian bytes, finalised
+ * by MurmurHash3's fmix64); the solution-set hash is the wrapping sum. */
+uint64_t orc_solution_hash(const int32_t *vals, int32_t n);
+
+/* ---- brute force (independent of the propagation code) ---------------- */
+
+/* All integer points of the initial box satisfying every linear row and
+ * every reified item.  Counts them, hashes their decision-variable values,
+ * and copies up to cap of them (ndec values each) to out. */
+int64_t orc_brute_points(const orc_model *m, int32_t *out, int64_t cap,
+                         uint64_t *hash);
+
+/* Minimum makespan of a raw RCPSP <T, P, R> by enumerating start times in
+ * [0, h - d_i] and checking precedences and the per-instant resource
+ * profile directly.  Returns -1 if no schedule exists.  best_s (may be NULL)
+ * receives one optimal schedule. */
+int32_t orc_brute_rcpsp(int32_t n, const int32_t *dur, int32_t nedges,
+                        const int32_t *edges, int32_t nres, const int32_t *dem,
+                        const int32_t *cap, int32_t h, int32_t *best_s);
+
+/* Check a schedule against the raw RCPSP data, instant by instant.
+ * Returns 1 if feasible, 0 otherwise; *makespan gets max(s_i + d_i). */
+int32_t orc_check_schedule(int32_t n, const int32_t *dur, int32_t nedges,
+                           const int32_t *edges, int32_t nres,
+                           const int32_t *dem, const int32_t *cap,
+                           const int32_t *s, int32_t *makespan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,289 @@
+"""Seeded synthetic instances: the tiny CSP and the RCPSP family.
+
+This module produces *input data only*: variable boxes, linear rows,
+reified-overlap items, the decision-variable list and the objective.  It holds
+none of the solving arithmetic (no propagation, no search); both the HIP
+solver and the CPU oracle consume the `Model` it returns.
+
+Randomness: SplitMix64 (Steele, Lea & Flood, "Fast splittable pseudorandom
+number generators", OOPSLA 2014), uniform integers by rejection sampling so
+that every draw is exactly uniform.
+
+Model encoding of the RCPSP follows the PCCP model of §2 (variables s_i over
+IZ(0,h), the n*n Boolean overlap variables b_ij over IZ(0,1), one precedence
+per edge i << j, one reified overlap per ordered pair (i, j) including i = j,
+one resource row per (resource k, task j)), plus a makespan variable m with
+s_i + d_i <= m for every task (the paper names the objective but gives no
+encoding for it).  The horizon is h = sum of durations, the example the paper
+gives for it.
+
+The paper's datasets (Patterson, PSPLIB j30) are not used; these generators
+stand in for them with j30's shape (30 tasks, 4 renewable resources) and
+larger sizes (60, 90, 120 tasks).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import hashlib
+
+import numpy as np
+
+MASK64 = (1 << 64) - 1
+
+# Configuration ids mixed into the seed so that different workloads never
+# share a random stream.
+CFG_TINY_CSP = 1
+CFG_RCPSP = 2
+CFG_TINY_RCPSP = 3
+CFG_PREC_ONLY = 4
+
+
+class SplitMix64:
+    """SplitMix64 stream (Steele, Lea & Flood 2014)."""
+
+    def __init__(self, seed: int):
+        self.state = seed & MASK64
+
+    def next_u64(self) -> int:
+        self.state = (self.state + 0x9E3779B97F4A7C15) & MASK64
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+        return z ^ (z >> 31)
+
+    def below(self, n: int) -> int:
+        """Uniform integer in [0, n) by rejection sampling."""
+        if n <= 0:
+            raise ValueError("n must be positive")
+        limit = (1 << 64) - ((1 << 64) % n)
+        while True:
+            r = self.next_u64()
+            if r < limit:
+                return r % n
+
+    def uniform(self, lo: int, hi: int) -> int:
+        """Uniform integer in [lo, hi] (inclusive)."""
+        return lo + self.below(hi - lo + 1)
+
+    def shuffle(self, xs: list) -> None:
+        """Fisher-Yates shuffle in place."""
+        for i in range(len(xs) - 1, 0, -1):
+            j = self.below(i + 1)
+            xs[i], xs[j] = xs[j], xs[i]
+
+
+def stream(config_id: int, seed: int) -> SplitMix64:
+    return SplitMix64(((config_id & 0xFFFFFFFF) << 32) ^ (seed & 0xFFFFFFFF))
+
+
+MODE_ENUMERATE = 0
+MODE_MINIMIZE = 1
+
+
+@dataclass
+class Model:
+    """A constraint model over int32 interval variables (lattice IZ, §2).
+
+    lb, ub         int32[V]      initial box of every variable
+    lin_ptr        int32[R+1]    CSR row pointer of the linear rows
+    lin_coef       int32[T]      nonzero coefficients
+    lin_var        int32[T]      variable of each term (distinct within a row)
+    lin_rhs        int32[R]      row r means  sum_t coef_t * x_t <= rhs_r
+    reif           int32[Q, 4]   (b, si, sj, d): b <=> (si <= sj  and  sj < si + d)
+    decision       int32[D]      branching candidates, in tie-break order
+    objective      int           variable to minimise, or -1
+    mode           int           MODE_ENUMERATE or MODE_MINIMIZE
+    meta           dict          generator parameters (durations, demands, ...)
+    """
+
+    lb: np.ndarray
+    ub: np.ndarray
+    lin_ptr: np.ndarray
+    lin_coef: np.ndarray
+    lin_var: np.ndarray
+    lin_rhs: np.ndarray
+    reif: np.ndarray
+    decision: np.ndarray
+    objective: int
+    mode: int
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nvars(self) -> int:
+        return int(self.lb.shape[0])
+
+    @property
+    def nrows(self) -> int:
+        return int(self.lin_rhs.shape[0])
+
+    @property
+    def nterms(self) -> int:
+        return int(self.lin_coef.shape[0])
+
+    @property
+    def nreif(self) -> int:
+        return int(self.reif.shape[0])
+
+    def rows(self):
+        """Yield (coef array, var array, rhs) per linear row."""
+        for r in range(self.nrows):
+            a, b = int(self.lin_ptr[r]), int(self.lin_ptr[r + 1])
+            yield self.lin_coef[a:b], self.lin_var[a:b], int(self.lin_rhs[r])
+
+    def content_hash(self) -> str:
+        h = hashlib.sha256()
+        for arr in (self.lb, self.ub, self.lin_ptr, self.lin_coef, self.lin_var,
+                    self.lin_rhs, self.reif, self.decision):
+            h.update(np.ascontiguousarray(arr, dtype=np.int32).tobytes())
+        h.update(np.int64(self.objective).tobytes())
+        h.update(np.int64(self.mode).tobytes())
+        return h.hexdigest()[:16]
+
+
+class _Builder:
+    def __init__(self):
+        self.lb: list[int] = []
+        self.ub: list[int] = []
+        self.ptr = [0]
+        self.coef: list[int] = []
+        self.var: list[int] = []
+        self.rhs: list[int] = []
+        self.reif: list[tuple[int, int, int, int]] = []
+
+    def add_vars(self, n: int, lo: int, hi: int) -> int:
+        first = len(self.lb)
+        self.lb.extend([lo] * n)
+        self.ub.extend([hi] * n)
+        return first
+
+    def add_row(self, coefs, vars_, rhs: int) -> None:
+        pairs = [(int(a), int(v)) for a, v in zip(coefs, vars_) if int(a) != 0]
+        if not pairs:
+            return  # 0 <= rhs holds for every generated row (rhs >= 0)
+        for a, v in pairs:
+            self.coef.append(a)
+            self.var.append(v)
+        self.rhs.append(int(rhs))
+        self.ptr.append(len(self.coef))
+
+    def add_reif(self, b: int, si: int, sj: int, d: int) -> None:
+        self.reif.append((b, si, sj, d))
+
+    def finish(self, decision, objective, mode, meta) -> Model:
+        i32 = lambda xs: np.asarray(xs, dtype=np.int32)
+        reif = np.asarray(self.reif, dtype=np.int32).reshape(-1, 4)
+        return Model(i32(self.lb), i32(self.ub), i32(self.ptr), i32(self.coef),
+                     i32(self.var), i32(self.rhs), reif, i32(decision),
+                     int(objective), int(mode), meta)
+
+
+def tiny_csp(seed: int, nvars: int = 8, dom: int = 20, nprec: int = 12) -> Model:
+    """Tiny CSP: `nvars` variables over [0, dom], `nprec` random precedences
+    x_u + d <= x_v (d uniform 1..5) along a random topological order (so the
+    precedence graph is a DAG), and one row sum_i a_i x_i <= c with a_i
+    uniform 1..4 and c = 60% of the largest possible sum (exactly
+    0.6 * dom * sum a_i = 12 * sum a_i for dom = 20).  Enumerate all
+    solutions, branching over every variable."""
+    rng = stream(CFG_TINY_CSP, seed)
+    b = _Builder()
+    b.add_vars(nvars, 0, dom)
+    perm = list(range(nvars))
+    rng.shuffle(perm)
+    pairs = [(p, q) for p in range(nvars) for q in range(p + 1, nvars)]
+    rng.shuffle(pairs)
+    precs = []
+    for (p, q) in pairs[:nprec]:
+        u, v = perm[p], perm[q]
+        d = rng.uniform(1, 5)
+        precs.append((u, v, d))
+        b.add_row([1, -1], [u, v], -d)  # x_u - x_v <= -d
+    a = [rng.uniform(1, 4) for _ in range(nvars)]
+    c = (dom * sum(a) * 6) // 10
+    b.add_row(a, list(range(nvars)), c)
+    meta = dict(kind="tiny_csp", seed=seed, precedences=precs, weights=a, cap=c,
+                dom=dom)
+    return b.finish(list(range(nvars)), -1, MODE_ENUMERATE, meta)
+
+
+def rcpsp_data(n: int, seed: int, nres: int = 4, cap: int = 10, dmax: int = 10,
+               config_id: int = CFG_RCPSP):
+    """Raw RCPSP data <T, P, R> (§2): durations, precedence edges, demands,
+    capacities.  Durations uniform 1..dmax; each task i < n-1 gets 1..3
+    distinct successors drawn uniformly from {i+1, ..., n-1} (all of them if
+    fewer remain); each demand r_{k,i} is 0 with probability 1/2, else uniform
+    1..10 (clipped to the capacity)."""
+    rng = stream(config_id, (n << 20) ^ seed)
+    dur = [rng.uniform(1, dmax) for _ in range(n)]
+    edges = []
+    for i in range(n - 1):
+        cands = list(range(i + 1, n))
+        k = rng.uniform(1, 3)
+        if k >= len(cands):
+            succ = cands
+        else:
+            rng.shuffle(cands)
+            succ = sorted(cands[:k])
+        edges.extend((i, j) for j in succ)
+    dem = [[0] * n for _ in range(nres)]
+    for k in range(nres):
+        for i in range(n):
+            if rng.below(2) == 1:
+                dem[k][i] = min(cap, rng.uniform(1, 10))
+    caps = [cap] * nres
+    return dur, edges, dem, caps
+
+
+def rcpsp_model(dur, edges, dem, caps, horizon: int | None = None,
+                with_overlap: bool = True, meta: dict | None = None) -> Model:
+    """The PCCP RCPSP model of §2 with the makespan objective.
+
+    Variable layout: s_i = i (i < n); b_ij = n + i*n + j; m = n + n*n
+    (or m = n when `with_overlap` is False, for precedence-only models)."""
+    n = len(dur)
+    h = sum(dur) if horizon is None else horizon
+    b = _Builder()
+    s0 = b.add_vars(n, 0, h)
+    if with_overlap:
+        b0 = b.add_vars(n * n, 0, 1)
+    m = b.add_vars(1, 0, h)
+    for (i, j) in edges:                       # s_i + d_i <= s_j
+        b.add_row([1, -1], [s0 + i, s0 + j], -dur[i])
+    for i in range(n):                         # s_i + d_i <= m
+        b.add_row([1, -1], [s0 + i, m], -dur[i])
+    if with_overlap:
+        for j in range(n):
+            for i in range(n):                 # b_ij <=> (s_i <= s_j < s_i + d_i)
+                b.add_reif(b0 + i * n + j, s0 + i, s0 + j, dur[i])
+        for k in range(len(caps)):
+            for j in range(n):                 # sum_i r_ki * b_ij <= c_k
+                b.add_row([dem[k][i] for i in range(n)],
+                          [b0 + i * n + j for i in range(n)], caps[k])
+    md = dict(kind="rcpsp", n=n, horizon=h, durations=list(dur), edges=list(edges),
+              demands=[list(r) for r in dem], capacities=list(caps))
+    if meta:
+        md.update(meta)
+    return b.finish([s0 + i for i in range(n)], m, MODE_MINIMIZE, md)
+
+
+def rcpsp(n: int, seed: int) -> Model:
+    """Synthetic project scheduling instance with n tasks and 4 resources."""
+    dur, edges, dem, caps = rcpsp_data(n, seed)
+    return rcpsp_model(dur, edges, dem, caps, meta=dict(seed=seed))
+
+
+def tiny_rcpsp(n: int, seed: int, dmax: int = 3) -> Model:
+    """Tiny RCPSP (n <= 6, short durations) small enough to brute-force."""
+    dur, edges, dem, caps = rcpsp_data(n, seed, dmax=dmax, config_id=CFG_TINY_RCPSP)
+    return rcpsp_model(dur, edges, dem, caps, meta=dict(seed=seed))
+
+
+def precedence_only(n: int, seed: int) -> Model:
+    """Precedences plus makespan only (no resources): its root fixed point has
+    the critical-path closed form."""
+    dur, edges, dem, caps = rcpsp_data(n, seed, config_id=CFG_PREC_ONLY)
+    return rcpsp_model(dur, edges, dem, caps, with_overlap=False, meta=dict(seed=seed))
+
+
+def batch_sizes(seed: int) -> int:
+    """Mixed-size batch: the task count of seed s is (30, 60, 90)[s mod 3]."""
+    return (30, 60, 90)[seed % 3]
