@@ -1,0 +1,258 @@
+/*
+ * libpccp - lock-free parallel constraint propagation and propagate-and-search
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: P. Talbot, F. Pinel, P. Bouvry, "A Variant of Concurrent Constraint
+ * Programming on GPU", AAAI 2022 (arXiv 2207.12116).
+ *
+ * Vocabulary.
+ *   variable   an integer interval (lb, ub) of the lattice IZ = ZInc x ZDec
+ *              (§2); values are int32.  A store is one interval per variable
+ *              (§3: names erased to indices).  A store with lb > ub somewhere
+ *              is the failed store (top).
+ *   propagator the process compiling one constraint (§2, [[.]]).  Two
+ *              constraint forms are supported:
+ *                linear   sum_t a_t x_t <= c       (§2, [[x + y <= c]] and the
+ *                                                   resource sums)
+ *                reified  b <=> (si <= sj and sj < si + d)
+ *                                                  (§2, [[phi <=> psi]] as used
+ *                                                   by the RCPSP model)
+ *   fixed point the least store above a given store at which no propagator
+ *              tightens a bound (§3, Theorem 2); it is unique and does not
+ *              depend on the order in which propagators run (§3, Theorem 6;
+ *              §4, Theorems 8 and 9).
+ *   search     depth-first propagate-and-search (§1) over the decision
+ *              variables: a node's store is propagated; a failed node is
+ *              pruned; a node whose decision variables are all fixed is a
+ *              solution; otherwise it splits into x = lb(x) and x >= lb(x)+1
+ *              on the variable chosen by the branching rule.  Minimisation is
+ *              branch-and-bound: every node joins ub(objective) <= best - 1.
+ *
+ * Conventions.
+ *   - Every function returns int32_t: PCCP_OK (0) or a negative error code.
+ *     Solver outcomes (fixed point / failed, optimal / unsat / limit) are
+ *     returned through out-parameters, not as errors.
+ *   - pccp_last_error() returns a thread-local description of the last
+ *     error of the calling thread.  No C++ exception crosses this interface.
+ *   - Handles are opaque and owned by the library (create / destroy).
+ *     Host arrays passed in are copied during the call; output arrays are
+ *     owned by the caller and sized as documented.  Device pointers passed
+ *     in are owned by the caller; the library never frees them.
+ *   - A solver is bound to the HIP device that is current when it is created
+ *     and to the HIP stream given then (0 = the null stream).  All device
+ *     work is enqueued on that stream; calls that return host data
+ *     synchronise that stream only.
+ *   - Limits: at most 65535 variables per model, and the store (8 bytes per
+ *     variable) must fit in one workgroup's LDS; linear coefficients and
+ *     reified offsets d must fit in int16; every row must satisfy
+ *     sum |a_t| * max(|lb|, |ub|) + |c| < 2^30 so that int32 arithmetic
+ *     cannot overflow.  Violations are reported at solver creation.
+ */
+#ifndef PCCP_H
+#define PCCP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define PCCP_OK 0
+#define PCCP_E_INVALID_ARG (-1)  /* null pointer, negative size, bad enum    */
+#define PCCP_E_MODEL (-2)        /* index out of range, duplicate variable in
+                                    a row, zero coefficient, empty row       */
+#define PCCP_E_OVERFLOW (-3)     /* int32 overflow possible (see Limits)     */
+#define PCCP_E_NOMEM (-4)        /* host or device allocation failed         */
+#define PCCP_E_DEVICE (-5)       /* a HIP call failed (text kept)            */
+#define PCCP_E_LDS_CAPACITY (-6) /* the store does not fit in LDS            */
+#define PCCP_E_STATE (-7)        /* call out of order (e.g. no result yet)   */
+#define PCCP_E_UNSUPPORTED (-8)  /* value outside the packed layouts         */
+#define PCCP_E_DEPTH (-9)        /* a search path exceeded max_depth          */
+
+/* ---- outcomes ---------------------------------------------------------- */
+#define PCCP_FIXPOINT 0          /* propagate: the least fixed point reached */
+#define PCCP_FAILED 1            /* propagate: the fixed point is failed     */
+
+#define PCCP_ENUMERATE 0         /* search mode: all solutions               */
+#define PCCP_MINIMIZE 1          /* search mode: minimise the objective      */
+
+#define PCCP_OUT_ALL 0           /* ENUMERATE finished: every solution found */
+#define PCCP_OUT_OPTIMAL 1       /* MINIMIZE finished: best is optimal       */
+#define PCCP_OUT_UNSAT 2         /* MINIMIZE finished: no solution           */
+#define PCCP_OUT_LIMIT 3         /* node or time limit reached               */
+#define PCCP_OUT_CANCELLED 4     /* the cancel word was set                  */
+
+#define PCCP_BRANCH_FIRST_FAIL 0 /* smallest ub - lb, ties to the earliest
+                                    decision variable                        */
+#define PCCP_BRANCH_INPUT_ORDER 1/* the earliest unfixed decision variable   */
+#define PCCP_BRANCH_MLP 2        /* learned scores (pccp_mlp)                */
+
+typedef struct pccp_model pccp_model;
+typedef struct pccp_solver pccp_solver;
+
+/* ---- model building (host) -------------------------------------------- */
+/* §2 (modelling layer): a model declares interval variables and constraints;
+ * the library compiles each constraint to its propagator. */
+
+/* Create an empty model.  *out receives the handle. */
+int32_t pccp_model_create(pccp_model **out);
+int32_t pccp_model_destroy(pccp_model *m);
+
+/* Append n variables with initial intervals [lb[i], ub[i]] (§2, the tell
+ * x <- (l, u) that initialises a variable).  lb > ub is allowed: the model's
+ * root store is then failed.  *first_id (may be NULL) receives the index of
+ * the first new variable; the others follow consecutively. */
+int32_t pccp_model_add_vars(pccp_model *m, int32_t n, const int32_t *lb, const int32_t *ub,
+                            int32_t *first_id);
+
+/* Append the constraint sum_{t<nterms} coef[t] * x_{var[t]} <= rhs.
+ * §2 compiles x + y <= c to the tells ub(x) <= c - lb(y), ub(y) <= c - lb(x)
+ * and the resource sum to the tells on each b from the other terms; this
+ * generalises both: with m_t the smallest value of a_t x_t over the store
+ * and S = sum_t m_t, each x_t is told a_t x_t <= rhs - (S - m_t), rounded
+ * toward the interval's inside.  Terms must be nonzero and name distinct
+ * variables; nterms >= 1. */
+int32_t pccp_model_add_linear_le(pccp_model *m, int32_t nterms, const int32_t *coef,
+                                 const int32_t *var, int32_t rhs);
+
+/* Append b <=> (si <= sj and sj < si + d), compiled as the four guarded
+ * processes of §2 ([[phi <=> psi]]) with interval entailment; the negation
+ * sj < si or sj >= si + d is propagated when one disjunct is entailed false.
+ * b is read as true when lb(b) >= 1 and false when ub(b) <= 0. */
+int32_t pccp_model_add_reified_overlap(pccp_model *m, int32_t b, int32_t si, int32_t sj,
+                                       int32_t d);
+
+/* Branching candidates, in tie-break order (§1: the search splits on them). */
+int32_t pccp_model_set_decision_vars(pccp_model *m, int32_t n, const int32_t *vars);
+
+/* Variable to minimise (-1 = none).  A solution's value is lb(objective). */
+int32_t pccp_model_set_objective(pccp_model *m, int32_t var);
+
+/* Sizes of a model: any pointer may be NULL. */
+int32_t pccp_model_info(const pccp_model *m, int32_t *nvars, int32_t *nlinear,
+                        int32_t *nterms, int32_t *nreified, int32_t *ndecision);
+
+/* ---- solver ------------------------------------------------------------ */
+/* A zero-initialised pccp_config selects every default. */
+typedef struct {
+    int32_t wg_size;      /* threads per workgroup, multiple of 64, <= 1024;
+                             0 = 256                                          */
+    int32_t num_wgs;      /* workgroups of a search launch; 0 = as many as are
+                             resident at once on the device                   */
+    int32_t desc_lds;     /* propagator tables: 0 = choose, 1 = copy into
+                             LDS, 2 = read from global memory                 */
+    int32_t root_lds;     /* subtree-root store: 0 = choose, 1 = LDS,
+                             2 = global memory                                */
+    int32_t max_depth;    /* decision-stack capacity per workgroup; 0 = 1024  */
+    int32_t queue_cap;    /* subtree queue slots; 0 = 4 x workgroups          */
+    int64_t sol_cap;      /* ENUMERATE: solutions kept (all are counted)      */
+} pccp_config;
+
+/* Validate the model, compile it to packed per-kind propagator tables and
+ * upload them to the current device.  cfg may be NULL (defaults).  stream
+ * is a hipStream_t (may be 0). */
+int32_t pccp_solver_create(const pccp_model *m, const pccp_config *cfg, void *stream,
+                           pccp_solver **out);
+int32_t pccp_solver_destroy(pccp_solver *s);
+
+/* Fixed point (§3, Theorem 2) of the box (lb_in, ub_in) - host arrays of
+ * nvars values, or both NULL for the model's initial box - computed by one
+ * workgroup with every propagator running concurrently (§5, fixed point
+ * loop).  *status receives PCCP_FIXPOINT or PCCP_FAILED.  The store is kept
+ * for pccp_get_domains.  Synchronises the solver's stream. */
+int32_t pccp_propagate(pccp_solver *s, const int32_t *lb_in, const int32_t *ub_in,
+                       int32_t *status);
+
+/* Copy the store of the last pccp_propagate (cap >= nvars). */
+int32_t pccp_get_domains(pccp_solver *s, int32_t *lb, int32_t *ub, int32_t cap);
+
+/* Fixed points of nbox boxes at once, one workgroup per box.  All pointers
+ * are device memory: lb_in/ub_in/lb_out/ub_out are [nbox][nvars] int32
+ * (row-major), status is [nbox] (PCCP_FIXPOINT / PCCP_FAILED), sweeps is
+ * [nbox] (loop iterations, may be NULL).  On a failed box lb_out/ub_out are
+ * unspecified.  Enqueued on the solver's stream; returns without waiting. */
+int32_t pccp_propagate_batch(pccp_solver *s, int32_t nbox, const int32_t *lb_in,
+                             const int32_t *ub_in, int32_t *lb_out, int32_t *ub_out,
+                             int32_t *status, int32_t *sweeps);
+
+typedef struct {
+    int64_t node_limit;           /* 0 = none                                  */
+    double time_limit_s;          /* 0 = none; measured on the device clock    */
+    const volatile int32_t *cancel; /* host word in pinned memory polled by the
+                                     search (nonzero = stop); may be NULL     */
+} pccp_limits;
+
+/* Propagate-and-search on this solver's model (§1, §5): mode is
+ * PCCP_ENUMERATE or PCCP_MINIMIZE.  limits may be NULL.  One persistent
+ * launch: every workgroup takes subtrees from a device queue and explores
+ * them depth first; the subtree closest to a workgroup's root is donated to
+ * the queue while others are idle.  With cfg.num_wgs = 1 the node order is
+ * the sequential depth-first order.  *outcome receives a PCCP_OUT_* value.
+ * Synchronises the solver's stream.  Returns PCCP_E_DEPTH if a path was
+ * deeper than max_depth. */
+int32_t pccp_solve(pccp_solver *s, int32_t mode, const pccp_limits *limits, int32_t *outcome);
+
+/* The same search over n solvers' models in ONE persistent launch (one
+ * shared queue; instances of different sizes).  All solvers must live on
+ * the current device; the launch uses solvers[0]'s stream and cfg (may be
+ * NULL = solvers[0]'s).  outcomes[i] receives solver i's outcome, and each
+ * solver's stats/best/solutions are updated as if it had been solved
+ * alone. */
+int32_t pccp_batch_solve(pccp_solver *const *solvers, int32_t n, int32_t mode,
+                         const pccp_config *cfg, const pccp_limits *limits, int32_t *outcomes);
+
+typedef struct {
+    int64_t nodes;            /* propagate calls of the search (failed ones and
+                                 solutions included)                          */
+    int64_t fails;
+    int64_t solutions;        /* ENUMERATE: solutions; MINIMIZE: improvements */
+    int64_t sweeps;           /* propagation-loop iterations, all nodes       */
+    int64_t donations;        /* subtrees given to the queue                  */
+    int64_t subtrees;         /* subtrees taken from the queue                */
+    int64_t max_depth;
+    int64_t prop_linear2;     /* propagator executions: difference rows       */
+    int64_t prop_reified;     /*                         reified overlaps     */
+    int64_t prop_linear;      /*                         other linear rows    */
+    int64_t prop_terms;       /* terms visited by other linear rows           */
+    uint64_t sol_hash;        /* ENUMERATE: wrapping sum over solutions of
+                                 fmix64(FNV-1a-64(decision values, LE bytes)) */
+    int32_t best;             /* MINIMIZE: best objective (INT32_MAX = none)  */
+    int32_t outcome;          /* PCCP_OUT_*                                   */
+    double kernel_ms;         /* duration of the search kernel (HIP events)   */
+    double ttpo_ms;           /* device clock, search start -> last subtree
+                                 finished; -1 if not finished                 */
+    int32_t grid, block, desc_lds, root_lds;
+    int64_t lds_bytes;
+} pccp_stats;
+
+int32_t pccp_get_stats(const pccp_solver *s, pccp_stats *st);
+
+/* ENUMERATE: number of solutions found (counted even beyond sol_cap). */
+int32_t pccp_get_solution_count(const pccp_solver *s, int64_t *count);
+
+/* ENUMERATE: copy solutions [first, first + count) (ndecision values each,
+ * in the order they were found) into vals.  Only the first sol_cap are
+ * kept. */
+int32_t pccp_get_solutions(pccp_solver *s, int64_t first, int64_t count, int32_t *vals);
+
+/* MINIMIZE: best objective (*obj = INT32_MAX if none) and the decision
+ * values of that solution (cap >= ndecision). */
+int32_t pccp_get_best(pccp_solver *s, int32_t *obj, int32_t *vals, int32_t cap);
+
+/* Branching rule for later searches: PCCP_BRANCH_*.  For PCCP_BRANCH_MLP,
+ * weights is a device pointer to the network (see pccp_mlp_*); NULL falls
+ * back to first-fail. */
+int32_t pccp_set_branching(pccp_solver *s, int32_t kind, const void *weights);
+
+/* Number of workgroups of each configuration that are resident at once
+ * (the default grid of a search launch). */
+int32_t pccp_solver_capacity(const pccp_solver *s, int32_t *wgs_per_cu, int32_t *num_cus);
+
+const char *pccp_last_error(void);
+const char *pccp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,697 @@
+// C-ABI of libpccp: model building and validation, compilation of the model
+// to packed per-kind propagator tables (§2: constraints to propagators; §3:
+// names erased to store indices), device upload, launch configuration and
+// result read-back.  The device work itself is in pccp_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pccp.h"
+#include "pccp_launch.h"
+#include "pccp_types.h"
+
+using namespace pccp;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+static int32_t fail(int32_t code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+#define HIPCHK(call)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(PCCP_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" const char *pccp_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char *pccp_version(void) { return "pccp 0.1 (gfx950)"; }
+
+// ------------------------------------------------------------------ model
+struct pccp_model {
+    std::vector<int32_t> lb, ub;
+    std::vector<int32_t> row_ptr{0}, coef, var, rhs;
+    std::vector<int32_t> reif;  // 4 per item: b, si, sj, d
+    std::vector<int32_t> dec;
+    int32_t objective = -1;
+};
+
+extern "C" int32_t pccp_model_create(pccp_model **out)
+{
+    if (!out) return fail(PCCP_E_INVALID_ARG, "pccp_model_create: out is NULL");
+    *out = new (std::nothrow) pccp_model();
+    return *out ? PCCP_OK : fail(PCCP_E_NOMEM, "pccp_model_create: out of memory");
+}
+
+extern "C" int32_t pccp_model_destroy(pccp_model *m)
+{
+    delete m;
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_model_add_vars(pccp_model *m, int32_t n, const int32_t *lb,
+                                       const int32_t *ub, int32_t *first_id)
+{
+    if (!m || n < 0 || (n > 0 && (!lb || !ub)))
+        return fail(PCCP_E_INVALID_ARG, "pccp_model_add_vars: bad arguments");
+    if ((int64_t)m->lb.size() + n > kMaxVars)
+        return fail(PCCP_E_UNSUPPORTED, "pccp_model_add_vars: more than 65535 variables");
+    if (first_id) *first_id = (int32_t)m->lb.size();
+    m->lb.insert(m->lb.end(), lb, lb + n);
+    m->ub.insert(m->ub.end(), ub, ub + n);
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_model_add_linear_le(pccp_model *m, int32_t nterms, const int32_t *coef,
+                                            const int32_t *var, int32_t rhs)
+{
+    if (!m || nterms < 1 || !coef || !var)
+        return fail(PCCP_E_INVALID_ARG, "pccp_model_add_linear_le: bad arguments");
+    m->coef.insert(m->coef.end(), coef, coef + nterms);
+    m->var.insert(m->var.end(), var, var + nterms);
+    m->rhs.push_back(rhs);
+    m->row_ptr.push_back((int32_t)m->coef.size());
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_model_add_reified_overlap(pccp_model *m, int32_t b, int32_t si,
+                                                  int32_t sj, int32_t d)
+{
+    if (!m) return fail(PCCP_E_INVALID_ARG, "pccp_model_add_reified_overlap: model is NULL");
+    m->reif.insert(m->reif.end(), {b, si, sj, d});
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_model_set_decision_vars(pccp_model *m, int32_t n, const int32_t *vars)
+{
+    if (!m || n < 0 || (n > 0 && !vars))
+        return fail(PCCP_E_INVALID_ARG, "pccp_model_set_decision_vars: bad arguments");
+    m->dec.assign(vars, vars + n);
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_model_set_objective(pccp_model *m, int32_t v)
+{
+    if (!m || v < -1) return fail(PCCP_E_INVALID_ARG, "pccp_model_set_objective: bad arguments");
+    m->objective = v;
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_model_info(const pccp_model *m, int32_t *nvars, int32_t *nlinear,
+                                   int32_t *nterms, int32_t *nreified, int32_t *ndecision)
+{
+    if (!m) return fail(PCCP_E_INVALID_ARG, "pccp_model_info: model is NULL");
+    if (nvars) *nvars = (int32_t)m->lb.size();
+    if (nlinear) *nlinear = (int32_t)m->rhs.size();
+    if (nterms) *nterms = (int32_t)m->coef.size();
+    if (nreified) *nreified = (int32_t)(m->reif.size() / 4);
+    if (ndecision) *ndecision = (int32_t)m->dec.size();
+    return PCCP_OK;
+}
+
+// ------------------------------------------------------------------ compiled model
+// Packed tables (see pccp_types.h): difference rows, reified items, other
+// rows with their terms, decision variables.
+struct Compiled {
+    int32_t nvars = 0, ndec = 0, objective = -1;
+    std::vector<int32_t> lb0, ub0, dec;
+    std::vector<int2> diff, reif;
+    std::vector<int4> rows;
+    std::vector<uint32_t> terms;
+};
+
+static int32_t compile_model(const pccp_model *m, Compiled &c)
+{
+    const int64_t LIM = (int64_t)1 << 30;
+    const int32_t V = (int32_t)m->lb.size();
+    if (V > kMaxVars) return fail(PCCP_E_UNSUPPORTED, "more than 65535 variables");
+    c.nvars = V;
+    c.lb0 = m->lb;
+    c.ub0 = m->ub;
+    int64_t maxabs = 0;
+    std::vector<int64_t> mag(V);
+    for (int32_t v = 0; v < V; ++v) {
+        mag[v] = std::max(std::llabs((int64_t)m->lb[v]), std::llabs((int64_t)m->ub[v]));
+        maxabs = std::max(maxabs, mag[v]);
+    }
+    if (maxabs >= LIM) return fail(PCCP_E_OVERFLOW, "a variable bound is beyond 2^30 in magnitude");
+    if (m->objective < -1 || m->objective >= V)
+        return fail(PCCP_E_MODEL, "objective variable out of range");
+    c.objective = m->objective;
+    for (int32_t x : m->dec)
+        if (x < 0 || x >= V) return fail(PCCP_E_MODEL, "decision variable out of range");
+    c.dec = m->dec;
+    c.ndec = (int32_t)m->dec.size();
+    const int32_t R = (int32_t)m->rhs.size();
+    std::vector<char> seen(V, 0);
+    for (int32_t r = 0; r < R; ++r) {
+        const int32_t a0 = m->row_ptr[r], a1 = m->row_ptr[r + 1];
+        int64_t tot = std::llabs((int64_t)m->rhs[r]);
+        for (int32_t t = a0; t < a1; ++t) {
+            const int32_t x = m->var[t], a = m->coef[t];
+            if (x < 0 || x >= V) return fail(PCCP_E_MODEL, "row " + std::to_string(r) + ": variable out of range");
+            if (a == 0) return fail(PCCP_E_MODEL, "row " + std::to_string(r) + ": zero coefficient");
+            if (seen[x]) return fail(PCCP_E_MODEL, "row " + std::to_string(r) + ": variable repeated");
+            seen[x] = 1;
+            tot += std::llabs((int64_t)a) * mag[x];
+        }
+        for (int32_t t = a0; t < a1; ++t) seen[m->var[t]] = 0;
+        if (tot >= LIM) return fail(PCCP_E_OVERFLOW, "row " + std::to_string(r) + ": sum |a|*|bound| + |c| >= 2^30");
+        const bool is_diff = (a1 - a0 == 2) &&
+                             ((m->coef[a0] == 1 && m->coef[a0 + 1] == -1) ||
+                              (m->coef[a0] == -1 && m->coef[a0 + 1] == 1));
+        if (is_diff) {
+            const int32_t x = m->coef[a0] == 1 ? m->var[a0] : m->var[a0 + 1];
+            const int32_t y = m->coef[a0] == 1 ? m->var[a0 + 1] : m->var[a0];
+            c.diff.push_back(make_int2((int32_t)((uint32_t)x | ((uint32_t)y << 16)), m->rhs[r]));
+        } else {
+            c.rows.push_back(make_int4((int32_t)c.terms.size(), a1 - a0, m->rhs[r], 0));
+            for (int32_t t = a0; t < a1; ++t) {
+                const int32_t a = m->coef[t];
+                if (a < -32768 || a > 32767)
+                    return fail(PCCP_E_UNSUPPORTED, "row " + std::to_string(r) + ": coefficient outside int16");
+                c.terms.push_back((uint32_t)m->var[t] | ((uint32_t)(uint16_t)(int16_t)a << 16));
+            }
+        }
+    }
+    const size_t Q = m->reif.size() / 4;
+    for (size_t q = 0; q < Q; ++q) {
+        const int32_t *it = &m->reif[4 * q];
+        for (int k = 0; k < 3; ++k)
+            if (it[k] < 0 || it[k] >= V)
+                return fail(PCCP_E_MODEL, "reified item " + std::to_string(q) + ": variable out of range");
+        if (it[3] < -32768 || it[3] > 32767)
+            return fail(PCCP_E_UNSUPPORTED, "reified item " + std::to_string(q) + ": d outside int16");
+        if (2 * maxabs + std::llabs((int64_t)it[3]) + 1 >= LIM)
+            return fail(PCCP_E_OVERFLOW, "reified item " + std::to_string(q) + ": bounds + d beyond 2^30");
+        c.reif.push_back(make_int2((int32_t)((uint32_t)it[0] | ((uint32_t)it[1] << 16)),
+                                   (int32_t)((uint32_t)it[2] | ((uint32_t)(uint16_t)(int16_t)it[3] << 16))));
+    }
+    return PCCP_OK;
+}
+
+// ------------------------------------------------------------------ device buffers
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    int32_t ensure(size_t need)
+    {
+        if (need <= bytes) return PCCP_OK;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        hipError_t e = hipMalloc(&p, need);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return fail(PCCP_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        bytes = need;
+        return PCCP_OK;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+// search workspace (grow-only)
+struct Workspace {
+    DevBuf models, inst, globals, qseq, qdata, roots, best;
+    void release()
+    {
+        models.release(); inst.release(); globals.release(); qseq.release();
+        qdata.release(); roots.release(); best.release();
+    }
+};
+
+struct pccp_solver {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    pccp_config cfg{};
+    Compiled c;
+    size_t desc_bytes = 0;
+    DevBuf tables;      // the packed tables
+    DevBuf dmodel;      // DevModel on the device
+    DevModel hmodel{};  // same, host copy (device pointers)
+    DevBuf box;         // pccp_propagate staging
+    std::vector<int32_t> dom_lb, dom_ub;
+    bool have_domains = false;
+    Workspace ws;
+    DevBuf sols;
+    int64_t sol_count = 0;
+    int64_t sol_kept = 0;
+    std::vector<int32_t> best_vals;
+    int32_t best = INT32_MAX;
+    pccp_stats stats{};
+    bool have_stats = false;
+    int branching = PCCP_BRANCH_FIRST_FAIL;
+    const void *mlp = nullptr;
+    int num_cus = 0, wall_khz = 0;
+    size_t lds_max = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+static void fill_defaults(pccp_config &cfg)
+{
+    if (cfg.wg_size <= 0) cfg.wg_size = 256;
+    if (cfg.max_depth <= 0) cfg.max_depth = 1024;
+    if (cfg.sol_cap < 0) cfg.sol_cap = 0;
+}
+
+static int32_t check_cfg(const pccp_config &cfg)
+{
+    if (cfg.wg_size % 64 != 0 || cfg.wg_size > kMaxWg)
+        return fail(PCCP_E_INVALID_ARG, "wg_size must be a multiple of 64 and <= 1024");
+    if (cfg.num_wgs < 0 || cfg.queue_cap < 0 || cfg.desc_lds < 0 || cfg.desc_lds > 2 ||
+        cfg.root_lds < 0 || cfg.root_lds > 2 || cfg.max_depth > (1 << 16))
+        return fail(PCCP_E_INVALID_ARG, "bad config field");
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_solver_create(const pccp_model *m, const pccp_config *cfg, void *stream,
+                                      pccp_solver **out)
+{
+    if (!m || !out) return fail(PCCP_E_INVALID_ARG, "pccp_solver_create: bad arguments");
+    *out = nullptr;
+    pccp_solver *s = new (std::nothrow) pccp_solver();
+    if (!s) return fail(PCCP_E_NOMEM, "pccp_solver_create: out of memory");
+    if (cfg) s->cfg = *cfg;
+    fill_defaults(s->cfg);
+    int32_t rc = check_cfg(s->cfg);
+    if (rc == PCCP_OK) rc = compile_model(m, s->c);
+    if (rc != PCCP_OK) { delete s; return rc; }
+    s->stream = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipGetDevice(&s->device);
+    hipDeviceProp_t prop;
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, s->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&s->wall_khz, hipDeviceAttributeWallClockRate, s->device);
+    if (e != hipSuccess) { delete s; return fail(PCCP_E_DEVICE, std::string("device query: ") + hipGetErrorString(e)); }
+    s->num_cus = prop.multiProcessorCount;
+    s->lds_max = prop.sharedMemPerBlock;
+    const Compiled &c = s->c;
+    s->desc_bytes = model_desc_bytes((int)c.diff.size(), (int)c.reif.size(), (int)c.rows.size(),
+                                     (int)c.terms.size(), c.ndec);
+    if (propagate_lds_bytes(c.nvars, 0, false) > s->lds_max) {
+        delete s;
+        return fail(PCCP_E_LDS_CAPACITY, "the store (8 bytes per variable) does not fit in LDS");
+    }
+    // one blob: lb0, ub0, diff, reif, rows, terms, dec (16-byte aligned pieces)
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t o_lb = 0, o_ub = o_lb + al(4 * (size_t)c.nvars);
+    const size_t o_diff = o_ub + al(4 * (size_t)c.nvars);
+    const size_t o_reif = o_diff + al(8 * c.diff.size());
+    const size_t o_rows = o_reif + al(8 * c.reif.size());
+    const size_t o_terms = o_rows + al(16 * c.rows.size());
+    const size_t o_dec = o_terms + al(4 * c.terms.size());
+    const size_t total = o_dec + al(4 * (size_t)c.ndec) + 256;
+    rc = s->tables.ensure(total);
+    if (rc == PCCP_OK) rc = s->dmodel.ensure(sizeof(DevModel));
+    if (rc != PCCP_OK) { delete s; return rc; }
+    char *base = s->tables.as<char>();
+    std::vector<char> host(total, 0);
+    auto put = [&](size_t off, const void *src, size_t n) { if (n) memcpy(host.data() + off, src, n); };
+    put(o_lb, c.lb0.data(), 4 * (size_t)c.nvars);
+    put(o_ub, c.ub0.data(), 4 * (size_t)c.nvars);
+    put(o_diff, c.diff.data(), 8 * c.diff.size());
+    put(o_reif, c.reif.data(), 8 * c.reif.size());
+    put(o_rows, c.rows.data(), 16 * c.rows.size());
+    put(o_terms, c.terms.data(), 4 * c.terms.size());
+    put(o_dec, c.dec.data(), 4 * (size_t)c.ndec);
+    DevModel &dm = s->hmodel;
+    dm.nvars = c.nvars;
+    dm.ndiff = (int32_t)c.diff.size();
+    dm.nreif = (int32_t)c.reif.size();
+    dm.nrows = (int32_t)c.rows.size();
+    dm.nterms = (int32_t)c.terms.size();
+    dm.ndec = c.ndec;
+    dm.objective = c.objective;
+    dm.lb0 = reinterpret_cast<const int32_t *>(base + o_lb);
+    dm.ub0 = reinterpret_cast<const int32_t *>(base + o_ub);
+    dm.diff = reinterpret_cast<const int2 *>(base + o_diff);
+    dm.reif = reinterpret_cast<const int2 *>(base + o_reif);
+    dm.rows = reinterpret_cast<const int4 *>(base + o_rows);
+    dm.terms = reinterpret_cast<const uint32_t *>(base + o_terms);
+    dm.dec = reinterpret_cast<const int32_t *>(base + o_dec);
+    dm.feat_static = nullptr;
+    e = hipMemcpyAsync(base, host.data(), total, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->dmodel.p, &dm, sizeof(DevModel), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess) e = hipEventCreate(&s->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&s->ev1);
+    if (e != hipSuccess) {
+        pccp_solver_destroy(s);
+        return fail(PCCP_E_DEVICE, std::string("upload: ") + hipGetErrorString(e));
+    }
+    s->best_vals.assign(std::max(c.ndec, 1), 0);
+    *out = s;
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_solver_destroy(pccp_solver *s)
+{
+    if (!s) return PCCP_OK;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(s->device);
+    if (s->stream || true) (void)hipStreamSynchronize(s->stream);
+    s->tables.release();
+    s->dmodel.release();
+    s->box.release();
+    s->ws.release();
+    s->sols.release();
+    if (s->ev0) (void)hipEventDestroy(s->ev0);
+    if (s->ev1) (void)hipEventDestroy(s->ev1);
+    (void)hipSetDevice(prev);
+    delete s;
+    return PCCP_OK;
+}
+
+// ------------------------------------------------------------------ propagate
+static bool choose_prop_desc(const pccp_solver *s)
+{
+    const bool fits = propagate_lds_bytes(s->c.nvars, s->desc_bytes, true) <= s->lds_max;
+    if (s->cfg.desc_lds == 2) return false;
+    return fits;
+}
+
+extern "C" int32_t pccp_propagate_batch(pccp_solver *s, int32_t nbox, const int32_t *lb_in,
+                                        const int32_t *ub_in, int32_t *lb_out, int32_t *ub_out,
+                                        int32_t *status, int32_t *sweeps)
+{
+    if (!s || nbox < 0 || (nbox > 0 && (!lb_in || !ub_in || !lb_out || !ub_out || !status)))
+        return fail(PCCP_E_INVALID_ARG, "pccp_propagate_batch: bad arguments");
+    if (nbox == 0) return PCCP_OK;
+    if (s->cfg.desc_lds == 1 && !choose_prop_desc(s))
+        return fail(PCCP_E_LDS_CAPACITY, "propagator tables do not fit in LDS next to the store");
+    const bool dl = choose_prop_desc(s);
+    const size_t lds = propagate_lds_bytes(s->c.nvars, s->desc_bytes, dl);
+    const int grid = std::min(nbox, std::max(1, s->num_cus * 8));
+    HIPCHK(hipSetDevice(s->device));
+    HIPCHK(launch_propagate_batch(reinterpret_cast<const DevModel *>(s->dmodel.p), nbox, lb_in,
+                                  ub_in, lb_out, ub_out, status, sweeps, grid, s->cfg.wg_size, lds,
+                                  dl, s->stream));
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_propagate(pccp_solver *s, const int32_t *lb_in, const int32_t *ub_in,
+                                  int32_t *status)
+{
+    if (!s || !status || ((lb_in == nullptr) != (ub_in == nullptr)))
+        return fail(PCCP_E_INVALID_ARG, "pccp_propagate: bad arguments");
+    const size_t V = (size_t)s->c.nvars;
+    int32_t rc = s->box.ensure(4 * (4 * V + 8) + 256);
+    if (rc != PCCP_OK) return rc;
+    int32_t *d = s->box.as<int32_t>();
+    int32_t *dlb = d, *dub = d + V, *olb = d + 2 * V, *oub = d + 3 * V, *dst = d + 4 * V;
+    HIPCHK(hipSetDevice(s->device));
+    const int32_t *slb = lb_in ? lb_in : s->c.lb0.data();
+    const int32_t *sub = ub_in ? ub_in : s->c.ub0.data();
+    HIPCHK(hipMemcpyAsync(dlb, slb, 4 * V, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(dub, sub, 4 * V, hipMemcpyHostToDevice, s->stream));
+    rc = pccp_propagate_batch(s, 1, dlb, dub, olb, oub, dst, dst + 1);
+    if (rc != PCCP_OK) return rc;
+    s->dom_lb.resize(V);
+    s->dom_ub.resize(V);
+    int32_t st[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(s->dom_lb.data(), olb, 4 * V, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(s->dom_ub.data(), oub, 4 * V, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(st, dst, 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->have_domains = true;
+    *status = st[0] ? PCCP_FAILED : PCCP_FIXPOINT;
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_get_domains(pccp_solver *s, int32_t *lb, int32_t *ub, int32_t cap)
+{
+    if (!s || !lb || !ub) return fail(PCCP_E_INVALID_ARG, "pccp_get_domains: bad arguments");
+    if (!s->have_domains) return fail(PCCP_E_STATE, "pccp_get_domains: no propagation yet");
+    if (cap < s->c.nvars) return fail(PCCP_E_INVALID_ARG, "pccp_get_domains: cap < nvars");
+    memcpy(lb, s->dom_lb.data(), 4 * (size_t)s->c.nvars);
+    memcpy(ub, s->dom_ub.data(), 4 * (size_t)s->c.nvars);
+    return PCCP_OK;
+}
+
+// ------------------------------------------------------------------ search
+struct LaunchShape {
+    int block = 256, grid = 1, wgs_per_cu = 1;
+    bool desc_lds = false, root_lds = false;
+    size_t lds = 0;
+};
+
+static int32_t choose_shape(pccp_solver *const *sv, int n, const pccp_config &cfg, int max_vars,
+                            size_t max_desc, int num_cus, size_t lds_max, LaunchShape &sh)
+{
+    sh.block = cfg.wg_size;
+    struct Cand { bool d, r; };
+    const Cand cands[4] = {{true, true}, {false, true}, {true, false}, {false, false}};
+    int best_occ = -1;
+    for (const Cand &cd : cands) {
+        if (cfg.desc_lds != 0 && cd.d != (cfg.desc_lds == 1)) continue;
+        if (cfg.root_lds != 0 && cd.r != (cfg.root_lds == 1)) continue;
+        const size_t lds = search_lds_bytes(max_vars, cfg.max_depth, max_desc, cd.d, cd.r);
+        if (lds > lds_max) continue;
+        int occ = 0;
+        hipError_t e = search_occupancy(sh.block, lds, cd.d, cd.r, &occ);
+        if (e != hipSuccess) return fail(PCCP_E_DEVICE, std::string("occupancy: ") + hipGetErrorString(e));
+        if (occ > best_occ) {  // candidates are in order of preference
+            best_occ = occ;
+            sh.desc_lds = cd.d;
+            sh.root_lds = cd.r;
+            sh.lds = lds;
+        }
+    }
+    (void)sv; (void)n;
+    if (best_occ <= 0)
+        return fail(PCCP_E_LDS_CAPACITY, "no store layout fits in LDS with this wg_size/max_depth");
+    sh.wgs_per_cu = best_occ;
+    const int resident = best_occ * num_cus;
+    sh.grid = cfg.num_wgs > 0 ? std::min(cfg.num_wgs, resident) : resident;
+    return PCCP_OK;
+}
+
+static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const pccp_config *cfgp,
+                          const pccp_limits *lim, int32_t *outcomes)
+{
+    if (!sv || n < 1 || !outcomes || (mode != PCCP_ENUMERATE && mode != PCCP_MINIMIZE))
+        return fail(PCCP_E_INVALID_ARG, "search: bad arguments");
+    pccp_solver *s0 = sv[0];
+    if (!s0) return fail(PCCP_E_INVALID_ARG, "search: solver is NULL");
+    pccp_config cfg = cfgp ? *cfgp : s0->cfg;
+    fill_defaults(cfg);
+    int32_t rc = check_cfg(cfg);
+    if (rc != PCCP_OK) return rc;
+    int max_vars = 0, max_ndec = 1;
+    size_t max_desc = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!sv[i]) return fail(PCCP_E_INVALID_ARG, "search: solver is NULL");
+        if (sv[i]->device != s0->device) return fail(PCCP_E_INVALID_ARG, "search: solvers on different devices");
+        if (mode == PCCP_MINIMIZE && sv[i]->c.objective < 0)
+            return fail(PCCP_E_STATE, "search: MINIMIZE without an objective");
+        max_vars = std::max(max_vars, sv[i]->c.nvars);
+        max_ndec = std::max(max_ndec, sv[i]->c.ndec);
+        max_desc = std::max(max_desc, sv[i]->desc_bytes);
+    }
+    HIPCHK(hipSetDevice(s0->device));
+    LaunchShape sh;
+    rc = choose_shape(sv, n, cfg, max_vars, max_desc, s0->num_cus, s0->lds_max, sh);
+    if (rc != PCCP_OK) return rc;
+    const int qcap = cfg.queue_cap > 0 ? std::max(cfg.queue_cap, n) : std::max(4 * sh.grid, n + sh.grid);
+    const int slot_bytes = (int)(((size_t)sizeof(RecHdr) + sizeof(int2) * (size_t)cfg.max_depth + 15) & ~size_t(15));
+    const int Vp = (max_vars + 3) & ~3;
+    Workspace &ws = s0->ws;
+    if ((rc = ws.models.ensure(sizeof(DevModel) * n)) ||
+        (rc = ws.inst.ensure(sizeof(InstState) * n)) ||
+        (rc = ws.globals.ensure(sizeof(SearchGlobals))) ||
+        (rc = ws.qseq.ensure(sizeof(unsigned long long) * qcap)) ||
+        (rc = ws.qdata.ensure((size_t)slot_bytes * qcap)) ||
+        (rc = ws.best.ensure(sizeof(int32_t) * (size_t)n * max_ndec)))
+        return rc;
+    if (!sh.root_lds && (rc = ws.roots.ensure(sizeof(int32_t) * 2 * (size_t)Vp * sh.grid)))
+        return rc;
+    const bool keep_sols = (mode == PCCP_ENUMERATE && n == 1 && cfg.sol_cap > 0);
+    if (keep_sols && (rc = s0->sols.ensure(sizeof(int32_t) * (size_t)cfg.sol_cap * std::max(s0->c.ndec, 1))))
+        return rc;
+    std::vector<DevModel> hm(n);
+    for (int i = 0; i < n; ++i) hm[i] = sv[i]->hmodel;
+    HIPCHK(hipMemcpyAsync(ws.models.p, hm.data(), sizeof(DevModel) * n, hipMemcpyHostToDevice, s0->stream));
+
+    SearchParams P{};
+    P.models = ws.models.as<DevModel>();
+    P.inst = ws.inst.as<InstState>();
+    P.ninst = n;
+    P.mode = mode;
+    P.branching = s0->branching == PCCP_BRANCH_INPUT_ORDER ? 1 : 0;
+    P.max_depth = cfg.max_depth;
+    P.g = ws.globals.as<SearchGlobals>();
+    P.q_seq = ws.qseq.as<unsigned long long>();
+    P.q_data = ws.qdata.as<char>();
+    P.qcap = qcap;
+    P.slot_bytes = slot_bytes;
+    P.root_scratch = sh.root_lds ? nullptr : ws.roots.as<int32_t>();
+    P.max_vars = max_vars;
+    P.donate = sh.grid > 1 ? 1 : 0;
+    P.node_limit = lim ? lim->node_limit : 0;
+    P.t_limit_ticks = (lim && lim->time_limit_s > 0) ? (long long)(lim->time_limit_s * s0->wall_khz * 1000.0) : 0;
+    P.cancel = lim ? lim->cancel : nullptr;
+    P.sol_buf = keep_sols ? s0->sols.as<int32_t>() : nullptr;
+    P.sol_cap = keep_sols ? cfg.sol_cap : 0;
+    P.best_vals = ws.best.as<int32_t>();
+    P.max_ndec = max_ndec;
+    P.mlp = nullptr;
+
+    HIPCHK(hipEventRecord(s0->ev0, s0->stream));
+    HIPCHK(launch_search(P, sh.grid, sh.block, sh.lds, sh.desc_lds, sh.root_lds, s0->stream));
+    HIPCHK(hipEventRecord(s0->ev1, s0->stream));
+    std::vector<InstState> st(n);
+    SearchGlobals g{};
+    std::vector<int32_t> bv((size_t)n * max_ndec);
+    HIPCHK(hipMemcpyAsync(st.data(), P.inst, sizeof(InstState) * n, hipMemcpyDeviceToHost, s0->stream));
+    HIPCHK(hipMemcpyAsync(&g, P.g, sizeof(SearchGlobals), hipMemcpyDeviceToHost, s0->stream));
+    HIPCHK(hipMemcpyAsync(bv.data(), P.best_vals, sizeof(int32_t) * bv.size(), hipMemcpyDeviceToHost, s0->stream));
+    HIPCHK(hipStreamSynchronize(s0->stream));
+    float kms = 0.f;
+    HIPCHK(hipEventElapsedTime(&kms, s0->ev0, s0->ev1));
+
+    bool overflow = false;
+    for (int i = 0; i < n; ++i) {
+        pccp_solver *s = sv[i];
+        const InstState &is = st[i];
+        pccp_stats &o = s->stats;
+        memset(&o, 0, sizeof(o));
+        o.nodes = (int64_t)is.nodes;
+        o.fails = (int64_t)is.fails;
+        o.solutions = (int64_t)is.solutions;
+        o.sweeps = (int64_t)is.sweeps;
+        o.donations = (int64_t)is.donations;
+        o.subtrees = (int64_t)is.pops;
+        o.max_depth = (int64_t)is.max_depth;
+        o.prop_linear2 = o.sweeps * (int64_t)s->c.diff.size();
+        o.prop_reified = o.sweeps * (int64_t)s->c.reif.size();
+        o.prop_linear = o.sweeps * (int64_t)s->c.rows.size();
+        o.prop_terms = o.sweeps * (int64_t)s->c.terms.size();
+        o.sol_hash = is.sol_hash;
+        o.best = is.best;
+        o.kernel_ms = kms;
+        o.grid = sh.grid;
+        o.block = sh.block;
+        o.desc_lds = sh.desc_lds;
+        o.root_lds = sh.root_lds;
+        o.lds_bytes = (int64_t)sh.lds;
+        const bool done = is.outstanding == 0;
+        o.ttpo_ms = done ? (double)(is.t_done - g.t_start) / (double)s->wall_khz : -1.0;
+        if (done)
+            o.outcome = mode == PCCP_ENUMERATE ? PCCP_OUT_ALL
+                        : (is.best == INT32_MAX ? PCCP_OUT_UNSAT : PCCP_OUT_OPTIMAL);
+        else
+            o.outcome = g.abort == 3 ? PCCP_OUT_CANCELLED : PCCP_OUT_LIMIT;
+        if (is.depth_overflow) overflow = true;
+        outcomes[i] = o.outcome;
+        s->best = is.best;
+        for (int q = 0; q < s->c.ndec; ++q) s->best_vals[q] = bv[(size_t)i * max_ndec + q];
+        s->sol_count = mode == PCCP_ENUMERATE ? (int64_t)is.solutions : 0;
+        s->sol_kept = (keep_sols && i == 0) ? std::min<int64_t>(s->sol_count, cfg.sol_cap) : 0;
+        s->have_stats = true;
+    }
+    if (overflow)
+        return fail(PCCP_E_DEPTH, "a search path was deeper than max_depth");
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_solve(pccp_solver *s, int32_t mode, const pccp_limits *limits, int32_t *outcome)
+{
+    if (!s || !outcome) return fail(PCCP_E_INVALID_ARG, "pccp_solve: bad arguments");
+    pccp_solver *sv[1] = {s};
+    return run_search(sv, 1, mode, nullptr, limits, outcome);
+}
+
+extern "C" int32_t pccp_batch_solve(pccp_solver *const *solvers, int32_t n, int32_t mode,
+                                    const pccp_config *cfg, const pccp_limits *limits,
+                                    int32_t *outcomes)
+{
+    return run_search(solvers, n, mode, cfg, limits, outcomes);
+}
+
+extern "C" int32_t pccp_get_stats(const pccp_solver *s, pccp_stats *st)
+{
+    if (!s || !st) return fail(PCCP_E_INVALID_ARG, "pccp_get_stats: bad arguments");
+    if (!s->have_stats) return fail(PCCP_E_STATE, "pccp_get_stats: no search yet");
+    *st = s->stats;
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_get_solution_count(const pccp_solver *s, int64_t *count)
+{
+    if (!s || !count) return fail(PCCP_E_INVALID_ARG, "pccp_get_solution_count: bad arguments");
+    if (!s->have_stats) return fail(PCCP_E_STATE, "pccp_get_solution_count: no search yet");
+    *count = s->sol_count;
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_get_solutions(pccp_solver *s, int64_t first, int64_t count, int32_t *vals)
+{
+    if (!s || first < 0 || count < 0 || (count > 0 && !vals))
+        return fail(PCCP_E_INVALID_ARG, "pccp_get_solutions: bad arguments");
+    if (first + count > s->sol_kept)
+        return fail(PCCP_E_INVALID_ARG, "pccp_get_solutions: range beyond the kept solutions");
+    if (count == 0) return PCCP_OK;
+    const size_t nd = (size_t)std::max(s->c.ndec, 1);
+    HIPCHK(hipSetDevice(s->device));
+    HIPCHK(hipMemcpyAsync(vals, s->sols.as<int32_t>() + (size_t)first * nd, sizeof(int32_t) * nd * count,
+                          hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_get_best(pccp_solver *s, int32_t *obj, int32_t *vals, int32_t cap)
+{
+    if (!s || !obj) return fail(PCCP_E_INVALID_ARG, "pccp_get_best: bad arguments");
+    if (!s->have_stats) return fail(PCCP_E_STATE, "pccp_get_best: no search yet");
+    *obj = s->best;
+    if (vals) {
+        if (cap < s->c.ndec) return fail(PCCP_E_INVALID_ARG, "pccp_get_best: cap < ndecision");
+        memcpy(vals, s->best_vals.data(), sizeof(int32_t) * (size_t)s->c.ndec);
+    }
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_set_branching(pccp_solver *s, int32_t kind, const void *weights)
+{
+    if (!s || kind < PCCP_BRANCH_FIRST_FAIL || kind > PCCP_BRANCH_MLP)
+        return fail(PCCP_E_INVALID_ARG, "pccp_set_branching: bad arguments");
+    s->branching = kind;
+    s->mlp = weights;
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_solver_capacity(const pccp_solver *s, int32_t *wgs_per_cu, int32_t *num_cus)
+{
+    if (!s) return fail(PCCP_E_INVALID_ARG, "pccp_solver_capacity: bad arguments");
+    pccp_config cfg = s->cfg;
+    fill_defaults(cfg);
+    LaunchShape sh;
+    pccp_solver *sv[1] = {const_cast<pccp_solver *>(s)};
+    HIPCHK(hipSetDevice(s->device));
+    int32_t rc = choose_shape(sv, 1, cfg, s->c.nvars, s->desc_bytes, s->num_cus, s->lds_max, sh);
+    if (rc != PCCP_OK) return rc;
+    if (wgs_per_cu) *wgs_per_cu = sh.wgs_per_cu;
+    if (num_cus) *num_cus = s->num_cus;
+    return PCCP_OK;
+}

@@ -1,0 +1,24 @@
+// Host-side launchers of the HIP kernels (internal to libpccp).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "pccp_types.h"
+
+namespace pccp {
+
+size_t model_desc_bytes(int ndiff, int nreif, int nrows, int nterms, int ndec);
+size_t search_lds_bytes(int max_vars, int max_depth, size_t max_desc, bool desc_lds, bool root_lds);
+size_t propagate_lds_bytes(int nvars, size_t desc, bool desc_lds);
+
+hipError_t launch_propagate_batch(const DevModel *m_dev, int nbox, const int32_t *lb_in,
+                                  const int32_t *ub_in, int32_t *lb_out, int32_t *ub_out,
+                                  int32_t *status, int32_t *sweeps, int grid, int block,
+                                  size_t lds, bool desc_lds, hipStream_t stream);
+
+hipError_t launch_search(const SearchParams &P, int grid, int block, size_t lds, bool desc_lds,
+                         bool root_lds, hipStream_t stream);
+
+hipError_t search_occupancy(int block, size_t lds, bool desc_lds, bool root_lds, int *wgs_per_cu);
+
+}  // namespace pccp

@@ -1,0 +1,103 @@
+// Device-side data layout shared by the C-ABI host code and the HIP kernels
+// of libpccp.  Not part of the public interface (include/pccp.h is).
+//
+// One instance = one flattened model (§2: constraints compiled to
+// propagators, names erased to store indices as in §3) uploaded once.  Each
+// propagator kind is a structure-of-arrays table of packed descriptors so
+// that a wavefront reads 64 consecutive descriptors with coalesced loads.
+// Variable indices fit in 16 bits because a store must fit in one
+// workgroup's LDS (8 bytes per variable, 160 KiB per CU).
+#pragma once
+#include <stdint.h>
+
+namespace pccp {
+
+constexpr int kMaxVars = 65535;
+constexpr int kMaxWg = 1024;
+constexpr int kCtlWords = 64;   // LDS control block (int32 words)
+
+// Kind 1 - difference row  x - y <= c  (a linear row with coefficients
+// +1 / -1; every precedence s_i + d_i <= s_j is one).
+//   packed.x = x | (y << 16),  packed.y = c
+// Kind 2 - reified overlap  b <=> (si <= sj  and  sj < si + d).
+//   packed.x = b | (si << 16), packed.y = sj | (d << 16)   (d as int16)
+// Kind 3 - general linear row  sum_t a_t x_t <= rhs.
+//   row = {first term, number of terms, rhs, 0}; term = var | (a << 16)
+//   (a as int16, nonzero)
+struct DevModel {
+    int32_t nvars;
+    int32_t ndiff, nreif, nrows, nterms;
+    int32_t ndec, objective;
+    int32_t pad0;
+    const int32_t *lb0, *ub0;     // initial box
+    const int2 *diff;             // kind 1
+    const int2 *reif;             // kind 2
+    const int4 *rows;             // kind 3 rows
+    const uint32_t *terms;        // kind 3 terms
+    const int32_t *dec;           // decision variables (tie-break order)
+    const float *feat_static;     // learned branching: static features per decision var (may be null)
+};
+
+// Per-instance search results, written by the search kernel.
+struct InstState {
+    unsigned long long nodes, fails, solutions, sweeps;
+    unsigned long long donations, pops, sol_hash, max_depth;
+    long long t_done;           // wall-clock tick when the last subtree finished (0 = not done)
+    int32_t best;               // MINIMIZE: best objective so far (INT32_MAX = none)
+    int32_t outstanding;        // subtrees queued or in progress
+    int32_t best_lock;          // spin lock protecting best_vals
+    int32_t best_owner;         // workgroup that wrote best_vals
+    int32_t depth_overflow;     // a path exceeded the decision-stack capacity
+    int32_t pad[3];
+};
+
+// Queue slot header; a slot is followed by max_depth decisions (int2).
+struct RecHdr {
+    int32_t inst;
+    int32_t len;
+    int32_t pad[2];
+};
+
+// A decision on the search path.  word = var | (side << 16) | (donated << 17);
+// side 0 = left child (ub(var) := val), side 1 = right child (lb(var) := val + 1).
+constexpr uint32_t kSideBit = 1u << 16;
+constexpr uint32_t kDonatedBit = 1u << 17;
+
+struct SearchGlobals {
+    unsigned long long q_head, q_tail;  // Vyukov bounded MPMC queue positions
+    unsigned long long q_pushed;
+    int32_t outstanding;                // all instances
+    int32_t idle;                       // workgroups waiting for work
+    int32_t abort;                      // 1 = node limit, 2 = time limit, 3 = cancelled, 4 = stack overflow
+    int32_t pad;
+    unsigned long long nodes_total;     // flushed periodically, for the node limit
+    long long t_start;                  // wall_clock64() when the search was initialised
+};
+
+struct SearchParams {
+    const DevModel *models;     // [ninst]
+    InstState *inst;            // [ninst]
+    int32_t ninst;
+    int32_t mode;               // 0 enumerate, 1 minimise
+    int32_t branching;          // 0 first-fail, 1 input order, 2 MLP
+    int32_t max_depth;          // decision stack capacity
+    SearchGlobals *g;
+    unsigned long long *q_seq;  // [qcap]
+    char *q_data;               // [qcap * slot_bytes]
+    int32_t qcap;
+    int32_t slot_bytes;
+    int32_t *root_scratch;      // [grid * 2 * max_vars] (global subproblem roots)
+    int32_t max_vars;           // largest instance in the launch
+    int32_t donate;             // allow donation (0 in single-workgroup runs)
+    long long node_limit;       // 0 = none
+    long long t_limit_ticks;    // 0 = none (wall_clock64 ticks)
+    const volatile int32_t *cancel;   // host-visible cancel word (may be null)
+    int32_t *sol_buf;           // ENUMERATE: solutions (ndec values each)
+    long long sol_cap;
+    int32_t *best_vals;         // [ninst * max_ndec]
+    int32_t max_ndec;
+    int32_t pad;
+    const float *mlp;           // learned branching weights (see pccp_mlp.h), may be null
+};
+
+}  // namespace pccp

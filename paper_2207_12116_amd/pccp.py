@@ -1,0 +1,293 @@
+"""ctypes binding of libpccp (include/pccp.h): argument marshalling only.
+
+Every step of propagation and search runs in the library's HIP kernels.  If
+the library is not built, importing the binding raises; there is no
+fallback.  Device memory and streams come from PyTorch: `stream` defaults to
+torch's current stream, and the batch-propagation entry point takes int32
+CUDA tensors.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from .instances import Model, MODE_ENUMERATE, MODE_MINIMIZE
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpccp.so")
+
+OK = 0
+E_INVALID_ARG, E_MODEL, E_OVERFLOW, E_NOMEM, E_DEVICE = -1, -2, -3, -4, -5
+E_LDS_CAPACITY, E_STATE, E_UNSUPPORTED, E_DEPTH = -6, -7, -8, -9
+FIXPOINT, FAILED = 0, 1
+ENUMERATE, MINIMIZE = MODE_ENUMERATE, MODE_MINIMIZE
+OUT_ALL, OUT_OPTIMAL, OUT_UNSAT, OUT_LIMIT, OUT_CANCELLED = 0, 1, 2, 3, 4
+OUTCOME_NAMES = {OUT_ALL: "all", OUT_OPTIMAL: "optimal", OUT_UNSAT: "unsat",
+                 OUT_LIMIT: "limit", OUT_CANCELLED: "cancelled"}
+BRANCH_FIRST_FAIL, BRANCH_INPUT_ORDER, BRANCH_MLP = 0, 1, 2
+
+_P32 = C.POINTER(C.c_int32)
+_I32, _I64, _VP = C.c_int32, C.c_int64, C.c_void_p
+
+
+class Config(C.Structure):
+    """pccp_config; zero fields select the defaults."""
+    _fields_ = [("wg_size", _I32), ("num_wgs", _I32), ("desc_lds", _I32),
+                ("root_lds", _I32), ("max_depth", _I32), ("queue_cap", _I32),
+                ("sol_cap", _I64)]
+
+
+class Limits(C.Structure):
+    _fields_ = [("node_limit", _I64), ("time_limit_s", C.c_double), ("cancel", _VP)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("nodes", _I64), ("fails", _I64), ("solutions", _I64), ("sweeps", _I64),
+                ("donations", _I64), ("subtrees", _I64), ("max_depth", _I64),
+                ("prop_linear2", _I64), ("prop_reified", _I64), ("prop_linear", _I64),
+                ("prop_terms", _I64), ("sol_hash", C.c_uint64), ("best", _I32),
+                ("outcome", _I32), ("kernel_ms", C.c_double), ("ttpo_ms", C.c_double),
+                ("grid", _I32), ("block", _I32), ("desc_lds", _I32), ("root_lds", _I32),
+                ("lds_bytes", _I64)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["best"] = None if d["best"] == 2**31 - 1 else int(d["best"])
+        return d
+
+
+EXPORTS = [
+    "pccp_model_create", "pccp_model_destroy", "pccp_model_add_vars",
+    "pccp_model_add_linear_le", "pccp_model_add_reified_overlap",
+    "pccp_model_set_decision_vars", "pccp_model_set_objective", "pccp_model_info",
+    "pccp_solver_create", "pccp_solver_destroy", "pccp_propagate", "pccp_get_domains",
+    "pccp_propagate_batch", "pccp_solve", "pccp_batch_solve", "pccp_get_stats",
+    "pccp_get_solution_count", "pccp_get_solutions", "pccp_get_best",
+    "pccp_set_branching", "pccp_solver_capacity", "pccp_last_error", "pccp_version",
+]
+
+_lib = None
+
+
+class PccpError(RuntimeError):
+    def __init__(self, code, where):
+        msg = lib().pccp_last_error().decode(errors="replace")
+        super().__init__(f"{where}: error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load libpccp.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libpccp.so is not built ({LIB_PATH}); run "
+                          "`python -m paper_2207_12116_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    sig = {
+        "pccp_model_create": [C.POINTER(_VP)],
+        "pccp_model_destroy": [_VP],
+        "pccp_model_add_vars": [_VP, _I32, _P32, _P32, _P32],
+        "pccp_model_add_linear_le": [_VP, _I32, _P32, _P32, _I32],
+        "pccp_model_add_reified_overlap": [_VP, _I32, _I32, _I32, _I32],
+        "pccp_model_set_decision_vars": [_VP, _I32, _P32],
+        "pccp_model_set_objective": [_VP, _I32],
+        "pccp_model_info": [_VP, _P32, _P32, _P32, _P32, _P32],
+        "pccp_solver_create": [_VP, C.POINTER(Config), _VP, C.POINTER(_VP)],
+        "pccp_solver_destroy": [_VP],
+        "pccp_propagate": [_VP, _P32, _P32, _P32],
+        "pccp_get_domains": [_VP, _P32, _P32, _I32],
+        "pccp_propagate_batch": [_VP, _I32, _VP, _VP, _VP, _VP, _VP, _VP],
+        "pccp_solve": [_VP, _I32, C.POINTER(Limits), _P32],
+        "pccp_batch_solve": [C.POINTER(_VP), _I32, _I32, C.POINTER(Config),
+                             C.POINTER(Limits), _P32],
+        "pccp_get_stats": [_VP, C.POINTER(Stats)],
+        "pccp_get_solution_count": [_VP, C.POINTER(_I64)],
+        "pccp_get_solutions": [_VP, _I64, _I64, _P32],
+        "pccp_get_best": [_VP, _P32, _P32, _I32],
+        "pccp_set_branching": [_VP, _I32, _VP],
+        "pccp_solver_capacity": [_VP, _P32, _P32],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = _I32
+    L.pccp_last_error.argtypes = []
+    L.pccp_last_error.restype = C.c_char_p
+    L.pccp_version.argtypes = []
+    L.pccp_version.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _chk(rc, where):
+    if rc != OK:
+        raise PccpError(rc, where)
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(_P32)
+
+
+def _current_stream():
+    import torch
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+def _limits(node_limit=0, time_limit=0.0, cancel=None):
+    lim = Limits(int(node_limit), float(time_limit), None)
+    if cancel is not None:          # a pinned int32 torch tensor
+        lim.cancel = C.c_void_p(int(cancel.data_ptr()))
+    return lim
+
+
+class ModelHandle:
+    """A pccp_model built from an `instances.Model`."""
+
+    def __init__(self, model: Model):
+        L = lib()
+        h = _VP()
+        _chk(L.pccp_model_create(C.byref(h)), "pccp_model_create")
+        self.h = h
+        lb, ub = _i32(model.lb), _i32(model.ub)
+        _chk(L.pccp_model_add_vars(h, model.nvars, _p(lb), _p(ub), None), "add_vars")
+        ptr, coef, var, rhs = (_i32(model.lin_ptr), _i32(model.lin_coef),
+                               _i32(model.lin_var), _i32(model.lin_rhs))
+        for r in range(model.nrows):
+            a, b = int(ptr[r]), int(ptr[r + 1])
+            cc, vv = coef[a:b], var[a:b]
+            _chk(L.pccp_model_add_linear_le(h, b - a, _p(cc), _p(vv), int(rhs[r])),
+                 "add_linear_le")
+        for b_, si, sj, d in _i32(model.reif).reshape(-1, 4).tolist():
+            _chk(L.pccp_model_add_reified_overlap(h, b_, si, sj, d), "add_reified_overlap")
+        dec = _i32(model.decision)
+        _chk(L.pccp_model_set_decision_vars(h, int(dec.shape[0]), _p(dec)), "set_decision_vars")
+        _chk(L.pccp_model_set_objective(h, int(model.objective)), "set_objective")
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.pccp_model_destroy(self.h)
+            self.h = None
+
+
+class Solver:
+    """A model compiled and uploaded to the current HIP device."""
+
+    def __init__(self, model: Model, config: Config | None = None, stream=None, **cfg):
+        L = lib()
+        self.model = model
+        self.cfg = config if config is not None else Config(**cfg)
+        self._mh = ModelHandle(model)
+        self.stream = _current_stream() if stream is None else int(stream)
+        h = _VP()
+        _chk(L.pccp_solver_create(self._mh.h, C.byref(self.cfg), C.c_void_p(self.stream),
+                                  C.byref(h)), "pccp_solver_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.pccp_solver_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    # ---- propagation
+    def propagate(self, lb=None, ub=None):
+        """Fixed point of a host box (default: the model's initial box).
+        Returns (status, lb, ub)."""
+        L = lib()
+        st = C.c_int32(0)
+        if lb is None:
+            _chk(L.pccp_propagate(self.h, None, None, C.byref(st)), "pccp_propagate")
+        else:
+            lb, ub = _i32(lb), _i32(ub)
+            _chk(L.pccp_propagate(self.h, _p(lb), _p(ub), C.byref(st)), "pccp_propagate")
+        V = self.model.nvars
+        olb = np.zeros(V, dtype=np.int32)
+        oub = np.zeros(V, dtype=np.int32)
+        _chk(L.pccp_get_domains(self.h, _p(olb), _p(oub), V), "pccp_get_domains")
+        return int(st.value), olb, oub
+
+    def propagate_batch(self, lb_in, ub_in, lb_out, ub_out, status, sweeps=None):
+        """Fixed points of many boxes; int32 CUDA tensors of shape [nbox, nvars]
+        (status, sweeps: [nbox]).  Enqueued on the solver's stream."""
+        nbox = int(lb_in.shape[0])
+        for t in (lb_in, ub_in, lb_out, ub_out):
+            assert t.is_cuda and t.is_contiguous() and t.shape == (nbox, self.model.nvars)
+        assert status.is_cuda and status.numel() >= nbox
+        _chk(lib().pccp_propagate_batch(
+            self.h, nbox, C.c_void_p(lb_in.data_ptr()), C.c_void_p(ub_in.data_ptr()),
+            C.c_void_p(lb_out.data_ptr()), C.c_void_p(ub_out.data_ptr()),
+            C.c_void_p(status.data_ptr()),
+            C.c_void_p(sweeps.data_ptr()) if sweeps is not None else None),
+            "pccp_propagate_batch")
+
+    # ---- search
+    def solve(self, mode=None, node_limit=0, time_limit=0.0, cancel=None):
+        mode = self.model.mode if mode is None else mode
+        out = C.c_int32(0)
+        lim = _limits(node_limit, time_limit, cancel)
+        _chk(lib().pccp_solve(self.h, int(mode), C.byref(lim), C.byref(out)), "pccp_solve")
+        return int(out.value)
+
+    def stats(self) -> dict:
+        st = Stats()
+        _chk(lib().pccp_get_stats(self.h, C.byref(st)), "pccp_get_stats")
+        return st.as_dict()
+
+    def solution_count(self) -> int:
+        n = C.c_int64(0)
+        _chk(lib().pccp_get_solution_count(self.h, C.byref(n)), "pccp_get_solution_count")
+        return int(n.value)
+
+    def solutions(self, count=None) -> np.ndarray:
+        nd = int(self.model.decision.shape[0])
+        n = min(self.solution_count(), int(self.cfg.sol_cap)) if count is None else count
+        out = np.zeros((max(n, 1), max(nd, 1)), dtype=np.int32)
+        if n > 0:
+            _chk(lib().pccp_get_solutions(self.h, 0, n, _p(out)), "pccp_get_solutions")
+        return out[:n, :nd]
+
+    def best(self):
+        nd = int(self.model.decision.shape[0])
+        obj = C.c_int32(0)
+        vals = np.zeros(max(nd, 1), dtype=np.int32)
+        _chk(lib().pccp_get_best(self.h, C.byref(obj), _p(vals), max(nd, 1)), "pccp_get_best")
+        if obj.value == 2**31 - 1:
+            return None, None
+        return int(obj.value), vals[:nd]
+
+    def set_branching(self, kind, weights_ptr=None):
+        _chk(lib().pccp_set_branching(self.h, int(kind),
+                                      C.c_void_p(weights_ptr) if weights_ptr else None),
+             "pccp_set_branching")
+
+    def capacity(self):
+        a, b = C.c_int32(0), C.c_int32(0)
+        _chk(lib().pccp_solver_capacity(self.h, C.byref(a), C.byref(b)), "pccp_solver_capacity")
+        return int(a.value), int(b.value)
+
+
+def batch_solve(solvers, mode=MINIMIZE, config: Config | None = None, node_limit=0,
+                time_limit=0.0, cancel=None):
+    """One persistent launch over every solver's model; returns outcomes."""
+    n = len(solvers)
+    arr = (_VP * n)(*[s.h for s in solvers])
+    outs = np.zeros(n, dtype=np.int32)
+    lim = _limits(node_limit, time_limit, cancel)
+    cfg_p = C.byref(config) if config is not None else None
+    _chk(lib().pccp_batch_solve(arr, n, int(mode), cfg_p, C.byref(lim), _p(outs)),
+         "pccp_batch_solve")
+    return outs.tolist()
+
+
+def version() -> str:
+    return lib().pccp_version().decode()

@@ -22,3 +22,20 @@ def make_model(boxes, rows=(), reif=(), decision=None, objective=-1, mode=None):
     i32 = lambda v: np.asarray(v, dtype=np.int32)
     return Model(lb, ub, i32(ptr), i32(coef), i32(var), i32(rhs), reif,
                  i32(decision), int(objective), int(mode), {})
+
+
+def random_subbox(model, rng, frac=0.3, tight=0.5):
+    """Shrink a random subset of the variables' initial intervals (data only)."""
+    lb, ub = model.lb.copy(), model.ub.copy()
+    for v in range(model.nvars):
+        if rng.random() < frac and lb[v] < ub[v]:
+            a = rng.randint(int(lb[v]), int(ub[v]))
+            b = rng.randint(int(lb[v]), int(ub[v]))
+            a, b = min(a, b), max(a, b)
+            if rng.random() < tight:
+                lb[v], ub[v] = a, b
+            elif rng.random() < 0.5:
+                lb[v] = a
+            else:
+                ub[v] = b
+    return lb, ub

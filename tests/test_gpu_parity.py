@@ -1,0 +1,278 @@
+"""HIP solver against the CPU oracle, element by element, through the C-ABI.
+
+  - fixed points (root and random sub-boxes) bit-exact on the tiny CSP and
+    the RCPSP family at 30, 60, 90 and 120 tasks, under several workgroup
+    sizes and both descriptor placements (the order-independence of the
+    fixed point, §3 Theorem 6 and §4 Theorems 8-9, is what makes a
+    concurrent GPU schedule comparable element by element);
+  - single-workgroup search: (nodes, fails, solutions, best) identical to the
+    oracle's depth-first search;
+  - multi-workgroup search: ENUMERATE solution set and node count identical,
+    MINIMIZE optimum identical (the tree of ENUMERATE is fixed; the node
+    count of a parallel MINIMIZE depends on when bounds arrive);
+  - failure cases forced from the host: empty boxes, cycles, bounds below the
+    optimum, node limits, a too-small decision stack.
+"""
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2207_12116_amd import instances as I
+from tests.models import make_model, random_subbox
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2207_12116_amd import pccp
+    pccp.lib()
+    return pccp
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _check_fixpoint(gst, glb, gub, ref, tag):
+    st, lb, ub, _ = ref
+    assert gst == st, (tag, gst, st)
+    if st == O.FIXPOINT:
+        assert np.array_equal(glb, lb), tag
+        assert np.array_equal(gub, ub), tag
+
+
+FIX_MODELS = [("csp0", lambda: I.tiny_csp(0)), ("csp7", lambda: I.tiny_csp(7)),
+              ("rcpsp6", lambda: I.tiny_rcpsp(6, 3)),
+              ("rcpsp30", lambda: I.rcpsp(30, 0)), ("rcpsp60", lambda: I.rcpsp(60, 1)),
+              ("rcpsp90", lambda: I.rcpsp(90, 2)), ("rcpsp120", lambda: I.rcpsp(120, 0))]
+
+
+@pytest.mark.parametrize("name,mk", FIX_MODELS, ids=[m[0] for m in FIX_MODELS])
+def test_root_fixpoint(P, name, mk):
+    model = mk()
+    say("root fixpoint", name, model.nvars)
+    s = P.Solver(model)
+    st, lb, ub = s.propagate()
+    _check_fixpoint(st, lb, ub, O.propagate(model), name)
+
+
+@pytest.mark.parametrize("name,mk", FIX_MODELS, ids=[m[0] for m in FIX_MODELS])
+@pytest.mark.parametrize("wg,desc", [(64, 1), (256, 1), (256, 2), (1024, 1), (512, 2)])
+def test_subbox_fixpoints_batch(P, name, mk, wg, desc):
+    import torch
+    model = mk()
+    nbox = 300 if model.nvars < 5000 else 60
+    rng = random.Random(1000 + wg + desc)
+    boxes = [random_subbox(model, rng, frac=0.2) for _ in range(nbox)]
+    # a few boxes around a deep node of the oracle's search: fix a prefix of
+    # the decision variables to their root-fixpoint lower bounds
+    st0, rlb, rub, _ = O.propagate(model)
+    for k in range(1, min(8, len(model.decision)) + 1):
+        lb = rlb.copy(); ub = rub.copy()
+        for v in model.decision[:k]:
+            ub[v] = lb[v]
+        boxes.append((lb, ub))
+    lbs = torch.tensor(np.stack([b[0] for b in boxes]), dtype=torch.int32, device="cuda")
+    ubs = torch.tensor(np.stack([b[1] for b in boxes]), dtype=torch.int32, device="cuda")
+    olb, oub = torch.empty_like(lbs), torch.empty_like(ubs)
+    stt = torch.zeros(len(boxes), dtype=torch.int32, device="cuda")
+    sw = torch.zeros(len(boxes), dtype=torch.int32, device="cuda")
+    say("subbox batch", name, wg, desc, len(boxes))
+    s = P.Solver(model, wg_size=wg, desc_lds=desc)
+    if desc == 1 and model.nvars > 5000:
+        # the tables of the 90- and 120-task models do not fit in LDS next
+        # to the store: forcing them there is refused, the default falls back
+        with pytest.raises(P.PccpError) as e:
+            s.propagate_batch(lbs, ubs, olb, oub, stt, sw)
+        assert e.value.code == P.E_LDS_CAPACITY
+        s = P.Solver(model, wg_size=wg)
+    s.propagate_batch(lbs, ubs, olb, oub, stt, sw)
+    torch.cuda.synchronize()
+    glb, gub, gst = olb.cpu().numpy(), oub.cpu().numpy(), stt.cpu().numpy()
+    om = O.OracleModel(model)
+    nfail = 0
+    for k, (lb0, ub0) in enumerate(boxes):
+        ref = O.propagate(om, lb0, ub0)
+        nfail += ref[0] == O.FAILED
+        _check_fixpoint(int(gst[k]), glb[k], gub[k], ref, (name, k))
+    assert (sw.cpu().numpy() >= 1).all()
+
+
+def test_repeat_determinism(P):
+    """The same boxes propagated 20 times give the same stores every time."""
+    import torch
+    model = I.rcpsp(30, 5)
+    rng = random.Random(5)
+    boxes = [random_subbox(model, rng, frac=0.3) for _ in range(256)]
+    lbs = torch.tensor(np.stack([b[0] for b in boxes]), dtype=torch.int32, device="cuda")
+    ubs = torch.tensor(np.stack([b[1] for b in boxes]), dtype=torch.int32, device="cuda")
+    s = P.Solver(model)
+    first = None
+    for rep in range(20):
+        olb, oub = torch.empty_like(lbs), torch.empty_like(ubs)
+        stt = torch.zeros(len(boxes), dtype=torch.int32, device="cuda")
+        s.propagate_batch(lbs, ubs, olb, oub, stt)
+        torch.cuda.synchronize()
+        got = (stt.cpu().numpy(), olb.cpu().numpy(), oub.cpu().numpy())
+        ok = got[0] == 0
+        if first is None:
+            first = got
+        else:
+            assert np.array_equal(got[0], first[0])
+            assert np.array_equal(got[1][ok], first[1][ok]) and np.array_equal(got[2][ok], first[2][ok])
+
+
+def test_failures_and_edge_models(P):
+    hand = [
+        (make_model([(0, 1000), (0, 1000)], [([1, -1], [0, 1], -1), ([-1, 1], [0, 1], -1)]), O.FAILED),
+        (make_model([(3, 2), (0, 5)], [([1, 1], [0, 1], 10)]), O.FAILED),
+        (make_model([(1, 1), (0, 50), (0, 50)], [([1, -1], [2, 1], -1)], [(0, 1, 2, 3)]), O.FAILED),
+        (make_model([(0, 4), (2, 9)], []), O.FIXPOINT),
+        (make_model([(-5, 5), (-5, 5)], [([-2, 3], [0, 1], -4)]), O.FIXPOINT),
+        (make_model([(0, 10)] * 4, [([3, -2, 5, 7], [0, 1, 2, 3], 11), ([-1, -1], [0, 3], -9)]), O.FIXPOINT),
+    ]
+    for model, expect in hand:
+        s = P.Solver(model)
+        st, lb, ub = s.propagate()
+        ref = O.propagate(model)
+        assert ref[0] == expect
+        _check_fixpoint(st, lb, ub, ref, "edge")
+
+
+def test_bad_model_rejected(P):
+    with pytest.raises(P.PccpError) as e:
+        P.Solver(make_model([(0, 1), (0, 1)], [([1, 1], [0, 0], 1)]))
+    assert e.value.code == P.E_MODEL
+    with pytest.raises(P.PccpError) as e:
+        P.Solver(make_model([(0, 2**29)], [([4], [0], 0)]))
+    assert e.value.code == P.E_OVERFLOW
+
+
+# ------------------------------------------------------------------ search
+def _oracle_counts(r):
+    return (r["nodes"], r["fails"], r["solutions"], r["best"])
+
+
+def _gpu_counts(s):
+    st = s.stats()
+    return (st["nodes"], st["fails"], st["solutions"], st["best"])
+
+
+@pytest.mark.parametrize("seed,dom", [(0, 10), (1, 12), (3, 11), (6, 9)])
+def test_single_wg_enumerate(P, seed, dom):
+    model = I.tiny_csp(seed, dom=dom)
+    ref = O.solve(model, sol_cap=10**6)
+    say("enumerate 1wg", seed, dom, ref["solutions"])
+    s = P.Solver(model, num_wgs=1, sol_cap=10**6)
+    out = s.solve(time_limit=60)
+    assert out == P.OUT_ALL
+    assert _gpu_counts(s) == _oracle_counts(ref)
+    st = s.stats()
+    assert st["sol_hash"] == ref["sol_hash"]
+    sols = s.solutions()
+    assert np.array_equal(sols, ref["solutions_list"])   # same order: sequential DFS
+
+
+@pytest.mark.parametrize("n,seed", [(4, 0), (5, 1), (6, 2), (6, 3), (8, 4), (10, 5)])
+def test_single_wg_minimize(P, n, seed):
+    model = I.tiny_rcpsp(n, seed)
+    ref = O.solve(model)
+    say("minimize 1wg", n, seed, ref["nodes"])
+    s = P.Solver(model, num_wgs=1)
+    out = s.solve(time_limit=60)
+    assert out == P.OUT_OPTIMAL
+    assert _gpu_counts(s) == _oracle_counts(ref)
+    obj, vals = s.best()
+    ok, ms = O.check_schedule(model.meta, vals)
+    assert ok and ms == obj == ref["best"]
+
+
+@pytest.mark.parametrize("n,seed,limit", [(30, 0, 3000), (30, 4, 2000), (60, 1, 800)])
+def test_single_wg_node_limited_prefix(P, n, seed, limit):
+    """Both searches stop after exactly `limit` nodes of the same depth-first
+    order, so every counter and the incumbent agree."""
+    model = I.rcpsp(n, seed)
+    ref = O.solve(model, node_limit=limit)
+    say("prefix 1wg", n, seed, limit)
+    s = P.Solver(model, num_wgs=1)
+    out = s.solve(node_limit=limit, time_limit=60)
+    assert out == P.OUT_LIMIT and ref["outcome"] == O.OUT_LIMIT
+    assert _gpu_counts(s) == _oracle_counts(ref)
+    assert s.stats()["max_depth"] == ref["max_depth"]
+
+
+@pytest.mark.parametrize("seed", [0, 2])
+def test_multi_wg_enumerate_full_size(P, seed):
+    """Tiny CSP at its stated size (8 variables over [0, 20]): the solution
+    count, set hash and node count of the whole tree are schedule-free."""
+    model = I.tiny_csp(seed)
+    ref = O.solve(model)
+    say("enumerate multi", seed, ref["solutions"])
+    s = P.Solver(model)
+    out = s.solve(time_limit=120)
+    assert out == P.OUT_ALL
+    st = s.stats()
+    assert (st["nodes"], st["fails"], st["solutions"], st["sol_hash"]) == \
+        (ref["nodes"], ref["fails"], ref["solutions"], ref["sol_hash"])
+    assert st["grid"] > 1
+
+
+@pytest.mark.parametrize("n,seed", [(8, 0), (10, 1), (10, 2), (12, 3)])
+def test_multi_wg_minimize(P, n, seed):
+    model = I.tiny_rcpsp(n, seed)
+    ref = O.solve(model)
+    say("minimize multi", n, seed)
+    s = P.Solver(model)
+    out = s.solve(time_limit=60)
+    assert out == P.OUT_OPTIMAL
+    obj, vals = s.best()
+    assert obj == ref["best"]
+    ok, ms = O.check_schedule(model.meta, vals)
+    assert ok and ms == obj
+
+
+def test_batch_solve_matches_oracle(P):
+    models = [I.tiny_rcpsp(n, s) for n, s in [(6, 0), (8, 1), (10, 2), (5, 3), (9, 4), (7, 5)]]
+    refs = [O.solve(m) for m in models]
+    solvers = [P.Solver(m) for m in models]
+    say("batch minimize", len(models))
+    outs = P.batch_solve(solvers, P.MINIMIZE, time_limit=60)
+    assert outs == [P.OUT_OPTIMAL] * len(models)
+    for s, r in zip(solvers, refs):
+        assert s.best()[0] == r["best"]
+    # enumerate in one launch too
+    cs = [I.tiny_csp(k, dom=10) for k in range(4)]
+    crefs = [O.solve(m) for m in cs]
+    csol = [P.Solver(m) for m in cs]
+    outs = P.batch_solve(csol, P.ENUMERATE, time_limit=60)
+    assert outs == [P.OUT_ALL] * 4
+    for s, r in zip(csol, crefs):
+        st = s.stats()
+        assert (st["nodes"], st["solutions"], st["sol_hash"]) == (r["nodes"], r["solutions"], r["sol_hash"])
+
+
+def test_search_limits_and_errors(P):
+    model = I.tiny_rcpsp(6, 1)
+    opt = O.solve(model)["best"]
+    m2 = I.tiny_rcpsp(6, 1)
+    m2.ub = m2.ub.copy()
+    m2.ub[m2.objective] = opt - 1
+    s = P.Solver(m2)
+    assert s.solve(time_limit=60) == P.OUT_UNSAT
+    assert s.best() == (None, None)
+    big = I.rcpsp(30, 0)
+    s = P.Solver(big, num_wgs=1)
+    assert s.solve(node_limit=100, time_limit=60) == P.OUT_LIMIT
+    assert s.stats()["nodes"] == 100
+    s = P.Solver(big)
+    assert s.solve(time_limit=0.5) == P.OUT_LIMIT
+    s = P.Solver(big, num_wgs=1, max_depth=4)
+    with pytest.raises(P.PccpError) as e:
+        s.solve(time_limit=60)
+    assert e.value.code == P.E_DEPTH

@@ -14,27 +14,11 @@ import pytest
 
 import oracle as O
 from paper_2207_12116_amd import instances as I
+from tests.models import random_subbox
 
 SCHEDS = [(O.SCHED_GS, 0), (O.SCHED_JACOBI, 0), (O.SCHED_REVERSE, 0),
           (O.SCHED_PERM, 1), (O.SCHED_PERM, 2), (O.SCHED_PERM, 3),
           (O.SCHED_SELECT, 4), (O.SCHED_SELECT, 5)]
-
-
-def random_subbox(model, rng, frac=0.3, tight=0.5):
-    """Shrink a random subset of the variables' initial intervals."""
-    lb, ub = model.lb.copy(), model.ub.copy()
-    for v in range(model.nvars):
-        if rng.random() < frac and lb[v] < ub[v]:
-            a = rng.randint(int(lb[v]), int(ub[v]))
-            b = rng.randint(int(lb[v]), int(ub[v]))
-            a, b = min(a, b), max(a, b)
-            if rng.random() < tight:
-                lb[v], ub[v] = a, b
-            elif rng.random() < 0.5:
-                lb[v] = a
-            else:
-                ub[v] = b
-    return lb, ub
 
 
 def leq(lb1, ub1, lb2, ub2):
