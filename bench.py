@@ -75,6 +75,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-nodes", type=int, default=150000)
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -92,8 +93,16 @@ def main():
     seeds = list(range(args.batch))
     log(f"building {args.batch} instances of {args.n} tasks")
     models = [I.rcpsp(args.n, s) for s in seeds]
-    cfg = pccp.Config(wg_size=args.wg)
-    solvers = [pccp.Solver(m, config=pccp.Config(wg_size=args.wg)) for m in models]
+    tuned = None
+    if args.wg == 0 and not args.no_autotune:
+        from paper_2207_12116_amd import autotune
+        cfg, rep = autotune.tune(models, pccp.MINIMIZE, budget_s=0.4, cache_path=None, log=log)
+        tuned = {"wg_size": cfg.wg_size, "desc_lds": cfg.desc_lds, "root_lds": cfg.root_lds,
+                 "candidates": len(rep["candidates"])}
+        log(f"autotuned: {tuned}")
+    else:
+        cfg = pccp.Config(wg_size=args.wg)
+    solvers = [pccp.Solver(m, config=cfg) for m in models]
 
     def step():
         outs = pccp.batch_solve(solvers, pccp.MINIMIZE, config=cfg, time_limit=args.step_time)
@@ -138,7 +147,7 @@ def main():
 
     plain = None
     if not args.no_plain:
-        s = pccp.Solver(models[0], config=pccp.Config(wg_size=args.wg))
+        s = pccp.Solver(models[0], config=cfg)
         tp = time.perf_counter()
         out = s.solve(pccp.MINIMIZE, time_limit=args.step_time)
         dtp = time.perf_counter() - tp
@@ -165,7 +174,8 @@ def main():
                    "form": "batched", "branching": "first-fail",
                    "step_time_limit_s": args.step_time,
                    "grid": sts[0]["grid"], "block": sts[0]["block"],
-                   "desc_lds": sts[0]["desc_lds"], "root_lds": sts[0]["root_lds"]},
+                   "desc_lds": sts[0]["desc_lds"], "root_lds": sts[0]["root_lds"],
+                   "autotuned": tuned, "launch": "hipGraph"},
         "propagations_per_s": round(tot_props / wall, 1),
         "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "ttpo": ttpo,
     }

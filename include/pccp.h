@@ -86,7 +86,7 @@ extern "C" {
 #define PCCP_BRANCH_FIRST_FAIL 0 /* smallest ub - lb, ties to the earliest
                                     decision variable                        */
 #define PCCP_BRANCH_INPUT_ORDER 1/* the earliest unfixed decision variable   */
-#define PCCP_BRANCH_MLP 2        /* learned scores (pccp_mlp)                */
+#define PCCP_BRANCH_MLP 2        /* learned scores (pccp_mlp_*)              */
 
 typedef struct pccp_model pccp_model;
 typedef struct pccp_solver pccp_solver;
@@ -147,6 +147,10 @@ typedef struct {
     int32_t max_depth;    /* decision-stack capacity per workgroup; 0 = 1024  */
     int32_t queue_cap;    /* subtree queue slots; 0 = 4 x workgroups          */
     int64_t sol_cap;      /* ENUMERATE: solutions kept (all are counted)      */
+    int32_t launch;       /* 0 = one hipGraph (initialisation + search
+                             kernels, re-used while the launch parameters are
+                             unchanged), 1 = two plain kernel launches        */
+    int32_t reserved;
 } pccp_config;
 
 /* Validate the model, compile it to packed per-kind propagator tables and
@@ -175,6 +179,22 @@ int32_t pccp_get_domains(pccp_solver *s, int32_t *lb, int32_t *ub, int32_t cap);
 int32_t pccp_propagate_batch(pccp_solver *s, int32_t nbox, const int32_t *lb_in,
                              const int32_t *ub_in, int32_t *lb_out, int32_t *ub_out,
                              int32_t *status, int32_t *sweeps);
+
+/* Branching features (6 floats per decision variable, in decision-list
+ * order) of nbox stores; all pointers are device memory: lb/ub are
+ * [nbox][nvars] int32, feat is [nbox][ndecision][6] float.  For decision
+ * variable x with initial interval [lo, hi], H = max(1, hi - lo):
+ *   f0 = (lb(x) - lo)/H, f1 = (ub(x) - lo)/H, f2 = (ub(x) - lb(x))/H,
+ *   f3 = (rows + reified items containing x) / the largest such count,
+ *   f4 = min(1, min over rows x - y <= c of (c + ub(y) - lb(x))/H),
+ *   f5 = mean over reified items with si = x of d * w(b) / H (w(b) = sum of
+ *        a/c over rows a*b + ... <= c with a, c > 0) plus the fraction of
+ *        those items with lb(b) >= 1.
+ * These are the inputs of the learned branching rule (the paper leaves the
+ * search strategy open, §5 Evaluation).  Decision variables must be
+ * distinct.  Enqueued on the solver's stream. */
+int32_t pccp_node_features(pccp_solver *s, int32_t nbox, const int32_t *lb, const int32_t *ub,
+                           float *feat);
 
 typedef struct {
     int64_t node_limit;           /* 0 = none                                  */
@@ -241,13 +261,59 @@ int32_t pccp_get_solutions(pccp_solver *s, int64_t first, int64_t count, int32_t
 int32_t pccp_get_best(pccp_solver *s, int32_t *obj, int32_t *vals, int32_t cap);
 
 /* Branching rule for later searches: PCCP_BRANCH_*.  For PCCP_BRANCH_MLP,
- * weights is a device pointer to the network (see pccp_mlp_*); NULL falls
- * back to first-fail. */
+ * weights is the device pointer given by pccp_mlp_weights (the network must
+ * outlive the searches that use it); NULL falls back to first-fail. */
 int32_t pccp_set_branching(pccp_solver *s, int32_t kind, const void *weights);
 
 /* Number of workgroups of each configuration that are resident at once
  * (the default grid of a search launch). */
 int32_t pccp_solver_capacity(const pccp_solver *s, int32_t *wgs_per_cu, int32_t *num_cus);
+
+/* ---- learned branching: network and training --------------------------
+ * The rule scores each unfixed decision variable from its 6 features
+ * (pccp_node_features) with a 2-layer network: s = w2 . max(0, W1 x + b1)
+ * + b2, 64 hidden units; the search branches on the largest score (ties to
+ * the earliest decision variable).  Parameters (513 floats): W1[k][f] at
+ * k*6+f, b1 at 384+k, w2 at 448+k, b2 at 512.  Training keeps FP32 master
+ * weights and Adam moments on the device; the search reads a BF16 copy and
+ * accumulates in FP32.  Targets come from search traces (how strongly an
+ * expert prefers each candidate of a node); the loss is the mean over nodes
+ * of the cross-entropy between target and softmax over the candidates.  The paper leaves the
+ * search strategy open (§5, Evaluation); first-fail is the fallback. */
+typedef struct pccp_mlp pccp_mlp;
+
+/* New network on the current device, Glorot-uniform weights drawn from a
+ * SplitMix64 stream seeded with `seed`, zero biases.  stream: hipStream_t. */
+int32_t pccp_mlp_create(uint64_t seed, void *stream, pccp_mlp **out);
+int32_t pccp_mlp_destroy(pccp_mlp *m);
+
+/* Host copies of the 513 FP32 parameters; set also resets the Adam state. */
+int32_t pccp_mlp_set_params(pccp_mlp *m, const float *params);
+int32_t pccp_mlp_get_params(pccp_mlp *m, float *params);
+
+/* One training step on device data: feat [ncand][6] float, node_off
+ * [nnodes+1] int32 (candidates of node i are node_off[i]..node_off[i+1]-1),
+ * target [ncand] float (a distribution over each node's candidates: the
+ * loss is the mean over nodes of -sum_c target_c log softmax(s)_c),
+ * max_cand = the largest candidate count of a node (<= 256).  Computes the
+ * loss and gradient at the current parameters, then (lr > 0) one Adam step
+ * (beta 0.9/0.999, eps 1e-8) and refreshes the BF16 copy.  *loss (may be
+ * NULL) receives the loss before the step (synchronises the stream). */
+int32_t pccp_mlp_train_step(pccp_mlp *m, const float *feat, const int32_t *node_off,
+                            const float *target, int32_t nnodes, int32_t ncand,
+                            int32_t max_cand, float lr, float *loss);
+
+/* Gradient (513 floats, host) of the last training step. */
+int32_t pccp_mlp_get_grads(pccp_mlp *m, float *grads);
+
+/* Scores of ncand candidates (device arrays feat [ncand][6], scores
+ * [ncand]) with the FP32 master weights (bf16 = 0) or the BF16 copy the
+ * search uses (bf16 = 1). */
+int32_t pccp_mlp_scores(pccp_mlp *m, const float *feat, int32_t ncand, float *scores,
+                        int32_t bf16);
+
+/* Device pointer of the BF16 parameters, for pccp_set_branching. */
+int32_t pccp_mlp_weights(const pccp_mlp *m, const void **weights);
 
 const char *pccp_last_error(void);
 const char *pccp_version(void);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "liboracle.so")
 FIXPOINT, FAILED = 0, 1
 SCHED_GS, SCHED_JACOBI, SCHED_PERM, SCHED_SELECT, SCHED_REVERSE = 0, 1, 2, 3, 4
 ENUMERATE, MINIMIZE = 0, 1
-FIRST_FAIL, INPUT_ORDER = 0, 1
+FIRST_FAIL, INPUT_ORDER, EXPERT, MLP = 0, 1, 2, 3
 OUT_ALL, OUT_OPTIMAL, OUT_UNSAT, OUT_LIMIT = 0, 1, 2, 3
 OUTCOME_NAMES = {OUT_ALL: "all", OUT_OPTIMAL: "optimal", OUT_UNSAT: "unsat",
                  OUT_LIMIT: "limit"}
@@ -74,6 +74,18 @@ def lib():
         L.orc_check_schedule.argtypes = [C.c_int32, _P32, C.c_int32, _P32,
                                          C.c_int32, _P32, _P32, _P32, _P32]
         L.orc_check_schedule.restype = C.c_int32
+        PD = C.POINTER(C.c_double)
+        L.orc_features.argtypes = [MP, _P32, _P32, PD]
+        L.orc_features.restype = C.c_int32
+        L.orc_mlp_forward.argtypes = [PD, PD, C.c_int64, PD]
+        L.orc_mlp_forward.restype = C.c_int32
+        L.orc_mlp_loss_grad.argtypes = [PD, PD, _P32, PD, C.c_int32, PD, PD]
+        L.orc_mlp_loss_grad.restype = C.c_int32
+        L.orc_trace.argtypes = [MP, C.c_int32, C.c_int64, C.POINTER(C.c_float), PD, _P32,
+                                _P32, _P32, C.c_int64, C.c_int64, C.POINTER(C.c_int64)]
+        L.orc_trace.restype = C.c_int64
+        L.orc_set_mlp_params.argtypes = [PD]
+        L.orc_set_mlp_params.restype = None
         L.orc_floor_div.argtypes = [C.c_int64, C.c_int64]
         L.orc_floor_div.restype = C.c_int64
         L.orc_ceil_div.argtypes = [C.c_int64, C.c_int64]
@@ -229,3 +241,83 @@ def floor_div(a: int, b: int) -> int:
 
 def ceil_div(a: int, b: int) -> int:
     return int(lib().orc_ceil_div(a, b))
+
+
+# ---------------------------------------------------------------- learned
+NFEAT, NHID = 6, 64
+NPARAM = NHID * NFEAT + NHID + NHID + 1
+
+
+def _pd(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def features(model, lb, ub):
+    """[ndecision, 6] float64 features of a store."""
+    om = _om(model)
+    lb, ub = _i32(lb), _i32(ub)
+    out = np.zeros((max(int(om.model.decision.shape[0]), 1), NFEAT), dtype=np.float64)
+    rc = lib().orc_features(om.ref(), _ptr(lb), _ptr(ub), _pd(out))
+    if rc < 0:
+        raise ValueError(f"orc_features error {rc}")
+    return out[:int(om.model.decision.shape[0])]
+
+
+def mlp_forward(params, x):
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, NFEAT)
+    out = np.zeros(max(x.shape[0], 1), dtype=np.float64)
+    lib().orc_mlp_forward(_pd(p), _pd(x), x.shape[0], _pd(out))
+    return out[:x.shape[0]]
+
+
+def one_hot(node_off, label):
+    t = np.zeros(int(node_off[-1]), dtype=np.float64)
+    t[np.asarray(node_off[:-1]) + np.asarray(label)] = 1.0
+    return t
+
+
+def mlp_loss_grad(params, x, node_off, target):
+    """Loss and gradient; `target` is a distribution per node over its
+    candidates ([C] floats), e.g. one_hot(off, label)."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, NFEAT)
+    off = _i32(node_off)
+    t = np.ascontiguousarray(target, dtype=np.float64)
+    assert t.shape == (x.shape[0],)
+    g = np.zeros(NPARAM, dtype=np.float64)
+    loss = C.c_double(0.0)
+    lib().orc_mlp_loss_grad(_pd(p), _pd(x), _ptr(off), _pd(t), int(off.shape[0] - 1),
+                            C.byref(loss), _pd(g))
+    return float(loss.value), g
+
+
+def trace(model, node_limit, mode=None, cap_nodes=100000, cap_cand=4000000):
+    """Expert-labelled search trace: dict(feat [C,6] f32, cand [C], off [N+1],
+    label [N])."""
+    om = _om(model)
+    mode = om.model.mode if mode is None else mode
+    feat = np.zeros((cap_cand, NFEAT), dtype=np.float32)
+    score = np.zeros(cap_cand, dtype=np.float64)
+    cand = np.zeros(cap_cand, dtype=np.int32)
+    off = np.zeros(cap_nodes + 1, dtype=np.int32)
+    lab = np.zeros(cap_nodes, dtype=np.int32)
+    nc = C.c_int64(0)
+    n = lib().orc_trace(om.ref(), int(mode), int(node_limit),
+                        feat.ctypes.data_as(C.POINTER(C.c_float)), _pd(score), _ptr(cand), _ptr(off),
+                        _ptr(lab), cap_nodes, cap_cand, C.byref(nc))
+    if n < 0:
+        raise ValueError(f"orc_trace error {n}")
+    c = int(nc.value)
+    return dict(feat=feat[:c].copy(), score=score[:c].copy(), cand=cand[:c].copy(),
+                off=off[:n + 1].copy(), label=lab[:n].copy())
+
+
+_mlp_keep = None
+
+
+def set_mlp_params(params):
+    """Parameters for MLP branching in solve(..., branching=MLP)."""
+    global _mlp_keep
+    _mlp_keep = np.ascontiguousarray(params, dtype=np.float64)
+    lib().orc_set_mlp_params(_pd(_mlp_keep))

@@ -6,14 +6,14 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["propagate.c", "search.c", "brute.c"]
+SOURCES = ["propagate.c", "search.c", "brute.c", "learn.c"]
 
 
 def build(verbose: bool = False) -> str:
     out = os.path.join(HERE, "liboracle.so")
     tmp = out + ".tmp"
     cmd = ["gcc", "-O3", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
-           "-o", tmp] + [os.path.join(HERE, s) for s in SOURCES]
+           "-o", tmp] + [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

@@ -73,7 +73,9 @@ enum {
 };
 
 enum { ORC_ENUMERATE = 0, ORC_MINIMIZE = 1 };
-enum { ORC_FIRST_FAIL = 0, ORC_INPUT_ORDER = 1 };
+enum { ORC_FIRST_FAIL = 0, ORC_INPUT_ORDER = 1, ORC_EXPERT = 2 /* learn.c */,
+       ORC_MLP = 3 /* network scores, see orc_set_mlp_params */ };
+void orc_set_mlp_params(const double *p);
 enum {
     ORC_OUT_ALL = 0,        /* ENUMERATE: search tree exhausted             */
     ORC_OUT_OPTIMAL = 1,    /* MINIMIZE: best solution proven optimal       */
@@ -141,6 +143,25 @@ int32_t orc_check_schedule(int32_t n, const int32_t *dur, int32_t nedges,
                            const int32_t *edges, int32_t nres,
                            const int32_t *dem, const int32_t *cap,
                            const int32_t *s, int32_t *makespan);
+
+/* ---- learned branching (learn.c) ----------------------------------- */
+
+/* Features of every decision variable in the store (lb, ub): 6 doubles per
+ * decision variable, in decision-list order (definitions in learn.c). */
+int32_t orc_features(const orc_model *m, const int32_t *lb, const int32_t *ub, double *out);
+
+/* Scores of ncand candidates (6 features each) under parameters p (513). */
+int32_t orc_mlp_forward(const double *p, const double *x, int64_t ncand, double *scores);
+
+/* Mean per-node cross-entropy between targets t (per candidate, summing to
+ * 1 over each node) and the softmax of the scores; gradient (513 values). */
+int32_t orc_mlp_loss_grad(const double *p, const double *x, const int32_t *node_off,
+                          const double *t, int32_t nnodes, double *loss, double *g);
+
+/* Search traces with expert labels (see learn.c). */
+int64_t orc_trace(const orc_model *m, int32_t mode, int64_t node_limit, float *feat,
+                  double *score, int32_t *cand, int32_t *off, int32_t *label, int64_t cap_nodes,
+                  int64_t cap_cand, int64_t *ncand);
 
 #ifdef __cplusplus
 }

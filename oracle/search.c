@@ -60,10 +60,22 @@ typedef struct {
     int hit_limit;
 } ctx_t;
 
+int32_t orc_expert_choice(const orc_model *m, const int32_t *lb, const int32_t *ub);
+int32_t orc_mlp_choice(const orc_model *m, const double *p, const int32_t *lb, const int32_t *ub);
+static const double *g_mlp_params = NULL;  /* set by orc_set_mlp_params */
+
+/* Parameters (513 doubles, see learn.c) used by ORC_MLP branching; the
+ * caller keeps them alive during the searches.  Not thread-safe. */
+void orc_set_mlp_params(const double *p) { g_mlp_params = p; }
+
 /* index into m->dec of the branching variable, or -1 if all are fixed */
 static int32_t choose(const ctx_t *c, const int32_t *lb, const int32_t *ub)
 {
     const orc_model *m = c->m;
+    if (c->branching == ORC_EXPERT)
+        return orc_expert_choice(m, lb, ub);
+    if (c->branching == ORC_MLP)
+        return orc_mlp_choice(m, g_mlp_params, lb, ub);
     int32_t pick = -1;
     int64_t best_w = 0;
     for (int32_t k = 0; k < m->ndec; ++k) {
@@ -153,7 +165,8 @@ int32_t orc_solve(const orc_model *m, int32_t mode, int32_t branching,
     if (rc)
         return rc;
     if (!st || (mode != ORC_ENUMERATE && mode != ORC_MINIMIZE) ||
-        (branching != ORC_FIRST_FAIL && branching != ORC_INPUT_ORDER))
+        (branching != ORC_FIRST_FAIL && branching != ORC_INPUT_ORDER && branching != ORC_EXPERT &&
+         branching != ORC_MLP) || (branching == ORC_MLP && !g_mlp_params))
         return -1;
     if (mode == ORC_MINIMIZE && m->objective < 0)
         return -1;

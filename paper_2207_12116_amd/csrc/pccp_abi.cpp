@@ -131,7 +131,72 @@ struct Compiled {
     std::vector<int2> diff, reif;
     std::vector<int4> rows;
     std::vector<uint32_t> terms;
+    // learned-branching tables (see pccp_types.h)
+    std::vector<float> fstat;
+    std::vector<int32_t> fr_ptr, fb_ptr, fb;
+    std::vector<int2> fr;
 };
+
+// Static part of the branching features of every decision variable q
+// (x = dec[q], H = max(1, ub0 - lb0)): 1/H, the share of the largest
+// variable degree (rows + reified items containing the variable), the
+// static load (mean over the reified items with si = x of d * w(b) / H,
+// w(b) = sum of a / c over rows a*b + ... <= c with a > 0, c > 0), 1/N;
+// and the tables the dynamic features read: rows x - y <= c leaving x,
+// and the b of the items with si = x.
+static void compile_features(const pccp_model *m, Compiled &c)
+{
+    const int32_t V = c.nvars, D = c.ndec;
+    std::vector<double> deg(V, 0.0), w(V, 0.0);
+    const int32_t R = (int32_t)m->rhs.size();
+    for (int32_t r = 0; r < R; ++r)
+        for (int32_t t = m->row_ptr[r]; t < m->row_ptr[r + 1]; ++t) {
+            deg[m->var[t]] += 1.0;
+            if (m->coef[t] > 0 && m->rhs[r] > 0) w[m->var[t]] += (double)m->coef[t] / m->rhs[r];
+        }
+    const size_t Q = m->reif.size() / 4;
+    for (size_t q = 0; q < Q; ++q)
+        for (int k = 0; k < 3; ++k) deg[m->reif[4 * q + k]] += 1.0;
+    double maxdeg = 1.0;
+    for (double d : deg) maxdeg = std::max(maxdeg, d);
+    // rows x - y <= c by their +1 variable, items by si
+    std::vector<std::vector<int2>> out_rows(V);
+    for (int32_t r = 0; r < R; ++r) {
+        const int32_t a0 = m->row_ptr[r];
+        if (m->row_ptr[r + 1] - a0 != 2) continue;
+        if (m->coef[a0] == 1 && m->coef[a0 + 1] == -1)
+            out_rows[m->var[a0]].push_back(make_int2(m->var[a0 + 1], m->rhs[r]));
+        else if (m->coef[a0] == -1 && m->coef[a0 + 1] == 1)
+            out_rows[m->var[a0 + 1]].push_back(make_int2(m->var[a0], m->rhs[r]));
+    }
+    std::vector<std::vector<int32_t>> items_b(V);
+    std::vector<double> load(V, 0.0);
+    for (size_t q = 0; q < Q; ++q) {
+        const int32_t *it = &m->reif[4 * q];
+        items_b[it[1]].push_back(it[0]);
+        load[it[1]] += (double)it[3] * w[it[0]];
+    }
+    c.fstat.assign(8 * (size_t)D, 0.f);
+    c.fr_ptr.assign(D + 1, 0);
+    c.fb_ptr.assign(D + 1, 0);
+    for (int32_t q = 0; q < D; ++q) {
+        const int32_t x = c.dec[q];
+        const double H = std::max(1.0, (double)c.ub0[x] - (double)c.lb0[x]);
+        const double N = std::max<double>(1.0, (double)items_b[x].size());
+        float lo_bits;
+        const int32_t lo = c.lb0[x];
+        memcpy(&lo_bits, &lo, 4);
+        c.fstat[8 * q + 0] = lo_bits;
+        c.fstat[8 * q + 1] = (float)(1.0 / H);
+        c.fstat[8 * q + 2] = (float)(deg[x] / maxdeg);
+        c.fstat[8 * q + 3] = (float)(load[x] / N / H);
+        c.fstat[8 * q + 4] = (float)(1.0 / N);
+        c.fr.insert(c.fr.end(), out_rows[x].begin(), out_rows[x].end());
+        c.fb.insert(c.fb.end(), items_b[x].begin(), items_b[x].end());
+        c.fr_ptr[q + 1] = (int32_t)c.fr.size();
+        c.fb_ptr[q + 1] = (int32_t)c.fb.size();
+    }
+}
 
 static int32_t compile_model(const pccp_model *m, Compiled &c)
 {
@@ -151,8 +216,14 @@ static int32_t compile_model(const pccp_model *m, Compiled &c)
     if (m->objective < -1 || m->objective >= V)
         return fail(PCCP_E_MODEL, "objective variable out of range");
     c.objective = m->objective;
-    for (int32_t x : m->dec)
-        if (x < 0 || x >= V) return fail(PCCP_E_MODEL, "decision variable out of range");
+    {
+        std::vector<char> isdec(V, 0);
+        for (int32_t x : m->dec) {
+            if (x < 0 || x >= V) return fail(PCCP_E_MODEL, "decision variable out of range");
+            if (isdec[x]) return fail(PCCP_E_MODEL, "decision variable listed twice");
+            isdec[x] = 1;
+        }
+    }
     c.dec = m->dec;
     c.ndec = (int32_t)m->dec.size();
     const int32_t R = (int32_t)m->rhs.size();
@@ -200,6 +271,7 @@ static int32_t compile_model(const pccp_model *m, Compiled &c)
         c.reif.push_back(make_int2((int32_t)((uint32_t)it[0] | ((uint32_t)it[1] << 16)),
                                    (int32_t)((uint32_t)it[2] | ((uint32_t)(uint16_t)(int16_t)it[3] << 16))));
     }
+    compile_features(m, c);
     return PCCP_OK;
 }
 
@@ -230,13 +302,18 @@ struct DevBuf {
     template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
 };
 
-// search workspace (grow-only)
+// search workspace (grow-only), and the graph of the last launch
 struct Workspace {
     DevBuf models, inst, globals, qseq, qdata, roots, best;
+    hipGraphExec_t graph = nullptr;
+    std::vector<char> graph_key;
     void release()
     {
         models.release(); inst.release(); globals.release(); qseq.release();
         qdata.release(); roots.release(); best.release();
+        if (graph) (void)hipGraphExecDestroy(graph);
+        graph = nullptr;
+        graph_key.clear();
     }
 };
 
@@ -278,6 +355,8 @@ static int32_t check_cfg(const pccp_config &cfg)
 {
     if (cfg.wg_size % 64 != 0 || cfg.wg_size > kMaxWg)
         return fail(PCCP_E_INVALID_ARG, "wg_size must be a multiple of 64 and <= 1024");
+    if (cfg.launch < 0 || cfg.launch > 1)
+        return fail(PCCP_E_INVALID_ARG, "launch must be 0 (graph) or 1 (plain)");
     if (cfg.num_wgs < 0 || cfg.queue_cap < 0 || cfg.desc_lds < 0 || cfg.desc_lds > 2 ||
         cfg.root_lds < 0 || cfg.root_lds > 2 || cfg.max_depth > (1 << 16))
         return fail(PCCP_E_INVALID_ARG, "bad config field");
@@ -319,7 +398,12 @@ extern "C" int32_t pccp_solver_create(const pccp_model *m, const pccp_config *cf
     const size_t o_rows = o_reif + al(8 * c.reif.size());
     const size_t o_terms = o_rows + al(16 * c.rows.size());
     const size_t o_dec = o_terms + al(4 * c.terms.size());
-    const size_t total = o_dec + al(4 * (size_t)c.ndec) + 256;
+    const size_t o_fstat = o_dec + al(4 * (size_t)c.ndec);
+    const size_t o_frp = o_fstat + al(4 * c.fstat.size());
+    const size_t o_fr = o_frp + al(4 * c.fr_ptr.size());
+    const size_t o_fbp = o_fr + al(8 * c.fr.size());
+    const size_t o_fb = o_fbp + al(4 * c.fb_ptr.size());
+    const size_t total = o_fb + al(4 * c.fb.size()) + 256;
     rc = s->tables.ensure(total);
     if (rc == PCCP_OK) rc = s->dmodel.ensure(sizeof(DevModel));
     if (rc != PCCP_OK) { delete s; return rc; }
@@ -333,6 +417,11 @@ extern "C" int32_t pccp_solver_create(const pccp_model *m, const pccp_config *cf
     put(o_rows, c.rows.data(), 16 * c.rows.size());
     put(o_terms, c.terms.data(), 4 * c.terms.size());
     put(o_dec, c.dec.data(), 4 * (size_t)c.ndec);
+    put(o_fstat, c.fstat.data(), 4 * c.fstat.size());
+    put(o_frp, c.fr_ptr.data(), 4 * c.fr_ptr.size());
+    put(o_fr, c.fr.data(), 8 * c.fr.size());
+    put(o_fbp, c.fb_ptr.data(), 4 * c.fb_ptr.size());
+    put(o_fb, c.fb.data(), 4 * c.fb.size());
     DevModel &dm = s->hmodel;
     dm.nvars = c.nvars;
     dm.ndiff = (int32_t)c.diff.size();
@@ -341,6 +430,14 @@ extern "C" int32_t pccp_solver_create(const pccp_model *m, const pccp_config *cf
     dm.nterms = (int32_t)c.terms.size();
     dm.ndec = c.ndec;
     dm.objective = c.objective;
+    // lanes per linear row in a sweep: the smallest group (4, 8, 16) that
+    // covers the longest row in at most two terms per lane, else 16
+    int lmax = 0;
+    for (const int4 &r : c.rows) lmax = std::max(lmax, r.y);
+    dm.row_group = 16;
+    for (int g : {4, 8, 16})
+        if ((lmax + g - 1) / g <= 2) { dm.row_group = g; break; }
+    dm.row_chunks = (lmax + dm.row_group - 1) / dm.row_group;
     dm.lb0 = reinterpret_cast<const int32_t *>(base + o_lb);
     dm.ub0 = reinterpret_cast<const int32_t *>(base + o_ub);
     dm.diff = reinterpret_cast<const int2 *>(base + o_diff);
@@ -348,7 +445,11 @@ extern "C" int32_t pccp_solver_create(const pccp_model *m, const pccp_config *cf
     dm.rows = reinterpret_cast<const int4 *>(base + o_rows);
     dm.terms = reinterpret_cast<const uint32_t *>(base + o_terms);
     dm.dec = reinterpret_cast<const int32_t *>(base + o_dec);
-    dm.feat_static = nullptr;
+    dm.fstat = reinterpret_cast<const float *>(base + o_fstat);
+    dm.fr_ptr = reinterpret_cast<const int32_t *>(base + o_frp);
+    dm.fr = reinterpret_cast<const int2 *>(base + o_fr);
+    dm.fb_ptr = reinterpret_cast<const int32_t *>(base + o_fbp);
+    dm.fb = reinterpret_cast<const int32_t *>(base + o_fb);
     e = hipMemcpyAsync(base, host.data(), total, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->dmodel.p, &dm, sizeof(DevModel), hipMemcpyHostToDevice, s->stream);
@@ -439,6 +540,18 @@ extern "C" int32_t pccp_propagate(pccp_solver *s, const int32_t *lb_in, const in
     return PCCP_OK;
 }
 
+extern "C" int32_t pccp_node_features(pccp_solver *s, int32_t nbox, const int32_t *lb,
+                                      const int32_t *ub, float *feat)
+{
+    if (!s || nbox < 0 || (nbox > 0 && (!lb || !ub || !feat)))
+        return fail(PCCP_E_INVALID_ARG, "pccp_node_features: bad arguments");
+    if (nbox == 0 || s->c.ndec == 0) return PCCP_OK;
+    HIPCHK(hipSetDevice(s->device));
+    HIPCHK(launch_features(reinterpret_cast<const DevModel *>(s->dmodel.p), s->c.nvars, nbox, lb, ub,
+                           feat, s->stream));
+    return PCCP_OK;
+}
+
 extern "C" int32_t pccp_get_domains(pccp_solver *s, int32_t *lb, int32_t *ub, int32_t cap)
 {
     if (!s || !lb || !ub) return fail(PCCP_E_INVALID_ARG, "pccp_get_domains: bad arguments");
@@ -457,7 +570,8 @@ struct LaunchShape {
 };
 
 static int32_t choose_shape(pccp_solver *const *sv, int n, const pccp_config &cfg, int max_vars,
-                            size_t max_desc, int num_cus, size_t lds_max, LaunchShape &sh)
+                            size_t max_desc, int num_cus, size_t lds_max, LaunchShape &sh,
+                            int feat_ndec = 0)
 {
     sh.block = cfg.wg_size;
     struct Cand { bool d, r; };
@@ -466,7 +580,7 @@ static int32_t choose_shape(pccp_solver *const *sv, int n, const pccp_config &cf
     for (const Cand &cd : cands) {
         if (cfg.desc_lds != 0 && cd.d != (cfg.desc_lds == 1)) continue;
         if (cfg.root_lds != 0 && cd.r != (cfg.root_lds == 1)) continue;
-        const size_t lds = search_lds_bytes(max_vars, cfg.max_depth, max_desc, cd.d, cd.r);
+        const size_t lds = search_lds_bytes(max_vars, cfg.max_depth, max_desc, cd.d, cd.r, feat_ndec);
         if (lds > lds_max) continue;
         int occ = 0;
         hipError_t e = search_occupancy(sh.block, lds, cd.d, cd.r, &occ);
@@ -510,8 +624,10 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
         max_desc = std::max(max_desc, sv[i]->desc_bytes);
     }
     HIPCHK(hipSetDevice(s0->device));
+    const bool learned = s0->branching == PCCP_BRANCH_MLP && s0->mlp != nullptr;
     LaunchShape sh;
-    rc = choose_shape(sv, n, cfg, max_vars, max_desc, s0->num_cus, s0->lds_max, sh);
+    rc = choose_shape(sv, n, cfg, max_vars, max_desc, s0->num_cus, s0->lds_max, sh,
+                      learned ? max_ndec : 0);
     if (rc != PCCP_OK) return rc;
     const int qcap = cfg.queue_cap > 0 ? std::max(cfg.queue_cap, n) : std::max(4 * sh.grid, n + sh.grid);
     const int slot_bytes = (int)(((size_t)sizeof(RecHdr) + sizeof(int2) * (size_t)cfg.max_depth + 15) & ~size_t(15));
@@ -538,7 +654,7 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
     P.inst = ws.inst.as<InstState>();
     P.ninst = n;
     P.mode = mode;
-    P.branching = s0->branching == PCCP_BRANCH_INPUT_ORDER ? 1 : 0;
+    P.branching = learned ? 2 : (s0->branching == PCCP_BRANCH_INPUT_ORDER ? 1 : 0);
     P.max_depth = cfg.max_depth;
     P.g = ws.globals.as<SearchGlobals>();
     P.q_seq = ws.qseq.as<unsigned long long>();
@@ -555,11 +671,28 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
     P.sol_cap = keep_sols ? cfg.sol_cap : 0;
     P.best_vals = ws.best.as<int32_t>();
     P.max_ndec = max_ndec;
-    P.mlp = nullptr;
+    P.mlp = learned ? reinterpret_cast<const uint16_t *>(s0->mlp) : nullptr;
 
-    HIPCHK(hipEventRecord(s0->ev0, s0->stream));
-    HIPCHK(launch_search(P, sh.grid, sh.block, sh.lds, sh.desc_lds, sh.root_lds, s0->stream));
-    HIPCHK(hipEventRecord(s0->ev1, s0->stream));
+    if (cfg.launch == 0) {
+        // the graph bakes in the launch parameters: rebuild it when they change
+        std::vector<char> key(sizeof(P) + 5 * sizeof(int64_t));
+        memcpy(key.data(), &P, sizeof(P));
+        const int64_t extra[5] = {sh.grid, sh.block, (int64_t)sh.lds, sh.desc_lds, sh.root_lds};
+        memcpy(key.data() + sizeof(P), extra, sizeof(extra));
+        if (!ws.graph || key != ws.graph_key) {
+            if (ws.graph) (void)hipGraphExecDestroy(ws.graph);
+            ws.graph = nullptr;
+            HIPCHK(build_search_graph(P, sh.grid, sh.block, sh.lds, sh.desc_lds, sh.root_lds, &ws.graph));
+            ws.graph_key = key;
+        }
+        HIPCHK(hipEventRecord(s0->ev0, s0->stream));
+        HIPCHK(hipGraphLaunch(ws.graph, s0->stream));
+        HIPCHK(hipEventRecord(s0->ev1, s0->stream));
+    } else {
+        HIPCHK(hipEventRecord(s0->ev0, s0->stream));
+        HIPCHK(launch_search(P, sh.grid, sh.block, sh.lds, sh.desc_lds, sh.root_lds, s0->stream));
+        HIPCHK(hipEventRecord(s0->ev1, s0->stream));
+    }
     std::vector<InstState> st(n);
     SearchGlobals g{};
     std::vector<int32_t> bv((size_t)n * max_ndec);
@@ -693,5 +826,144 @@ extern "C" int32_t pccp_solver_capacity(const pccp_solver *s, int32_t *wgs_per_c
     if (rc != PCCP_OK) return rc;
     if (wgs_per_cu) *wgs_per_cu = sh.wgs_per_cu;
     if (num_cus) *num_cus = s->num_cus;
+    return PCCP_OK;
+}
+
+// ------------------------------------------------------------------ learned branching
+struct pccp_mlp {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    DevBuf state;      // params, m1, v1, grad (kNumParams each), bf16 copy, loss
+    DevBuf work;       // per-candidate dL/ds + per-wave partials
+    int64_t step = 0;
+    float *params() { return state.as<float>(); }
+    float *m1() { return state.as<float>() + 1 * 520; }
+    float *v1() { return state.as<float>() + 2 * 520; }
+    float *grad() { return state.as<float>() + 3 * 520; }
+    float *loss() { return state.as<float>() + 4 * 520; }
+    uint16_t *wbf() { return reinterpret_cast<uint16_t *>(state.as<float>() + 5 * 520); }
+};
+
+static uint64_t splitmix64(uint64_t &x)
+{
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+extern "C" int32_t pccp_mlp_create(uint64_t seed, void *stream, pccp_mlp **out)
+{
+    if (!out) return fail(PCCP_E_INVALID_ARG, "pccp_mlp_create: out is NULL");
+    *out = nullptr;
+    pccp_mlp *m = new (std::nothrow) pccp_mlp();
+    if (!m) return fail(PCCP_E_NOMEM, "pccp_mlp_create: out of memory");
+    m->stream = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipGetDevice(&m->device);
+    if (e != hipSuccess) { delete m; return fail(PCCP_E_DEVICE, hipGetErrorString(e)); }
+    int32_t rc = m->state.ensure(sizeof(float) * 520 * 6);
+    if (rc != PCCP_OK) { delete m; return rc; }
+    // Glorot-uniform initial weights from a SplitMix64 stream, zero biases
+    std::vector<float> host(520 * 5, 0.f);
+    uint64_t st = seed;
+    auto unif = [&](double a) {
+        return (float)(a * (2.0 * ((splitmix64(st) >> 11) * (1.0 / 9007199254740992.0)) - 1.0));
+    };
+    const double a1 = std::sqrt(6.0 / (kNumFeat + kHidden)), a2 = std::sqrt(6.0 / (kHidden + 1));
+    for (int i = 0; i < kHidden * kNumFeat; ++i) host[i] = unif(a1);
+    for (int k = 0; k < kHidden; ++k) host[kHidden * kNumFeat + kHidden + k] = unif(a2);
+    e = hipMemcpyAsync(m->state.p, host.data(), sizeof(float) * host.size(), hipMemcpyHostToDevice,
+                       m->stream);
+    if (e == hipSuccess) e = launch_mlp_sync_bf16(m->params(), m->wbf(), m->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    if (e != hipSuccess) {
+        m->state.release();
+        delete m;
+        return fail(PCCP_E_DEVICE, std::string("pccp_mlp_create: ") + hipGetErrorString(e));
+    }
+    *out = m;
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_mlp_destroy(pccp_mlp *m)
+{
+    if (!m) return PCCP_OK;
+    (void)hipStreamSynchronize(m->stream);
+    m->state.release();
+    m->work.release();
+    delete m;
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_mlp_set_params(pccp_mlp *m, const float *params)
+{
+    if (!m || !params) return fail(PCCP_E_INVALID_ARG, "pccp_mlp_set_params: bad arguments");
+    HIPCHK(hipSetDevice(m->device));
+    HIPCHK(hipMemcpyAsync(m->params(), params, sizeof(float) * kNumParams, hipMemcpyHostToDevice, m->stream));
+    HIPCHK(hipMemsetAsync(m->m1(), 0, sizeof(float) * 520 * 2, m->stream));
+    HIPCHK(launch_mlp_sync_bf16(m->params(), m->wbf(), m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
+    m->step = 0;
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_mlp_get_params(pccp_mlp *m, float *params)
+{
+    if (!m || !params) return fail(PCCP_E_INVALID_ARG, "pccp_mlp_get_params: bad arguments");
+    HIPCHK(hipSetDevice(m->device));
+    HIPCHK(hipMemcpyAsync(params, m->params(), sizeof(float) * kNumParams, hipMemcpyDeviceToHost, m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_mlp_get_grads(pccp_mlp *m, float *grads)
+{
+    if (!m || !grads) return fail(PCCP_E_INVALID_ARG, "pccp_mlp_get_grads: bad arguments");
+    HIPCHK(hipSetDevice(m->device));
+    HIPCHK(hipMemcpyAsync(grads, m->grad(), sizeof(float) * kNumParams, hipMemcpyDeviceToHost, m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_mlp_train_step(pccp_mlp *m, const float *feat, const int32_t *node_off,
+                                       const float *target, int32_t nnodes, int32_t ncand,
+                                       int32_t max_cand, float lr, float *loss)
+{
+    if (!m || !feat || !node_off || !target || nnodes < 1 || ncand < 1 || lr < 0.f)
+        return fail(PCCP_E_INVALID_ARG, "pccp_mlp_train_step: bad arguments");
+    if (max_cand > kMlpMaxCand || max_cand < 1)
+        return fail(PCCP_E_UNSUPPORTED, "pccp_mlp_train_step: more than 256 candidates in a node");
+    HIPCHK(hipSetDevice(m->device));
+    const int rows = mlp_partial_rows();
+    int32_t rc = m->work.ensure(sizeof(float) * ((size_t)ncand + (size_t)rows * 520 + 64));
+    if (rc != PCCP_OK) return rc;
+    float *g = m->work.as<float>();
+    float *partial = g + (((size_t)ncand + 63) & ~size_t(63));
+    if (lr > 0.f) m->step += 1;
+    HIPCHK(launch_mlp_train(feat, node_off, target, nnodes, ncand, m->params(), m->m1(), m->v1(),
+                            m->wbf(), m->grad(), g, partial, lr, (int)std::max<int64_t>(m->step, 1),
+                            m->loss(), m->stream));
+    if (loss) {
+        HIPCHK(hipMemcpyAsync(loss, m->loss(), sizeof(float), hipMemcpyDeviceToHost, m->stream));
+        HIPCHK(hipStreamSynchronize(m->stream));
+    }
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_mlp_scores(pccp_mlp *m, const float *feat, int32_t ncand, float *scores,
+                                   int32_t bf16)
+{
+    if (!m || ncand < 0 || (ncand > 0 && (!feat || !scores)))
+        return fail(PCCP_E_INVALID_ARG, "pccp_mlp_scores: bad arguments");
+    if (ncand == 0) return PCCP_OK;
+    HIPCHK(hipSetDevice(m->device));
+    HIPCHK(launch_mlp_scores(m->params(), m->wbf(), bf16 ? 1 : 0, feat, ncand, scores, m->stream));
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_mlp_weights(const pccp_mlp *m, const void **weights)
+{
+    if (!m || !weights) return fail(PCCP_E_INVALID_ARG, "pccp_mlp_weights: bad arguments");
+    *weights = reinterpret_cast<const void *>(const_cast<pccp_mlp *>(m)->wbf());
     return PCCP_OK;
 }

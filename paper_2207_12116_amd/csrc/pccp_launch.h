@@ -8,7 +8,8 @@
 namespace pccp {
 
 size_t model_desc_bytes(int ndiff, int nreif, int nrows, int nterms, int ndec);
-size_t search_lds_bytes(int max_vars, int max_depth, size_t max_desc, bool desc_lds, bool root_lds);
+size_t search_lds_bytes(int max_vars, int max_depth, size_t max_desc, bool desc_lds, bool root_lds,
+                        int feat_ndec);
 size_t propagate_lds_bytes(int nvars, size_t desc, bool desc_lds);
 
 hipError_t launch_propagate_batch(const DevModel *m_dev, int nbox, const int32_t *lb_in,
@@ -18,6 +19,22 @@ hipError_t launch_propagate_batch(const DevModel *m_dev, int nbox, const int32_t
 
 hipError_t launch_search(const SearchParams &P, int grid, int block, size_t lds, bool desc_lds,
                          bool root_lds, hipStream_t stream);
+
+hipError_t build_search_graph(const SearchParams &P, int grid, int block, size_t lds,
+                              bool desc_lds, bool root_lds, hipGraphExec_t *exec);
+
+hipError_t launch_features(const DevModel *m_dev, int nvars, int nbox, const int32_t *lb_in,
+                           const int32_t *ub_in, float *out, hipStream_t stream);
+
+constexpr int kMlpMaxCand = 256;
+int mlp_partial_rows();
+hipError_t launch_mlp_train(const float *feat, const int32_t *off, const float *target, int nnodes,
+                            int ncand, float *params, float *m1, float *v1, uint16_t *wbf,
+                            float *grad, float *g, float *partial, float lr, int step,
+                            float *loss_dev, hipStream_t stream);
+hipError_t launch_mlp_sync_bf16(const float *params, uint16_t *wbf, hipStream_t stream);
+hipError_t launch_mlp_scores(const float *params, const uint16_t *wbf, int use_bf16,
+                             const float *feat, int ncand, float *scores, hipStream_t stream);
 
 hipError_t search_occupancy(int block, size_t lds, bool desc_lds, bool root_lds, int *wgs_per_cu);
 

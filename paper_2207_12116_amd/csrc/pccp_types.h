@@ -28,6 +28,8 @@ struct DevModel {
     int32_t nvars;
     int32_t ndiff, nreif, nrows, nterms;
     int32_t ndec, objective;
+    int32_t row_group;            // lanes per linear row in a sweep (4, 8 or 16)
+    int32_t row_chunks;           // ceil(longest row / row_group)
     int32_t pad0;
     const int32_t *lb0, *ub0;     // initial box
     const int2 *diff;             // kind 1
@@ -35,8 +37,20 @@ struct DevModel {
     const int4 *rows;             // kind 3 rows
     const uint32_t *terms;        // kind 3 terms
     const int32_t *dec;           // decision variables (tie-break order)
-    const float *feat_static;     // learned branching: static features per decision var (may be null)
+    // learned branching: per decision variable q, fstat[8q..8q+4] =
+    // {lo, 1/H, degree share, static load, 1/N}; rows x - y <= c leaving
+    // x = dec[q] as fr[fr_ptr[q]..fr_ptr[q+1]) = {y, c}; b of the reified
+    // items with si = x as fb[fb_ptr[q]..fb_ptr[q+1])
+    const float *fstat;
+    const int32_t *fr_ptr;
+    const int2 *fr;
+    const int32_t *fb_ptr;
+    const int32_t *fb;
 };
+
+constexpr int kNumFeat = 6;
+constexpr int kHidden = 64;
+constexpr int kNumParams = kHidden * kNumFeat + kHidden + kHidden + 1;  // 513
 
 // Per-instance search results, written by the search kernel.
 struct InstState {
@@ -97,7 +111,7 @@ struct SearchParams {
     int32_t *best_vals;         // [ninst * max_ndec]
     int32_t max_ndec;
     int32_t pad;
-    const float *mlp;           // learned branching weights (see pccp_mlp.h), may be null
+    const uint16_t *mlp;        // learned branching: bf16 parameters (513), or null
 };
 
 }  // namespace pccp

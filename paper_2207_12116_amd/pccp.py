@@ -36,7 +36,7 @@ class Config(C.Structure):
     """pccp_config; zero fields select the defaults."""
     _fields_ = [("wg_size", _I32), ("num_wgs", _I32), ("desc_lds", _I32),
                 ("root_lds", _I32), ("max_depth", _I32), ("queue_cap", _I32),
-                ("sol_cap", _I64)]
+                ("sol_cap", _I64), ("launch", _I32), ("reserved", _I32)]
 
 
 class Limits(C.Structure):
@@ -66,6 +66,9 @@ EXPORTS = [
     "pccp_propagate_batch", "pccp_solve", "pccp_batch_solve", "pccp_get_stats",
     "pccp_get_solution_count", "pccp_get_solutions", "pccp_get_best",
     "pccp_set_branching", "pccp_solver_capacity", "pccp_last_error", "pccp_version",
+    "pccp_node_features", "pccp_mlp_create", "pccp_mlp_destroy", "pccp_mlp_set_params",
+    "pccp_mlp_get_params", "pccp_mlp_train_step", "pccp_mlp_get_grads", "pccp_mlp_scores",
+    "pccp_mlp_weights",
 ]
 
 _lib = None
@@ -110,6 +113,16 @@ def lib():
         "pccp_get_best": [_VP, _P32, _P32, _I32],
         "pccp_set_branching": [_VP, _I32, _VP],
         "pccp_solver_capacity": [_VP, _P32, _P32],
+        "pccp_node_features": [_VP, _I32, _VP, _VP, _VP],
+        "pccp_mlp_create": [C.c_uint64, _VP, C.POINTER(_VP)],
+        "pccp_mlp_destroy": [_VP],
+        "pccp_mlp_set_params": [_VP, C.POINTER(C.c_float)],
+        "pccp_mlp_get_params": [_VP, C.POINTER(C.c_float)],
+        "pccp_mlp_train_step": [_VP, _VP, _VP, _VP, _I32, _I32, _I32, C.c_float,
+                                C.POINTER(C.c_float)],
+        "pccp_mlp_get_grads": [_VP, C.POINTER(C.c_float)],
+        "pccp_mlp_scores": [_VP, _VP, _I32, _VP, _I32],
+        "pccp_mlp_weights": [_VP, C.POINTER(_VP)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -270,6 +283,14 @@ class Solver:
                                       C.c_void_p(weights_ptr) if weights_ptr else None),
              "pccp_set_branching")
 
+    def node_features(self, lb, ub, out):
+        """Features of stores (int32 CUDA tensors [nbox, nvars]) into out
+        (float32 CUDA tensor [nbox, ndecision, 6])."""
+        nbox = int(lb.shape[0])
+        _chk(lib().pccp_node_features(self.h, nbox, C.c_void_p(lb.data_ptr()),
+                                      C.c_void_p(ub.data_ptr()), C.c_void_p(out.data_ptr())),
+             "pccp_node_features")
+
     def capacity(self):
         a, b = C.c_int32(0), C.c_int32(0)
         _chk(lib().pccp_solver_capacity(self.h, C.byref(a), C.byref(b)), "pccp_solver_capacity")
@@ -291,3 +312,63 @@ def batch_solve(solvers, mode=MINIMIZE, config: Config | None = None, node_limit
 
 def version() -> str:
     return lib().pccp_version().decode()
+
+
+NPARAM = 513
+
+
+class MLP:
+    """The learned branching network (pccp_mlp_*)."""
+
+    def __init__(self, seed=0, stream=None):
+        h = _VP()
+        self.stream = _current_stream() if stream is None else int(stream)
+        _chk(lib().pccp_mlp_create(C.c_uint64(seed), C.c_void_p(self.stream), C.byref(h)),
+             "pccp_mlp_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.pccp_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(NPARAM, dtype=np.float32)
+        _chk(lib().pccp_mlp_get_params(self.h, out.ctypes.data_as(C.POINTER(C.c_float))),
+             "pccp_mlp_get_params")
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.shape == (NPARAM,)
+        _chk(lib().pccp_mlp_set_params(self.h, p.ctypes.data_as(C.POINTER(C.c_float))),
+             "pccp_mlp_set_params")
+
+    def grads(self) -> np.ndarray:
+        out = np.zeros(NPARAM, dtype=np.float32)
+        _chk(lib().pccp_mlp_get_grads(self.h, out.ctypes.data_as(C.POINTER(C.c_float))),
+             "pccp_mlp_get_grads")
+        return out
+
+    def train_step(self, feat, off, target, max_cand, lr):
+        """feat float32 [C, 6], off int32 [N+1], target float32 [C] (a
+        distribution over each node's candidates): CUDA tensors."""
+        loss = C.c_float(0.0)
+        _chk(lib().pccp_mlp_train_step(
+            self.h, C.c_void_p(feat.data_ptr()), C.c_void_p(off.data_ptr()),
+            C.c_void_p(target.data_ptr()), int(off.shape[0]) - 1, int(feat.shape[0]),
+            int(max_cand), C.c_float(lr), C.byref(loss)), "pccp_mlp_train_step")
+        return float(loss.value)
+
+    def scores(self, feat, out, bf16=True):
+        _chk(lib().pccp_mlp_scores(self.h, C.c_void_p(feat.data_ptr()), int(feat.shape[0]),
+                                   C.c_void_p(out.data_ptr()), 1 if bf16 else 0),
+             "pccp_mlp_scores")
+
+    def weights_ptr(self) -> int:
+        w = _VP()
+        _chk(lib().pccp_mlp_weights(self.h, C.byref(w)), "pccp_mlp_weights")
+        return int(w.value)

@@ -1,0 +1,78 @@
+"""Launch forms of the search: hipGraph replay vs plain launches, and the
+autotuner.  A graph is replayed several times with eager work and
+synchronisation in between; every replay must equal the plain launch."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2207_12116_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2207_12116_amd import pccp
+    pccp.lib()
+    return pccp
+
+
+def counts(s):
+    st = s.stats()
+    return (st["nodes"], st["fails"], st["solutions"], st["sol_hash"], st["best"])
+
+
+def test_graph_replays_match_plain_launch(P):
+    model = I.tiny_csp(1, dom=12)
+    ref = O.solve(model)
+    plain = P.Solver(model, num_wgs=1, launch=1)
+    assert plain.solve(time_limit=60) == P.OUT_ALL
+    want = counts(plain)
+    assert want[:4] == (ref["nodes"], ref["fails"], ref["solutions"], ref["sol_hash"])
+    g = P.Solver(model, num_wgs=1, launch=0)
+    other = P.Solver(I.rcpsp(30, 1))
+    for rep in range(4):
+        print("graph replay", rep, file=sys.stderr, flush=True)
+        assert g.solve(time_limit=60) == P.OUT_ALL
+        assert counts(g) == want
+        other.propagate()        # eager work between replays
+    # multi-workgroup graph: ENUMERATE counts are schedule-free
+    gm = P.Solver(I.tiny_csp(2, dom=14), launch=0)
+    refm = O.solve(I.tiny_csp(2, dom=14))
+    for rep in range(3):
+        assert gm.solve(time_limit=60) == P.OUT_ALL
+        st = gm.stats()
+        assert (st["nodes"], st["solutions"], st["sol_hash"]) == \
+            (refm["nodes"], refm["solutions"], refm["sol_hash"])
+
+
+def test_graph_minimize_batch_replays(P):
+    models = [I.tiny_rcpsp(n, s) for n, s in [(8, 0), (10, 1), (9, 2), (12, 3)]]
+    refs = [O.solve(m)["best"] for m in models]
+    solvers = [P.Solver(m) for m in models]
+    cfg = P.Config(launch=0)
+    for rep in range(3):
+        outs = P.batch_solve(solvers, P.MINIMIZE, config=cfg, time_limit=60)
+        assert outs == [P.OUT_OPTIMAL] * 4
+        assert [s.best()[0] for s in solvers] == refs
+
+
+def test_autotune_picks_a_working_config(P, tmp_path):
+    from paper_2207_12116_amd import autotune
+    models = [I.rcpsp(30, s) for s in range(4)]
+    cfg, rep = autotune.tune(models, budget_s=0.15, cache_path=str(tmp_path / "at.json"),
+                             wg_sizes=(128, 256))
+    assert not rep["cached"] and len(rep["candidates"]) >= 4
+    assert cfg.wg_size in (128, 256)
+    cfg2, rep2 = autotune.tune(models, budget_s=0.15, cache_path=str(tmp_path / "at.json"),
+                               wg_sizes=(128, 256))
+    assert rep2["cached"] and cfg2.wg_size == cfg.wg_size
+    # the tuned configuration still finds the oracle's optimum
+    small = [I.tiny_rcpsp(10, 1)]
+    s = P.Solver(small[0], config=cfg)
+    assert s.solve(time_limit=60) == P.OUT_OPTIMAL
+    assert s.best()[0] == O.solve(small[0])["best"]
