@@ -42,6 +42,38 @@ LDS_PEAK_GBS = 256 * 128 * 2.4  # GB/s: CUs x bytes/clk/CU x GHz
 BYTES_DIFF, BYTES_REIF, BYTES_TERM = 16, 24, 8
 
 
+# HBM traffic of the search kernel from rocprofv3 counter runs (FETCH_SIZE and
+# WRITE_SIZE in separate passes), per search node, for one kernel source and
+# launch shape.  FETCH_SIZE is scaled by 2.0 and WRITE_SIZE by 1.0: what a
+# 2 GiB device copy (`--copy-calibration`) reads back as 1 GiB fetched and
+# 2 GiB written.  A run whose kernel source or shape differs reports null.
+PROFILED_TRAFFIC = [
+    {"kernel_sha256": "f93944629382ade5083d7819b38a25671f393a8fe98934eecca7174463bdd410", "block": 256, "desc_lds": 0, "root_lds": 1,
+     "fetch_bytes_per_node": 4.858, "write_bytes_per_node": 1.394,
+     "profile": "profiles/search_kernel_rcpsp30_traffic.md"},
+]
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+
+
+def kernel_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2207_12116_amd", "csrc")
+    for f in ("pccp_kernels.hip", "pccp_types.h"):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(st, nodes_per_launch):
+    sha = kernel_sha256()
+    for e in PROFILED_TRAFFIC:
+        if (e["kernel_sha256"], e["block"], e["desc_lds"], e["root_lds"]) == \
+                (sha, st["block"], st["desc_lds"], st["root_lds"]):
+            return round((e["fetch_bytes_per_node"] + e["write_bytes_per_node"]) * nodes_per_launch)
+    return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -63,6 +95,71 @@ def cpu_baseline(n, seed, nodes):
                       f"first {r['nodes']} nodes ({dt:.1f} s)"}
 
 
+def ttpo_suite(n, seeds, limit, cfg, weights):
+    """Time to proven optimum of the same instances in three forms:
+    plain (one launch per instance, whole GPU), batched (one launch for all)
+    and learned (batched, branching on the trained network).  Instance times
+    are device-clock times from launch start to proof (the limit if not
+    proven); `total_s` is the time to prove the whole set: the sum of the
+    plain launches, the duration of the batched launch."""
+    from paper_2207_12116_amd import instances as I, learn, pccp
+    models = [I.rcpsp(n, s) for s in seeds]
+    solved = (pccp.OUT_OPTIMAL, pccp.OUT_UNSAT)
+
+    def summary(times, proven, total, best):
+        g = [max(t, 1e-4) for t in times]
+        return {"proven": proven, "instances": len(times), "total_s": round(total, 4),
+                "sum_s": round(sum(times), 4),
+                "geomean_ms": round(1e3 * math.exp(sum(math.log(x) for x in g) / len(g)), 3),
+                "best": best}
+
+    times, proven, best = [], 0, []
+    for m in models:
+        s = pccp.Solver(m, config=cfg)
+        out = s.solve(pccp.MINIMIZE, time_limit=limit)
+        st = s.stats()
+        ok = out in solved
+        proven += ok
+        times.append(st["ttpo_ms"] / 1e3 if ok else limit)
+        best.append(st["best"])
+    res = {"tasks": n, "seeds": f"{seeds[0]}-{seeds[-1]}", "limit_s": limit,
+           "plain": summary(times, proven, sum(times), best)}
+    for form in ("batched", "learned"):
+        solvers = [pccp.Solver(m, config=cfg) for m in models]
+        mlp = None
+        if form == "learned":
+            if not os.path.exists(weights):
+                res[form] = None
+                continue
+            mlp = learn.network(weights)
+            for s in solvers:
+                learn.attach(s, mlp)
+        outs = pccp.batch_solve(solvers, pccp.MINIMIZE, config=cfg, time_limit=limit)
+        sts = [s.stats() for s in solvers]
+        t = [x["ttpo_ms"] / 1e3 if o in solved else limit for o, x in zip(outs, sts)]
+        pr = sum(o in solved for o in outs)
+        total = max(t) if pr == len(t) else limit
+        res[form] = summary(t, pr, total, [x["best"] for x in sts])
+    return res
+
+
+def copy_calibration(gib=2):
+    """One device-to-device copy of `gib` GiB (larger than the last-level
+    cache) through an elementwise kernel: the FETCH_SIZE / WRITE_SIZE that
+    rocprofv3 reports for it calibrate the counters' unit and overheads."""
+    import torch
+    n = gib * (1 << 30) // 4
+    src = torch.empty(n, dtype=torch.int32, device="cuda")
+    src.fill_(7)
+    dst = torch.empty_like(src)
+    flush = torch.empty(512 * (1 << 20) // 4, dtype=torch.int32, device="cuda")
+    flush.fill_(1)                      # evict src from the last-level cache
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 4, "read_bytes": n * 4, "write_bytes": n * 4}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,7 +173,21 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-nodes", type=int, default=150000)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--desc-lds", type=int, default=0, choices=(0, 1, 2),
+                    help="with --wg: descriptors 0 chosen by the library, 1 LDS, 2 global")
+    ap.add_argument("--root-lds", type=int, default=0, choices=(0, 1, 2),
+                    help="with --wg: subtree-root store 0 chosen, 1 LDS, 2 global")
+    ap.add_argument("--no-ttpo", action="store_true")
+    ap.add_argument("--ttpo-n", type=int, default=18)
+    ap.add_argument("--ttpo-seeds", type=int, default=16)
+    ap.add_argument("--ttpo-limit", type=float, default=2.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a 2 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -101,7 +212,7 @@ def main():
                  "candidates": len(rep["candidates"])}
         log(f"autotuned: {tuned}")
     else:
-        cfg = pccp.Config(wg_size=args.wg)
+        cfg = pccp.Config(wg_size=args.wg, desc_lds=args.desc_lds, root_lds=args.root_lds)
     solvers = [pccp.Solver(m, config=cfg) for m in models]
 
     def step():
@@ -141,9 +252,11 @@ def main():
     kernel_s = tot_kernel_ms / 1e3
     achieved = tot_bytes / kernel_s / 1e9 if kernel_s > 0 else 0.0
     roofline = {"bound": "lds", "achieved": round(achieved, 1), "peak": LDS_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBS, 4),
+                "traffic": profiled_traffic(sts[0], tot_nodes / args.steps),
                 "kernel": "search_kernel", "kernel_ms_avg": round(tot_kernel_ms / args.steps, 3),
-                "bytes_per_launch": tot_bytes // args.steps}
+                "bytes_per_launch": tot_bytes // args.steps,
+                "nodes_per_launch": tot_nodes // args.steps}
 
     plain = None
     if not args.no_plain:
@@ -156,6 +269,14 @@ def main():
                  "outcome": pccp.OUTCOME_NAMES[out], "best": st["best"],
                  "grid": st["grid"], "time_s": round(dtp, 3)}
         log(f"plain: {plain}")
+
+    ttpo_cmp = None
+    if not args.no_ttpo:
+        from paper_2207_12116_amd import learn
+        log(f"time to proven optimum: {args.ttpo_seeds} instances of {args.ttpo_n} tasks")
+        ttpo_cmp = ttpo_suite(args.ttpo_n, list(range(args.ttpo_seeds)), args.ttpo_limit, cfg,
+                              learn.DEFAULT_WEIGHTS)
+        log(f"ttpo: {json.dumps({k: v for k, v in ttpo_cmp.items()})}")
 
     cpu = None
     if not args.no_cpu:
@@ -178,6 +299,7 @@ def main():
                    "autotuned": tuned, "launch": "hipGraph"},
         "propagations_per_s": round(tot_props / wall, 1),
         "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "ttpo": ttpo,
+        "ttpo_forms": ttpo_cmp,
     }
     print(json.dumps(line), flush=True)
 

@@ -583,7 +583,7 @@ static int32_t choose_shape(pccp_solver *const *sv, int n, const pccp_config &cf
         const size_t lds = search_lds_bytes(max_vars, cfg.max_depth, max_desc, cd.d, cd.r, feat_ndec);
         if (lds > lds_max) continue;
         int occ = 0;
-        hipError_t e = search_occupancy(sh.block, lds, cd.d, cd.r, &occ);
+        hipError_t e = search_occupancy(sh.block, lds, cd.d, cd.r, feat_ndec > 0, &occ);
         if (e != hipSuccess) return fail(PCCP_E_DEVICE, std::string("occupancy: ") + hipGetErrorString(e));
         if (occ > best_occ) {  // candidates are in order of preference
             best_occ = occ;

@@ -270,25 +270,41 @@ __device__ __forceinline__ void sweep_diff(const View<DL> &v, int32_t *lb, int32
             lbx[u] = lds_ld(&lb[x]); ubx[u] = lds_ld(&ub[x]);
             lby[u] = lds_ld(&lb[y]); uby[u] = lds_ld(&ub[y]);
         }
+        bool pu[U], pl[U], any = false;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (!ok[u]) continue;
-            const int x = e[u].x & 0xffff, y = (uint32_t)e[u].x >> 16, c = e[u].y;
-            const int nu = c + uby[u];
-            if (nu < ubx[u]) { join_ub(&ub[x], nu); chg = true; bad |= nu < lbx[u]; }
-            const int nl = lbx[u] - c;
-            if (nl > lby[u]) { join_lb(&lb[y], nl); chg = true; bad |= nl > uby[u]; }
+            const int c = e[u].y;
+            pu[u] = ok[u] && c + uby[u] < ubx[u];
+            pl[u] = ok[u] && lbx[u] - c > lby[u];
+            any |= pu[u] | pl[u];
+        }
+        if (any) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int x = e[u].x & 0xffff, y = (uint32_t)e[u].x >> 16, c = e[u].y;
+                const int nu = c + uby[u], nl = lbx[u] - c;
+                if (pu[u]) { join_ub(&ub[x], nu); chg = true; bad |= nu < lbx[u]; }
+                if (pl[u]) { join_lb(&lb[y], nl); chg = true; bad |= nl > uby[u]; }
+            }
         }
     }
 }
 
 // kind 2: b <=> (si <= sj and sj < si + d): the four guarded processes of
-// [[phi <=> psi]] with interval entailment (see pccp.h)
+// [[phi <=> psi]] with interval entailment (see pccp.h).  The guarded
+// tells on the start variables are merged per bound: each of ub(si),
+// lb(sj), ub(sj), lb(si) gets the tightest value any enabled guard tells,
+//   b true  : ub(si) <= ub(sj),    lb(sj) >= lb(si),
+//             ub(sj) <= ub(si)+d-1, lb(si) >= lb(sj)-d+1
+//   b false, si <= sj entailed   : lb(sj) >= lb(si)+d, ub(si) <= ub(sj)-d
+//   b false, sj < si+d entailed  : ub(sj) <= ub(si)-1, lb(si) >= lb(sj)+1
+// and is told only if that value is tighter than the bound read.
 template <bool DL>
 __device__ __forceinline__ void sweep_reif(const View<DL> &v, int32_t *lb, int32_t *ub,
                                            bool &chg, bool &bad)
 {
     constexpr int U = 4;
+    constexpr int BIG = 0x3fffffff;
     const int tid = threadIdx.x, W = blockDim.x, n = v.nreif;
     for (int base = tid; base < n; base += U * W) {
         int2 e[U];
@@ -309,54 +325,52 @@ __device__ __forceinline__ void sweep_reif(const View<DL> &v, int32_t *lb, int32
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int b = e[u].x & 0xffff, i = (uint32_t)e[u].x >> 16;
-            const int j = e[u].y & 0xffff, d = e[u].y >> 16;
+            const int d = e[u].y >> 16;
             const bool E1 = ubi[u] <= lbj[u];            // entailed(si <= sj)
             const bool E2 = ubj[u] <= lbi[u] + d - 1;    // entailed(sj < si + d)
-            const bool t_b1 = lbb[u] < 1 && E1 && E2;
-            const bool t_b0 = ubb[u] > 0 && (lbi[u] > ubj[u] || lbj[u] >= ubi[u] + d);
-            const bool on = lbb[u] >= 1;                 // b  => si <= sj <= si + d - 1
-            const bool off = ubb[u] <= 0;                // !b => sj < si or sj >= si + d
-            const int u1 = ubj[u], l1 = lbi[u], u2 = ubi[u] + d - 1, l2 = lbj[u] - d + 1;
-            const int l3 = lbi[u] + d, u3 = ubj[u] - d, u4 = ubi[u] - 1, l4 = lbj[u] + 1;
-            const bool p1 = on && u1 < ubi[u], p2 = on && l1 > lbj[u];
-            const bool p3 = on && u2 < ubj[u], p4 = on && l2 > lbi[u];
-            const bool p5 = off && E1 && l3 > lbj[u], p6 = off && E1 && u3 < ubi[u];
-            const bool p7 = off && E2 && u4 < ubj[u], p8 = off && E2 && l4 > lbi[u];
-            if (!ok[u] || !(t_b1 | t_b0 | p1 | p2 | p3 | p4 | p5 | p6 | p7 | p8))
+            const bool on = lbb[u] >= 1, off = ubb[u] <= 0;
+            const bool t_b1 = !on && E1 && E2;           // psi entailed: b >= 1
+            const bool t_b0 = !off && (lbi[u] > ubj[u] || lbj[u] >= ubi[u] + d);  // not psi: b <= 0
+            const bool o1 = off && E1, o2 = off && E2;
+            const int nui = min(on ? ubj[u] : BIG, o1 ? ubj[u] - d : BIG);
+            const int nlj = max(on ? lbi[u] : -BIG, o1 ? lbi[u] + d : -BIG);
+            const int nuj = min(on ? ubi[u] + d - 1 : BIG, o2 ? ubi[u] - 1 : BIG);
+            const int nli = max(on ? lbj[u] - d + 1 : -BIG, o2 ? lbj[u] + 1 : -BIG);
+            const bool p_ui = nui < ubi[u], p_lj = nlj > lbj[u];
+            const bool p_uj = nuj < ubj[u], p_li = nli > lbi[u];
+            if (!ok[u] || !(t_b1 | t_b0 | p_ui | p_lj | p_uj | p_li))
                 continue;
+            const int b = e[u].x & 0xffff, i = (uint32_t)e[u].x >> 16, j = e[u].y & 0xffff;
             chg = true;
             if (t_b1) { join_lb(&lb[b], 1); bad |= ubb[u] < 1; }
             if (t_b0) { join_ub(&ub[b], 0); bad |= lbb[u] > 0; }
-            if (p1) { join_ub(&ub[i], u1); bad |= u1 < lbi[u]; }
-            if (p2) { join_lb(&lb[j], l1); bad |= l1 > ubj[u]; }
-            if (p3) { join_ub(&ub[j], u2); bad |= u2 < lbj[u]; }
-            if (p4) { join_lb(&lb[i], l2); bad |= l2 > ubi[u]; }
-            if (p5) { join_lb(&lb[j], l3); bad |= l3 > ubj[u]; }
-            if (p6) { join_ub(&ub[i], u3); bad |= u3 < lbi[u]; }
-            if (p7) { join_ub(&ub[j], u4); bad |= u4 < lbj[u]; }
-            if (p8) { join_lb(&lb[i], l4); bad |= l4 > ubi[u]; }
+            if (p_ui) { join_ub(&ub[i], nui); bad |= nui < lbi[u]; }
+            if (p_lj) { join_lb(&lb[j], nlj); bad |= nlj > ubj[u]; }
+            if (p_uj) { join_ub(&ub[j], nuj); bad |= nuj < lbj[u]; }
+            if (p_li) { join_lb(&lb[i], nli); bad |= nli > ubi[u]; }
         }
     }
 }
 
 // One term's tell of  a x <= rr  (rr = rhs - (S - m_t)) given the bounds the
-// lane read for x.
+// lane read for x: is it tighter, and the new bound.  Division only for
+// |a| > 1 (floor toward -inf for a > 0, ceil toward +inf for a < 0).
+__device__ __forceinline__ bool term_tight(int a, int lbx, int ubx, int rhs, int S)
+{
+    return a > 0 ? rhs - (S - a * lbx) < a * ubx : rhs - (S - a * ubx) < a * lbx;
+}
+
 __device__ __forceinline__ void term_tell(int32_t *lb, int32_t *ub, int x, int a, int lbx, int ubx,
                                           int rhs, int S, bool &chg, bool &bad)
 {
     if (a > 0) {
-        const int rr = rhs - (S - a * lbx);
-        if (rr < a * ubx) {
-            const int nb = a == 1 ? rr : floor_div_pos(rr, a);
-            join_ub(&ub[x], nb); chg = true; bad |= nb < lbx;
-        }
+        const int rr = rhs - (S - a * lbx);                 // a x <= rr
+        const int nb = a == 1 ? rr : floor_div_pos(rr, a);
+        join_ub(&ub[x], nb); chg = true; bad |= nb < lbx;
     } else {
-        const int rr = rhs - (S - a * ubx);
-        if (rr < a * lbx) {                          // x >= ceil(rr / a)
-            const int nb = a == -1 ? -rr : -floor_div_pos(rr, -a);
-            join_lb(&lb[x], nb); chg = true; bad |= nb > ubx;
-        }
+        const int rr = rhs - (S - a * ubx);                 // x >= ceil(rr / a)
+        const int nb = a == -1 ? -rr : -floor_div_pos(rr, -a);
+        join_lb(&lb[x], nb); chg = true; bad |= nb > ubx;
     }
 }
 
@@ -415,13 +429,24 @@ __device__ __forceinline__ void sweep_rows(const View<DL> &v, int32_t *lb, int32
                 }
                 S[q] = group_sum(part, G);
             }
+            bool tight[RR][TK], any = false;
 #pragma unroll
             for (int q = 0; q < RR; ++q)
 #pragma unroll
-                for (int k = 0; k < TK; ++k)
-                    if (tok[q][k])
-                        term_tell(lb, ub, tv[q][k] & 0xffff, (int32_t)tv[q][k] >> 16, tl[q][k],
-                                  tu[q][k], rd[q].z, S[q], chg, bad);
+                for (int k = 0; k < TK; ++k) {
+                    tight[q][k] = tok[q][k] && term_tight((int32_t)tv[q][k] >> 16, tl[q][k],
+                                                          tu[q][k], rd[q].z, S[q]);
+                    any |= tight[q][k];
+                }
+            if (any) {
+#pragma unroll
+                for (int q = 0; q < RR; ++q)
+#pragma unroll
+                    for (int k = 0; k < TK; ++k)
+                        if (tight[q][k])
+                            term_tell(lb, ub, tv[q][k] & 0xffff, (int32_t)tv[q][k] >> 16,
+                                      tl[q][k], tu[q][k], rd[q].z, S[q], chg, bad);
+            }
         } else {
             // long rows: sum chunk by chunk, then tell chunk by chunk
             int S[RR];
@@ -449,8 +474,9 @@ __device__ __forceinline__ void sweep_rows(const View<DL> &v, int32_t *lb, int32
                         const int x = t & 0xffff, a = (int32_t)t >> 16;
                         // a bound re-read here can only have tightened since S
                         // was formed: the tell is then weaker, never unsound
-                        term_tell(lb, ub, x, a, lds_ld(&lb[x]), lds_ld(&ub[x]), rd[q].z, S[q],
-                                  chg, bad);
+                        const int lbx = lds_ld(&lb[x]), ubx = lds_ld(&ub[x]);
+                        if (term_tight(a, lbx, ubx, rd[q].z, S[q]))
+                            term_tell(lb, ub, x, a, lbx, ubx, rd[q].z, S[q], chg, bad);
                     }
                 }
             }
@@ -587,7 +613,7 @@ __device__ __forceinline__ unsigned long long score_key(float s, int q)
 template <bool DL>
 __device__ void post_scan(const View<DL> &v, const int32_t *lb, const int32_t *ub, int32_t *ctl,
                           int branching, bool branch, float *fsc = nullptr,
-                          const MlpLane *ml = nullptr)
+                          const uint16_t *mlp = nullptr)
 {
     const int tid = threadIdx.x, W = blockDim.x, lane = tid & 63;
     bool bad = false;
@@ -614,13 +640,14 @@ __device__ void post_scan(const View<DL> &v, const int32_t *lb, const int32_t *u
         }
         lds_barrier();
         // ... then one wave per candidate, one lane per hidden unit
+        const MlpLane ml = load_mlp_lane(mlp);
         const int wid = tid >> 6, nw = W >> 6;
         for (int q = wid; q < v.ndec; q += nw) {
             if (fsc[8 * q + 6] == 0.f) continue;
-            float z = ml->b1;
+            float z = ml.b1;
 #pragma unroll
-            for (int k = 0; k < kNumFeat; ++k) z = fmaf(ml->w1[k], fsc[8 * q + k], z);
-            const float sc = wave_sum_f(ml->w2 * fmaxf(z, 0.f));
+            for (int k = 0; k < kNumFeat; ++k) z = fmaf(ml.w1[k], fsc[8 * q + k], z);
+            const float sc = wave_sum_f(ml.w2 * fmaxf(z, 0.f));
             const unsigned long long k2 = score_key(sc, q);
             key = k2 < key ? k2 : key;
         }
@@ -873,7 +900,7 @@ __device__ void flush_counters(Lane0 &z, InstState *is, int mode)
 
 // Persistent kernel: every workgroup loops { take a subtree record; DFS it }
 // until the queue is empty and no subtree is in progress, or a limit hits.
-template <bool DL, bool RL>
+template <bool DL, bool RL, bool LEARN>
 __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
 {
     extern __shared__ __align__(16) char smem[];
@@ -895,11 +922,10 @@ __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
         after = reinterpret_cast<char *>(ub + Vp);
     }
     int2 *stack = reinterpret_cast<int2 *>(after);
-    const bool learned = P.branching == 2 && P.mlp != nullptr;
+    const bool learned = LEARN;   // the host picks this variant only with weights
     float *fsc = reinterpret_cast<float *>(reinterpret_cast<char *>(after) +
                                            align16(sizeof(int2) * (size_t)P.max_depth));
     char *dsc = reinterpret_cast<char *>(fsc) + (learned ? align16(32 * (size_t)P.max_ndec) : 0);
-    const MlpLane ml = load_mlp_lane(learned ? P.mlp : nullptr);
     const int branching = learned ? 2 : (P.branching == 1 ? 1 : 0);
 
     if (tid == 0) {
@@ -1013,7 +1039,7 @@ __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
                 break;
             uint32_t nsw = 0;
             const int st = propagate_wg(v, lb, ub, ctl, nsw);
-            post_scan(v, lb, ub, ctl, branching, st == 0, fsc, &ml);
+            post_scan(v, lb, ub, ctl, branching, st == 0, fsc, P.mlp);
             const int failed = uni(st | lds_ld(&ctl[C_POSTFAIL]));
             const unsigned long long key =
                 *reinterpret_cast<volatile unsigned long long *>(ctl + C_KEY);
@@ -1465,6 +1491,23 @@ hipError_t launch_propagate_batch(const DevModel *m_dev, int nbox, const int32_t
     return hipGetLastError();
 }
 
+// the search kernel variant for a layout and branching rule
+static const void *search_fn(bool desc_lds, bool root_lds, bool learned)
+{
+#define PCCP_FN(a, b, c) reinterpret_cast<const void *>(search_kernel<a, b, c>)
+    if (learned) {
+        if (desc_lds && root_lds) return PCCP_FN(true, true, true);
+        if (desc_lds) return PCCP_FN(true, false, true);
+        if (root_lds) return PCCP_FN(false, true, true);
+        return PCCP_FN(false, false, true);
+    }
+    if (desc_lds && root_lds) return PCCP_FN(true, true, false);
+    if (desc_lds) return PCCP_FN(true, false, false);
+    if (root_lds) return PCCP_FN(false, true, false);
+    return PCCP_FN(false, false, false);
+#undef PCCP_FN
+}
+
 hipError_t launch_search(const SearchParams &P, int grid, int block, size_t lds, bool desc_lds,
                          bool root_lds, hipStream_t stream)
 {
@@ -1472,17 +1515,13 @@ hipError_t launch_search(const SearchParams &P, int grid, int block, size_t lds,
     hipLaunchKernelGGL(init_search_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, P);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-#define PCCP_LAUNCH(DLV, RLV)                                                                  \
-    do {                                                                                       \
-        e = set_lds_limit(search_kernel<DLV, RLV>, lds);                                       \
-        if (e != hipSuccess) return e;                                                         \
-        hipLaunchKernelGGL((search_kernel<DLV, RLV>), dim3(grid), dim3(block), lds, stream, P); \
-    } while (0)
-    if (desc_lds && root_lds) PCCP_LAUNCH(true, true);
-    else if (desc_lds) PCCP_LAUNCH(true, false);
-    else if (root_lds) PCCP_LAUNCH(false, true);
-    else PCCP_LAUNCH(false, false);
-#undef PCCP_LAUNCH
+    const void *fn = search_fn(desc_lds, root_lds, P.branching == 2 && P.mlp != nullptr);
+    e = set_lds_limit(fn, lds);
+    if (e != hipSuccess) return e;
+    SearchParams p = P;
+    void *args[] = {&p};
+    e = hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
@@ -1491,11 +1530,7 @@ hipError_t launch_search(const SearchParams &P, int grid, int block, size_t lds,
 hipError_t build_search_graph(const SearchParams &P, int grid, int block, size_t lds,
                               bool desc_lds, bool root_lds, hipGraphExec_t *exec)
 {
-    const void *fn;
-    if (desc_lds && root_lds) fn = reinterpret_cast<const void *>(search_kernel<true, true>);
-    else if (desc_lds) fn = reinterpret_cast<const void *>(search_kernel<true, false>);
-    else if (root_lds) fn = reinterpret_cast<const void *>(search_kernel<false, true>);
-    else fn = reinterpret_cast<const void *>(search_kernel<false, false>);
+    const void *fn = search_fn(desc_lds, root_lds, P.branching == 2 && P.mlp != nullptr);
     hipError_t e = set_lds_limit(fn, lds);
     if (e != hipSuccess) return e;
     hipGraph_t g = nullptr;
@@ -1525,22 +1560,13 @@ hipError_t build_search_graph(const SearchParams &P, int grid, int block, size_t
     return e;
 }
 
-hipError_t search_occupancy(int block, size_t lds, bool desc_lds, bool root_lds, int *wgs_per_cu)
+hipError_t search_occupancy(int block, size_t lds, bool desc_lds, bool root_lds, bool learned,
+                            int *wgs_per_cu)
 {
-    hipError_t e;
-#define PCCP_OCC(DLV, RLV)                                                                     \
-    do {                                                                                       \
-        e = set_lds_limit(search_kernel<DLV, RLV>, lds);                                       \
-        if (e != hipSuccess) return e;                                                         \
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, search_kernel<DLV, RLV>,  \
-                                                         block, lds);                          \
-    } while (0)
-    if (desc_lds && root_lds) PCCP_OCC(true, true);
-    else if (desc_lds) PCCP_OCC(true, false);
-    else if (root_lds) PCCP_OCC(false, true);
-    else PCCP_OCC(false, false);
-#undef PCCP_OCC
-    return e;
+    const void *fn = search_fn(desc_lds, root_lds, learned);
+    hipError_t e = set_lds_limit(fn, lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, fn, block, lds);
 }
 
 }  // namespace pccp

@@ -36,6 +36,7 @@ hipError_t launch_mlp_sync_bf16(const float *params, uint16_t *wbf, hipStream_t 
 hipError_t launch_mlp_scores(const float *params, const uint16_t *wbf, int use_bf16,
                              const float *feat, int ncand, float *scores, hipStream_t stream);
 
-hipError_t search_occupancy(int block, size_t lds, bool desc_lds, bool root_lds, int *wgs_per_cu);
+hipError_t search_occupancy(int block, size_t lds, bool desc_lds, bool root_lds, bool learned,
+                            int *wgs_per_cu);
 
 }  // namespace pccp
