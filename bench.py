@@ -48,7 +48,8 @@ BYTES_DIFF, BYTES_REIF, BYTES_TERM = 16, 24, 8
 # 2 GiB device copy (`--copy-calibration`) reads back as 1 GiB fetched and
 # 2 GiB written.  A run whose kernel source or shape differs reports null.
 PROFILED_TRAFFIC = [
-    {"kernel_sha256": "f93944629382ade5083d7819b38a25671f393a8fe98934eecca7174463bdd410", "block": 256, "desc_lds": 0, "root_lds": 1,
+    {"kernel_sha256": "f93944629382ade5083d7819b38a25671f393a8fe98934eecca7174463bdd410",
+     "block": 256, "desc_lds": 0, "root_lds": 1, "live": 0,
      "fetch_bytes_per_node": 4.858, "write_bytes_per_node": 1.394,
      "profile": "profiles/search_kernel_rcpsp30_traffic.md"},
 ]
@@ -68,8 +69,8 @@ def kernel_sha256():
 def profiled_traffic(st, nodes_per_launch):
     sha = kernel_sha256()
     for e in PROFILED_TRAFFIC:
-        if (e["kernel_sha256"], e["block"], e["desc_lds"], e["root_lds"]) == \
-                (sha, st["block"], st["desc_lds"], st["root_lds"]):
+        if (e["kernel_sha256"], e["block"], e["desc_lds"], e["root_lds"], e["live"]) == \
+                (sha, st["block"], st["desc_lds"], st["root_lds"], st["live"]):
             return round((e["fetch_bytes_per_node"] + e["write_bytes_per_node"]) * nodes_per_launch)
     return None
 
@@ -177,6 +178,10 @@ def main():
                     help="with --wg: descriptors 0 chosen by the library, 1 LDS, 2 global")
     ap.add_argument("--root-lds", type=int, default=0, choices=(0, 1, 2),
                     help="with --wg: subtree-root store 0 chosen, 1 LDS, 2 global")
+    ap.add_argument("--live", type=int, default=0, choices=(0, 1, 2),
+                    help="with --wg: item lists 0 chosen, 1 on, 2 off")
+    ap.add_argument("--max-depth", type=int, default=0,
+                    help="decision-stack capacity per workgroup (0 = library default)")
     ap.add_argument("--no-ttpo", action="store_true")
     ap.add_argument("--ttpo-n", type=int, default=18)
     ap.add_argument("--ttpo-seeds", type=int, default=16)
@@ -209,10 +214,11 @@ def main():
         from paper_2207_12116_amd import autotune
         cfg, rep = autotune.tune(models, pccp.MINIMIZE, budget_s=0.4, cache_path=None, log=log)
         tuned = {"wg_size": cfg.wg_size, "desc_lds": cfg.desc_lds, "root_lds": cfg.root_lds,
-                 "candidates": len(rep["candidates"])}
+                 "live": cfg.live, "candidates": len(rep["candidates"])}
         log(f"autotuned: {tuned}")
     else:
-        cfg = pccp.Config(wg_size=args.wg, desc_lds=args.desc_lds, root_lds=args.root_lds)
+        cfg = pccp.Config(wg_size=args.wg, desc_lds=args.desc_lds, root_lds=args.root_lds,
+                          live=args.live, max_depth=args.max_depth)
     solvers = [pccp.Solver(m, config=cfg) for m in models]
 
     def step():
@@ -296,6 +302,7 @@ def main():
                    "step_time_limit_s": args.step_time,
                    "grid": sts[0]["grid"], "block": sts[0]["block"],
                    "desc_lds": sts[0]["desc_lds"], "root_lds": sts[0]["root_lds"],
+                   "live": sts[0]["live"],
                    "autotuned": tuned, "launch": "hipGraph"},
         "propagations_per_s": round(tot_props / wall, 1),
         "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "ttpo": ttpo,

@@ -150,7 +150,13 @@ typedef struct {
     int32_t launch;       /* 0 = one hipGraph (initialisation + search
                              kernels, re-used while the launch parameters are
                              unchanged), 1 = two plain kernel launches        */
-    int32_t reserved;
+    int32_t live;         /* item lists: 1 = on; 0 (default) or 2 = off.  On: a
+                             propagator found entailed at a node (no tell of
+                             it can tighten that store or any tighter one) is
+                             left out of the sweeps below that node; fixed
+                             points, and so the search tree, are unchanged
+                             (Theorem 2 of section 3); the lists take three
+                             LDS buffers of 2 bytes per propagator          */
 } pccp_config;
 
 /* Validate the model, compile it to packed per-kind propagator tables and
@@ -244,6 +250,8 @@ typedef struct {
                                  finished; -1 if not finished                 */
     int32_t grid, block, desc_lds, root_lds;
     int64_t lds_bytes;
+    int32_t live;             /* the search kept item lists                   */
+    int32_t reserved;
 } pccp_stats;
 
 int32_t pccp_get_stats(const pccp_solver *s, pccp_stats *st);

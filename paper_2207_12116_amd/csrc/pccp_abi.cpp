@@ -131,6 +131,11 @@ struct Compiled {
     std::vector<int2> diff, reif;
     std::vector<int4> rows;
     std::vector<uint32_t> terms;
+    // Boolean knapsack rows: {rhs, len} and terms at a fixed stride of
+    // bgroup * bchunks slots per row (unused slots 0)
+    std::vector<int2> brows;
+    std::vector<uint32_t> bterms;
+    int32_t bgroup = 4, bchunks = 1, nbterms = 0;
     // learned-branching tables (see pccp_types.h)
     std::vector<float> fstat;
     std::vector<int32_t> fr_ptr, fb_ptr, fb;
@@ -244,10 +249,16 @@ static int32_t compile_model(const pccp_model *m, Compiled &c)
         const bool is_diff = (a1 - a0 == 2) &&
                              ((m->coef[a0] == 1 && m->coef[a0 + 1] == -1) ||
                               (m->coef[a0] == -1 && m->coef[a0 + 1] == 1));
+        bool is_bool = !is_diff && a1 > a0;
+        for (int32_t t = a0; t < a1 && is_bool; ++t)
+            is_bool = m->coef[t] > 0 && m->lb[m->var[t]] >= 0 && m->ub[m->var[t]] <= 1;
         if (is_diff) {
             const int32_t x = m->coef[a0] == 1 ? m->var[a0] : m->var[a0 + 1];
             const int32_t y = m->coef[a0] == 1 ? m->var[a0 + 1] : m->var[a0];
             c.diff.push_back(make_int2((int32_t)((uint32_t)x | ((uint32_t)y << 16)), m->rhs[r]));
+        } else if (is_bool) {
+            // laid out below, once the longest row is known
+            c.brows.push_back(make_int2(m->rhs[r], r));
         } else {
             c.rows.push_back(make_int4((int32_t)c.terms.size(), a1 - a0, m->rhs[r], 0));
             for (int32_t t = a0; t < a1; ++t) {
@@ -256,6 +267,33 @@ static int32_t compile_model(const pccp_model *m, Compiled &c)
                     return fail(PCCP_E_UNSUPPORTED, "row " + std::to_string(r) + ": coefficient outside int16");
                 c.terms.push_back((uint32_t)m->var[t] | ((uint32_t)(uint16_t)(int16_t)a << 16));
             }
+        }
+    }
+    // Boolean rows: the smallest group (4, 8, 16 lanes) that covers the
+    // longest row in at most 4 terms per lane, else 16 lanes
+    {
+        int lmax = 1;
+        for (const int2 &b : c.brows) {
+            const int32_t r = b.y;
+            lmax = std::max(lmax, m->row_ptr[r + 1] - m->row_ptr[r]);
+        }
+        c.bgroup = 16;
+        for (int g : {4, 8, 16})
+            if ((lmax + g - 1) / g <= 4) { c.bgroup = g; break; }
+        c.bchunks = (lmax + c.bgroup - 1) / c.bgroup;
+        const size_t SL = (size_t)c.bgroup * c.bchunks;
+        c.bterms.assign(SL * c.brows.size(), 0u);
+        c.nbterms = 0;
+        for (size_t i = 0; i < c.brows.size(); ++i) {
+            const int32_t r = c.brows[i].y, a0 = m->row_ptr[r], a1 = m->row_ptr[r + 1];
+            for (int32_t t = a0; t < a1; ++t) {
+                const int32_t a = m->coef[t];
+                if (a > 32767)
+                    return fail(PCCP_E_UNSUPPORTED, "row " + std::to_string(r) + ": coefficient outside int16");
+                c.bterms[SL * i + (t - a0)] = (uint32_t)m->var[t] | ((uint32_t)a << 16);
+            }
+            c.brows[i].y = a1 - a0;
+            c.nbterms += a1 - a0;
         }
     }
     const size_t Q = m->reif.size() / 4;
@@ -358,7 +396,8 @@ static int32_t check_cfg(const pccp_config &cfg)
     if (cfg.launch < 0 || cfg.launch > 1)
         return fail(PCCP_E_INVALID_ARG, "launch must be 0 (graph) or 1 (plain)");
     if (cfg.num_wgs < 0 || cfg.queue_cap < 0 || cfg.desc_lds < 0 || cfg.desc_lds > 2 ||
-        cfg.root_lds < 0 || cfg.root_lds > 2 || cfg.max_depth > (1 << 16))
+        cfg.root_lds < 0 || cfg.root_lds > 2 || cfg.max_depth > (1 << 16) || cfg.live < 0 ||
+        cfg.live > 2)
         return fail(PCCP_E_INVALID_ARG, "bad config field");
     return PCCP_OK;
 }
@@ -385,7 +424,8 @@ extern "C" int32_t pccp_solver_create(const pccp_model *m, const pccp_config *cf
     s->lds_max = prop.sharedMemPerBlock;
     const Compiled &c = s->c;
     s->desc_bytes = model_desc_bytes((int)c.diff.size(), (int)c.reif.size(), (int)c.rows.size(),
-                                     (int)c.terms.size(), c.ndec);
+                                     (int)c.terms.size(), c.ndec, (int)c.brows.size(),
+                                     (int)c.bterms.size());
     if (propagate_lds_bytes(c.nvars, 0, false) > s->lds_max) {
         delete s;
         return fail(PCCP_E_LDS_CAPACITY, "the store (8 bytes per variable) does not fit in LDS");
@@ -398,7 +438,9 @@ extern "C" int32_t pccp_solver_create(const pccp_model *m, const pccp_config *cf
     const size_t o_rows = o_reif + al(8 * c.reif.size());
     const size_t o_terms = o_rows + al(16 * c.rows.size());
     const size_t o_dec = o_terms + al(4 * c.terms.size());
-    const size_t o_fstat = o_dec + al(4 * (size_t)c.ndec);
+    const size_t o_brows = o_dec + al(4 * (size_t)c.ndec);
+    const size_t o_bterms = o_brows + al(8 * c.brows.size());
+    const size_t o_fstat = o_bterms + al(4 * c.bterms.size());
     const size_t o_frp = o_fstat + al(4 * c.fstat.size());
     const size_t o_fr = o_frp + al(4 * c.fr_ptr.size());
     const size_t o_fbp = o_fr + al(8 * c.fr.size());
@@ -417,6 +459,8 @@ extern "C" int32_t pccp_solver_create(const pccp_model *m, const pccp_config *cf
     put(o_rows, c.rows.data(), 16 * c.rows.size());
     put(o_terms, c.terms.data(), 4 * c.terms.size());
     put(o_dec, c.dec.data(), 4 * (size_t)c.ndec);
+    put(o_brows, c.brows.data(), 8 * c.brows.size());
+    put(o_bterms, c.bterms.data(), 4 * c.bterms.size());
     put(o_fstat, c.fstat.data(), 4 * c.fstat.size());
     put(o_frp, c.fr_ptr.data(), 4 * c.fr_ptr.size());
     put(o_fr, c.fr.data(), 8 * c.fr.size());
@@ -438,6 +482,13 @@ extern "C" int32_t pccp_solver_create(const pccp_model *m, const pccp_config *cf
     for (int g : {4, 8, 16})
         if ((lmax + g - 1) / g <= 2) { dm.row_group = g; break; }
     dm.row_chunks = (lmax + dm.row_group - 1) / dm.row_group;
+    dm.nbrows = (int32_t)c.brows.size();
+    dm.bgroup = c.bgroup;
+    dm.bchunks = c.bchunks;
+    dm.nbterms = c.nbterms;
+    dm.pad0 = 0;
+    dm.brows = reinterpret_cast<const int2 *>(base + o_brows);
+    dm.bterms = reinterpret_cast<const uint32_t *>(base + o_bterms);
     dm.lb0 = reinterpret_cast<const int32_t *>(base + o_lb);
     dm.ub0 = reinterpret_cast<const int32_t *>(base + o_ub);
     dm.diff = reinterpret_cast<const int2 *>(base + o_diff);
@@ -565,38 +616,56 @@ extern "C" int32_t pccp_get_domains(pccp_solver *s, int32_t *lb, int32_t *ub, in
 // ------------------------------------------------------------------ search
 struct LaunchShape {
     int block = 256, grid = 1, wgs_per_cu = 1;
-    bool desc_lds = false, root_lds = false;
+    SearchShape k;
     size_t lds = 0;
 };
 
-static int32_t choose_shape(pccp_solver *const *sv, int n, const pccp_config &cfg, int max_vars,
-                            size_t max_desc, int num_cus, size_t lds_max, LaunchShape &sh,
+// Launch shape of a search: the kernel variant (descriptor tables and
+// subtree-root store in LDS or global memory) with the most resident
+// workgroups.  Item lists are used only when asked for (cfg.live == 1): on
+// the workloads measured they cut propagator executions by half but cost
+// more time per node than they save, so the default leaves them to the
+// autotuner.
+static int32_t choose_shape(const pccp_config &cfg, int max_vars, size_t max_desc, int list_items,
+                            bool lists_ok, int num_cus, size_t lds_max, LaunchShape &sh,
                             int feat_ndec = 0)
 {
     sh.block = cfg.wg_size;
     struct Cand { bool d, r; };
     const Cand cands[4] = {{true, true}, {false, true}, {true, false}, {false, false}};
-    int best_occ = -1;
-    for (const Cand &cd : cands) {
-        if (cfg.desc_lds != 0 && cd.d != (cfg.desc_lds == 1)) continue;
-        if (cfg.root_lds != 0 && cd.r != (cfg.root_lds == 1)) continue;
-        const size_t lds = search_lds_bytes(max_vars, cfg.max_depth, max_desc, cd.d, cd.r, feat_ndec);
-        if (lds > lds_max) continue;
-        int occ = 0;
-        hipError_t e = search_occupancy(sh.block, lds, cd.d, cd.r, feat_ndec > 0, &occ);
-        if (e != hipSuccess) return fail(PCCP_E_DEVICE, std::string("occupancy: ") + hipGetErrorString(e));
-        if (occ > best_occ) {  // candidates are in order of preference
-            best_occ = occ;
-            sh.desc_lds = cd.d;
-            sh.root_lds = cd.r;
-            sh.lds = lds;
+    int best_occ[2] = {-1, -1};
+    LaunchShape best[2];
+    for (int live = 0; live < 2; ++live) {
+        if ((cfg.live == 1) != (live == 1)) continue;
+        if (live && !lists_ok) continue;
+        for (const Cand &cd : cands) {
+            if (cfg.desc_lds != 0 && cd.d != (cfg.desc_lds == 1)) continue;
+            if (cfg.root_lds != 0 && cd.r != (cfg.root_lds == 1)) continue;
+            const size_t lds = search_lds_bytes(max_vars, cfg.max_depth, max_desc, cd.d, cd.r,
+                                                feat_ndec, live ? list_items : 0);
+            if (lds > lds_max) continue;
+            SearchShape k;
+            k.desc_lds = cd.d;
+            k.root_lds = cd.r;
+            k.learned = feat_ndec > 0;
+            k.live = live != 0;
+            int occ = 0;
+            hipError_t e = search_occupancy(sh.block, lds, k, &occ);
+            if (e != hipSuccess) return fail(PCCP_E_DEVICE, std::string("occupancy: ") + hipGetErrorString(e));
+            if (occ > best_occ[live]) {  // candidates are in order of preference
+                best_occ[live] = occ;
+                best[live].k = k;
+                best[live].lds = lds;
+            }
         }
     }
-    (void)sv; (void)n;
-    if (best_occ <= 0)
+    const int pick = cfg.live == 1 ? 1 : 0;
+    if (best_occ[pick] <= 0)
         return fail(PCCP_E_LDS_CAPACITY, "no store layout fits in LDS with this wg_size/max_depth");
-    sh.wgs_per_cu = best_occ;
-    const int resident = best_occ * num_cus;
+    sh.k = best[pick].k;
+    sh.lds = best[pick].lds;
+    sh.wgs_per_cu = best_occ[pick];
+    const int resident = sh.wgs_per_cu * num_cus;
     sh.grid = cfg.num_wgs > 0 ? std::min(cfg.num_wgs, resident) : resident;
     return PCCP_OK;
 }
@@ -613,6 +682,7 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
     int32_t rc = check_cfg(cfg);
     if (rc != PCCP_OK) return rc;
     int max_vars = 0, max_ndec = 1;
+    int max_items[4] = {0, 0, 0, 0};
     size_t max_desc = 0;
     for (int i = 0; i < n; ++i) {
         if (!sv[i]) return fail(PCCP_E_INVALID_ARG, "search: solver is NULL");
@@ -622,12 +692,20 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
         max_vars = std::max(max_vars, sv[i]->c.nvars);
         max_ndec = std::max(max_ndec, sv[i]->c.ndec);
         max_desc = std::max(max_desc, sv[i]->desc_bytes);
+        max_items[0] = std::max(max_items[0], (int)sv[i]->c.diff.size());
+        max_items[1] = std::max(max_items[1], (int)sv[i]->c.reif.size());
+        max_items[2] = std::max(max_items[2], (int)sv[i]->c.rows.size());
+        max_items[3] = std::max(max_items[3], (int)sv[i]->c.brows.size());
     }
     HIPCHK(hipSetDevice(s0->device));
     const bool learned = s0->branching == PCCP_BRANCH_MLP && s0->mlp != nullptr;
     LaunchShape sh;
-    rc = choose_shape(sv, n, cfg, max_vars, max_desc, s0->num_cus, s0->lds_max, sh,
-                      learned ? max_ndec : 0);
+    // list entries are 16-bit descriptor indices
+    const bool lists_ok = *std::max_element(max_items, max_items + 4) <= 65536;
+    if (cfg.live == 1 && !lists_ok)
+        return fail(PCCP_E_UNSUPPORTED, "item lists need at most 65536 propagators of each kind");
+    rc = choose_shape(cfg, max_vars, max_desc, max_items[0] + max_items[1] + max_items[2] + max_items[3],
+                      lists_ok, s0->num_cus, s0->lds_max, sh, learned ? max_ndec : 0);
     if (rc != PCCP_OK) return rc;
     const int qcap = cfg.queue_cap > 0 ? std::max(cfg.queue_cap, n) : std::max(4 * sh.grid, n + sh.grid);
     const int slot_bytes = (int)(((size_t)sizeof(RecHdr) + sizeof(int2) * (size_t)cfg.max_depth + 15) & ~size_t(15));
@@ -640,7 +718,7 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
         (rc = ws.qdata.ensure((size_t)slot_bytes * qcap)) ||
         (rc = ws.best.ensure(sizeof(int32_t) * (size_t)n * max_ndec)))
         return rc;
-    if (!sh.root_lds && (rc = ws.roots.ensure(sizeof(int32_t) * 2 * (size_t)Vp * sh.grid)))
+    if (!sh.k.root_lds && (rc = ws.roots.ensure(sizeof(int32_t) * 2 * (size_t)Vp * sh.grid)))
         return rc;
     const bool keep_sols = (mode == PCCP_ENUMERATE && n == 1 && cfg.sol_cap > 0);
     if (keep_sols && (rc = s0->sols.ensure(sizeof(int32_t) * (size_t)cfg.sol_cap * std::max(s0->c.ndec, 1))))
@@ -661,7 +739,7 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
     P.q_data = ws.qdata.as<char>();
     P.qcap = qcap;
     P.slot_bytes = slot_bytes;
-    P.root_scratch = sh.root_lds ? nullptr : ws.roots.as<int32_t>();
+    P.root_scratch = sh.k.root_lds ? nullptr : ws.roots.as<int32_t>();
     P.max_vars = max_vars;
     P.donate = sh.grid > 1 ? 1 : 0;
     P.node_limit = lim ? lim->node_limit : 0;
@@ -672,17 +750,19 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
     P.best_vals = ws.best.as<int32_t>();
     P.max_ndec = max_ndec;
     P.mlp = learned ? reinterpret_cast<const uint16_t *>(s0->mlp) : nullptr;
+    for (int k = 0; k < 4; ++k) P.max_items[k] = max_items[k];
 
     if (cfg.launch == 0) {
         // the graph bakes in the launch parameters: rebuild it when they change
-        std::vector<char> key(sizeof(P) + 5 * sizeof(int64_t));
+        std::vector<char> key(sizeof(P) + 7 * sizeof(int64_t));
         memcpy(key.data(), &P, sizeof(P));
-        const int64_t extra[5] = {sh.grid, sh.block, (int64_t)sh.lds, sh.desc_lds, sh.root_lds};
+        const int64_t extra[7] = {sh.grid, sh.block, (int64_t)sh.lds, sh.k.desc_lds, sh.k.root_lds,
+                                  sh.k.learned, sh.k.live};
         memcpy(key.data() + sizeof(P), extra, sizeof(extra));
         if (!ws.graph || key != ws.graph_key) {
             if (ws.graph) (void)hipGraphExecDestroy(ws.graph);
             ws.graph = nullptr;
-            HIPCHK(build_search_graph(P, sh.grid, sh.block, sh.lds, sh.desc_lds, sh.root_lds, &ws.graph));
+            HIPCHK(build_search_graph(P, sh.grid, sh.block, sh.lds, sh.k, &ws.graph));
             ws.graph_key = key;
         }
         HIPCHK(hipEventRecord(s0->ev0, s0->stream));
@@ -690,7 +770,7 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
         HIPCHK(hipEventRecord(s0->ev1, s0->stream));
     } else {
         HIPCHK(hipEventRecord(s0->ev0, s0->stream));
-        HIPCHK(launch_search(P, sh.grid, sh.block, sh.lds, sh.desc_lds, sh.root_lds, s0->stream));
+        HIPCHK(launch_search(P, sh.grid, sh.block, sh.lds, sh.k, s0->stream));
         HIPCHK(hipEventRecord(s0->ev1, s0->stream));
     }
     std::vector<InstState> st(n);
@@ -716,18 +796,19 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
         o.donations = (int64_t)is.donations;
         o.subtrees = (int64_t)is.pops;
         o.max_depth = (int64_t)is.max_depth;
-        o.prop_linear2 = o.sweeps * (int64_t)s->c.diff.size();
-        o.prop_reified = o.sweeps * (int64_t)s->c.reif.size();
-        o.prop_linear = o.sweeps * (int64_t)s->c.rows.size();
-        o.prop_terms = o.sweeps * (int64_t)s->c.terms.size();
+        o.prop_linear2 = (int64_t)is.ex[0];
+        o.prop_reified = (int64_t)is.ex[1];
+        o.prop_linear = (int64_t)is.ex[2];
+        o.prop_terms = (int64_t)is.ex[3];
         o.sol_hash = is.sol_hash;
         o.best = is.best;
         o.kernel_ms = kms;
         o.grid = sh.grid;
         o.block = sh.block;
-        o.desc_lds = sh.desc_lds;
-        o.root_lds = sh.root_lds;
+        o.desc_lds = sh.k.desc_lds;
+        o.root_lds = sh.k.root_lds;
         o.lds_bytes = (int64_t)sh.lds;
+        o.live = sh.k.live;
         const bool done = is.outstanding == 0;
         o.ttpo_ms = done ? (double)(is.t_done - g.t_start) / (double)s->wall_khz : -1.0;
         if (done)
@@ -820,9 +901,12 @@ extern "C" int32_t pccp_solver_capacity(const pccp_solver *s, int32_t *wgs_per_c
     pccp_config cfg = s->cfg;
     fill_defaults(cfg);
     LaunchShape sh;
-    pccp_solver *sv[1] = {const_cast<pccp_solver *>(s)};
     HIPCHK(hipSetDevice(s->device));
-    int32_t rc = choose_shape(sv, 1, cfg, s->c.nvars, s->desc_bytes, s->num_cus, s->lds_max, sh);
+    const int items = (int)(s->c.diff.size() + s->c.reif.size() + s->c.rows.size() + s->c.brows.size());
+    const bool lists_ok = std::max(std::max(s->c.diff.size(), s->c.reif.size()),
+                                   std::max(s->c.rows.size(), s->c.brows.size())) <= 65536;
+    int32_t rc = choose_shape(cfg, s->c.nvars, s->desc_bytes, items, lists_ok, s->num_cus,
+                              s->lds_max, sh);
     if (rc != PCCP_OK) return rc;
     if (wgs_per_cu) *wgs_per_cu = sh.wgs_per_cu;
     if (num_cus) *num_cus = s->num_cus;

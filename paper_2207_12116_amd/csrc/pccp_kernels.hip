@@ -59,6 +59,28 @@ __device__ __forceinline__ void join_ub(int32_t *p, int32_t v)
     __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// The store: variable x is the pair st[x] = (lb, ub), so one 64-bit LDS read
+// fetches both bounds.  Each half is joined on its own by a 32-bit atomic;
+// the 64-bit read is single-copy atomic per half, which is all a propagator
+// needs (it may see one bound newer than the other, as with two reads).
+__device__ __forceinline__ int2 dom(const int2 *st, int x)
+{
+    const unsigned long long u =
+        __hip_atomic_load(reinterpret_cast<unsigned long long *>(const_cast<int2 *>(st + x)),
+                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return make_int2((int32_t)(uint32_t)u, (int32_t)(uint32_t)(u >> 32));
+}
+__device__ __forceinline__ void tell_lb(int2 *st, int x, int32_t v)
+{
+    join_lb(reinterpret_cast<int32_t *>(st) + 2 * x, v);
+}
+__device__ __forceinline__ void tell_ub(int2 *st, int x, int32_t v)
+{
+    join_ub(reinterpret_cast<int32_t *>(st) + 2 * x + 1, v);
+}
+
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
 // Barrier that orders LDS only (the store, flags and stack are all in LDS).
 __device__ __forceinline__ void lds_barrier()
 {
@@ -154,39 +176,42 @@ enum : int {
     C_STOP = 8,                             // abandon the current subproblem
     C_DEPTH = 9,                            // new depth after a backtrack (-1 = done)
     C_INST = 10, C_LEN = 11,
+    C_CNT = 12,                             // item-list counts: 5 words per list
+                                            // (R, A, B) = 4 kinds, row terms
 };
 
 // ------------------------------------------------------------ descriptors
 // Descriptor tables of one instance, in LDS (DL) or in global memory.
 template <bool DL>
 struct View {
-    int32_t nvars, ndiff, nreif, nrows, ndec, objective;
+    int32_t nvars, ndiff, nreif, nrows, nterms, ndec, objective;
     int32_t row_group, row_chunks;
+    int32_t nbrows, bgroup, bchunks, nbterms;
     const int2 *diff_;
     const int2 *reif_;
     const int4 *rows_;
     const uint32_t *terms_;
+    const int2 *brows_;
+    const uint32_t *bterms_;
     const int32_t *dec_;
+    __device__ __forceinline__ int2 brows(int t) const { return DL ? brows_[t] : gread(brows_ + t); }
+    __device__ __forceinline__ uint32_t bterms(int t) const { return DL ? bterms_[t] : gread(bterms_ + t); }
     __device__ __forceinline__ int2 diff(int t) const { return DL ? diff_[t] : gread(diff_ + t); }
     __device__ __forceinline__ int2 reif(int t) const { return DL ? reif_[t] : gread(reif_ + t); }
     __device__ __forceinline__ int4 rows(int t) const { return DL ? rows_[t] : gread(rows_ + t); }
     __device__ __forceinline__ uint32_t terms(int t) const { return DL ? terms_[t] : gread(terms_ + t); }
     __device__ __forceinline__ int32_t dec(int t) const { return DL ? dec_[t] : gread(dec_ + t); }
-    // learned-branching tables (always in global memory)
-    const float *fstat;
-    const int32_t *fr_ptr;
-    const int2 *fr;
-    const int32_t *fb_ptr;
-    const int32_t *fb;
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
-__host__ __device__ inline size_t desc_bytes(int ndiff, int nreif, int nrows, int nterms, int ndec)
+__host__ __device__ inline size_t desc_bytes(int ndiff, int nreif, int nrows, int nterms, int ndec,
+                                             int nbrows, int nbslots)
 {
     return align16(sizeof(int4) * (size_t)nrows) + align16(sizeof(int2) * (size_t)ndiff) +
            align16(sizeof(int2) * (size_t)nreif) + align16(sizeof(uint32_t) * (size_t)nterms) +
-           align16(sizeof(int32_t) * (size_t)ndec);
+           align16(sizeof(int32_t) * (size_t)ndec) + align16(sizeof(int2) * (size_t)nbrows) +
+           align16(sizeof(uint32_t) * (size_t)nbslots);
 }
 
 // View over global memory.
@@ -194,10 +219,11 @@ __device__ inline View<false> view_global(const DevModel &m)
 {
     View<false> v;
     v.nvars = m.nvars; v.ndiff = m.ndiff; v.nreif = m.nreif; v.nrows = m.nrows;
-    v.ndec = m.ndec; v.objective = m.objective;
+    v.nterms = m.nterms; v.ndec = m.ndec; v.objective = m.objective;
     v.row_group = m.row_group; v.row_chunks = m.row_chunks;
+    v.nbrows = m.nbrows; v.bgroup = m.bgroup; v.bchunks = m.bchunks; v.nbterms = m.nbterms;
     v.diff_ = m.diff; v.reif_ = m.reif; v.rows_ = m.rows; v.terms_ = m.terms; v.dec_ = m.dec;
-    v.fstat = m.fstat; v.fr_ptr = m.fr_ptr; v.fr = m.fr; v.fb_ptr = m.fb_ptr; v.fb = m.fb;
+    v.brows_ = m.brows; v.bterms_ = m.bterms;
     return v;
 }
 
@@ -208,8 +234,10 @@ __device__ inline View<true> stage_descriptors(const DevModel &m, char *dst)
     const int tid = threadIdx.x, W = blockDim.x;
     View<true> v;
     v.nvars = m.nvars; v.ndiff = m.ndiff; v.nreif = m.nreif; v.nrows = m.nrows;
-    v.ndec = m.ndec; v.objective = m.objective;
+    v.nterms = m.nterms; v.ndec = m.ndec; v.objective = m.objective;
     v.row_group = m.row_group; v.row_chunks = m.row_chunks;
+    v.nbrows = m.nbrows; v.bgroup = m.bgroup; v.bchunks = m.bchunks; v.nbterms = m.nbterms;
+    const int nbslots = m.nbrows * m.bgroup * m.bchunks;
     char *p = dst;
     int4 *rows = reinterpret_cast<int4 *>(p);
     p += align16(sizeof(int4) * (size_t)m.nrows);
@@ -220,21 +248,76 @@ __device__ inline View<true> stage_descriptors(const DevModel &m, char *dst)
     uint32_t *terms = reinterpret_cast<uint32_t *>(p);
     p += align16(sizeof(uint32_t) * (size_t)m.nterms);
     int32_t *dec = reinterpret_cast<int32_t *>(p);
+    p += align16(sizeof(int32_t) * (size_t)m.ndec);
+    int2 *brows = reinterpret_cast<int2 *>(p);
+    p += align16(sizeof(int2) * (size_t)m.nbrows);
+    uint32_t *bterms = reinterpret_cast<uint32_t *>(p);
+    for (int i = tid; i < m.nbrows; i += W) brows[i] = gread(m.brows + i);
+    for (int i = tid; i < nbslots; i += W) bterms[i] = gread(m.bterms + i);
     for (int i = tid; i < m.nrows; i += W) rows[i] = gread(m.rows + i);
     for (int i = tid; i < m.ndiff; i += W) diff[i] = gread(m.diff + i);
     for (int i = tid; i < m.nreif; i += W) reif[i] = gread(m.reif + i);
     for (int i = tid; i < m.nterms; i += W) terms[i] = gread(m.terms + i);
     for (int i = tid; i < m.ndec; i += W) dec[i] = gread(m.dec + i);
     v.rows_ = rows; v.diff_ = diff; v.reif_ = reif; v.terms_ = terms; v.dec_ = dec;
-    v.fstat = m.fstat; v.fr_ptr = m.fr_ptr; v.fr = m.fr; v.fb_ptr = m.fb_ptr; v.fb = m.fb;
+    v.brows_ = brows; v.bterms_ = bterms;
     return v;
 }
 
 // ------------------------------------------------------ propagation loop
-// Each lane issues the loads of several propagators before it uses any of
-// them (U items per chunk), so one sweep costs a few LDS round trips per
-// chunk rather than two per propagator.  Indices past the end of a table are
-// clamped to its last entry and the item is masked out of the tells.
+// A sweep runs every item of one list per kind once.  A list is either the
+// whole table of the kind (`in` = nullptr: entry t is descriptor t) or an
+// LDS array of descriptor indices.  Wavefront w takes the entries
+// 64 w + lane + k W, U chunks of 64 at a time: the loads of a chunk are all
+// issued before any is used, and a chunk that lies wholly past the end of
+// the list is skipped by the whole wavefront, so a sweep costs in proportion
+// to the list's length.
+//
+// Entailed propagators.  A propagator is entailed in a store when none of
+// its tells can tighten that store or any tighter one (its guards and bounds
+// are monotone in the store).  Dropping it from the sweeps of every node
+// below the one where that holds changes no fixed point (§3 Theorem 2: the
+// fixed point is the least store closed under the remaining propagators,
+// and the dropped ones are closed on every store that can follow).  With
+// `out` set, a sweep also appends to `out` (in any order) each item it ran
+// and did not find entailed, judged on the bounds it read joined with its
+// own tells (a store no tighter than any later one), and counts them in
+// *cnt; a row sweep also adds the terms of the rows it keeps to *tcnt.
+struct ListIO {
+    const uint16_t *in;   // nullptr: the whole table
+    int n;                // entries to run
+    uint16_t *out;        // compaction target, or nullptr
+    int32_t *cnt;         // count of the kept entries
+    int32_t *tcnt;        // rows: terms of the kept rows
+};
+
+// Append, per wavefront, the entries whose `keep` is set (U chunks) to out.
+template <int U>
+__device__ __forceinline__ void compact(const ListIO &io, const bool (&keep)[U], const int (&idx)[U])
+{
+    const int lane = threadIdx.x & 63;
+    unsigned long long mk[U];
+    int tot = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        mk[u] = __ballot(keep[u]);
+        tot += __popcll(mk[u]);
+    }
+    if (tot == 0) return;
+    int pos = 0;
+    if (lane == 0)
+        pos = __hip_atomic_fetch_add(io.cnt, tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    pos = __builtin_amdgcn_readfirstlane(pos);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (keep[u]) {
+            const int r = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk[u] >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mk[u], 0u));
+            io.out[pos + r] = (uint16_t)idx[u];
+        }
+        pos += __popcll(mk[u]);
+    }
+}
 
 // Sum over the `G` lanes of a row group (G = 4, 8 or 16; groups are aligned
 // so that every DPP source lane is in the same group).
@@ -247,45 +330,63 @@ __device__ __forceinline__ int group_sum(int x, int G)
     return x;
 }
 
-// kind 1: x - y <= c  =>  ub(x) <= c + ub(y),  lb(y) >= lb(x) - c
+// kind 1: x - y <= c  =>  ub(x) <= c + ub(y),  lb(y) >= lb(x) - c;
+// entailed once ub(x) - lb(y) <= c.
 template <bool DL>
-__device__ __forceinline__ void sweep_diff(const View<DL> &v, int32_t *lb, int32_t *ub,
+__device__ __forceinline__ void sweep_diff(const View<DL> &v, int2 *st, const ListIO &io,
                                            bool &chg, bool &bad)
 {
     constexpr int U = 2;
-    const int tid = threadIdx.x, W = blockDim.x, n = v.ndiff;
-    for (int base = tid; base < n; base += U * W) {
-        int2 e[U];
+    const int tid = threadIdx.x, lane = tid & 63, W = blockDim.x, n = io.n;
+    for (int c0 = uni(tid - lane); c0 < n; c0 += U * W) {
+        int idx[U];
         bool ok[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int t = base + u * W;
+            const int t = c0 + u * W + lane;
             ok[u] = t < n;
-            e[u] = v.diff(ok[u] ? t : n - 1);
+            const int tc = ok[u] ? t : n - 1;
+            idx[u] = io.in ? (int)io.in[tc] : tc;
         }
-        int lbx[U], ubx[U], lby[U], uby[U];
+        int2 e[U], dx[U], dy[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            e[u] = c0 + u * W < n ? v.diff(idx[u]) : make_int2(0, 0x3fffffff);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int x = e[u].x & 0xffff, y = (uint32_t)e[u].x >> 16;
-            lbx[u] = lds_ld(&lb[x]); ubx[u] = lds_ld(&ub[x]);
-            lby[u] = lds_ld(&lb[y]); uby[u] = lds_ld(&ub[y]);
+            dx[u] = make_int2(0, 0);
+            dy[u] = make_int2(0, 0);
+            if (c0 + u * W < n) {
+                dx[u] = dom(st, e[u].x & 0xffff);
+                dy[u] = dom(st, (uint32_t)e[u].x >> 16);
+            }
         }
         bool pu[U], pl[U], any = false;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int c = e[u].y;
-            pu[u] = ok[u] && c + uby[u] < ubx[u];
-            pl[u] = ok[u] && lbx[u] - c > lby[u];
+            pu[u] = ok[u] && c + dy[u].y < dx[u].y;
+            pl[u] = ok[u] && dx[u].x - c > dy[u].x;
             any |= pu[u] | pl[u];
         }
         if (any) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int x = e[u].x & 0xffff, y = (uint32_t)e[u].x >> 16, c = e[u].y;
-                const int nu = c + uby[u], nl = lbx[u] - c;
-                if (pu[u]) { join_ub(&ub[x], nu); chg = true; bad |= nu < lbx[u]; }
-                if (pl[u]) { join_lb(&lb[y], nl); chg = true; bad |= nl > uby[u]; }
+                const int nu = c + dy[u].y, nl = dx[u].x - c;
+                if (pu[u]) { tell_ub(st, x, nu); chg = true; bad |= nu < dx[u].x; }
+                if (pl[u]) { tell_lb(st, y, nl); chg = true; bad |= nl > dy[u].y; }
             }
+        }
+        if (io.out) {
+            bool keep[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = e[u].y;
+                const int ux = min(dx[u].y, c + dy[u].y), ly = max(dy[u].x, dx[u].x - c);
+                keep[u] = ok[u] && ux - ly > c;
+            }
+            compact<U>(io, keep, idx);
         }
     }
 }
@@ -299,56 +400,74 @@ __device__ __forceinline__ void sweep_diff(const View<DL> &v, int32_t *lb, int32
 //   b false, si <= sj entailed   : lb(sj) >= lb(si)+d, ub(si) <= ub(sj)-d
 //   b false, sj < si+d entailed  : ub(sj) <= ub(si)-1, lb(si) >= lb(sj)+1
 // and is told only if that value is tighter than the bound read.
-template <bool DL>
-__device__ __forceinline__ void sweep_reif(const View<DL> &v, int32_t *lb, int32_t *ub,
+// Entailed once b = 1 with both conjuncts entailed, or b = 0 with one of
+// them disentailed (lb(si) > ub(sj), or lb(sj) >= ub(si) + d).
+template <bool DL, int U>
+__device__ __forceinline__ void sweep_reif(const View<DL> &v, int2 *st, const ListIO &io,
                                            bool &chg, bool &bad)
 {
-    constexpr int U = 4;
     constexpr int BIG = 0x3fffffff;
-    const int tid = threadIdx.x, W = blockDim.x, n = v.nreif;
-    for (int base = tid; base < n; base += U * W) {
-        int2 e[U];
+    const int tid = threadIdx.x, lane = tid & 63, W = blockDim.x, n = io.n;
+    for (int c0 = uni(tid - lane); c0 < n; c0 += U * W) {
+        int idx[U];
         bool ok[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int t = base + u * W;
+            const int t = c0 + u * W + lane;
             ok[u] = t < n;
-            e[u] = v.reif(ok[u] ? t : n - 1);
+            const int tc = ok[u] ? t : n - 1;
+            idx[u] = io.in ? (int)io.in[tc] : tc;
         }
-        int lbi[U], ubi[U], lbj[U], ubj[U], lbb[U], ubb[U];
+        int2 e[U], di[U], dj[U], db[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            e[u] = c0 + u * W < n ? v.reif(idx[u]) : make_int2(0, 0);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int b = e[u].x & 0xffff, i = (uint32_t)e[u].x >> 16, j = e[u].y & 0xffff;
-            lbi[u] = lds_ld(&lb[i]); ubi[u] = lds_ld(&ub[i]);
-            lbj[u] = lds_ld(&lb[j]); ubj[u] = lds_ld(&ub[j]);
-            lbb[u] = lds_ld(&lb[b]); ubb[u] = lds_ld(&ub[b]);
+            db[u] = di[u] = dj[u] = make_int2(0, 0);
+            if (c0 + u * W < n) {
+                db[u] = dom(st, e[u].x & 0xffff);
+                di[u] = dom(st, (uint32_t)e[u].x >> 16);
+                dj[u] = dom(st, e[u].y & 0xffff);
+            }
         }
+        bool keep[U] = {};
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int d = e[u].y >> 16;
-            const bool E1 = ubi[u] <= lbj[u];            // entailed(si <= sj)
-            const bool E2 = ubj[u] <= lbi[u] + d - 1;    // entailed(sj < si + d)
-            const bool on = lbb[u] >= 1, off = ubb[u] <= 0;
+            const int lbi = di[u].x, ubi = di[u].y, lbj = dj[u].x, ubj = dj[u].y;
+            const int lbb = db[u].x, ubb = db[u].y;
+            const bool E1 = ubi <= lbj;                  // entailed(si <= sj)
+            const bool E2 = ubj <= lbi + d - 1;          // entailed(sj < si + d)
+            const bool on = lbb >= 1, off = ubb <= 0;
             const bool t_b1 = !on && E1 && E2;           // psi entailed: b >= 1
-            const bool t_b0 = !off && (lbi[u] > ubj[u] || lbj[u] >= ubi[u] + d);  // not psi: b <= 0
+            const bool t_b0 = !off && (lbi > ubj || lbj >= ubi + d);  // not psi: b <= 0
             const bool o1 = off && E1, o2 = off && E2;
-            const int nui = min(on ? ubj[u] : BIG, o1 ? ubj[u] - d : BIG);
-            const int nlj = max(on ? lbi[u] : -BIG, o1 ? lbi[u] + d : -BIG);
-            const int nuj = min(on ? ubi[u] + d - 1 : BIG, o2 ? ubi[u] - 1 : BIG);
-            const int nli = max(on ? lbj[u] - d + 1 : -BIG, o2 ? lbj[u] + 1 : -BIG);
-            const bool p_ui = nui < ubi[u], p_lj = nlj > lbj[u];
-            const bool p_uj = nuj < ubj[u], p_li = nli > lbi[u];
+            const int nui = min(on ? ubj : BIG, o1 ? ubj - d : BIG);
+            const int nlj = max(on ? lbi : -BIG, o1 ? lbi + d : -BIG);
+            const int nuj = min(on ? ubi + d - 1 : BIG, o2 ? ubi - 1 : BIG);
+            const int nli = max(on ? lbj - d + 1 : -BIG, o2 ? lbj + 1 : -BIG);
+            const bool p_ui = nui < ubi, p_lj = nlj > lbj;
+            const bool p_uj = nuj < ubj, p_li = nli > lbi;
+            if (io.out) {
+                const int ui = min(ubi, nui), lj = max(lbj, nlj), uj = min(ubj, nuj), li = max(lbi, nli);
+                const bool b1 = on || t_b1, b0 = off || t_b0;
+                const bool ent = (b1 && ui <= lj && uj <= li + d - 1) ||
+                                 (b0 && (li > uj || lj >= ui + d));
+                keep[u] = ok[u] && !ent;
+            }
             if (!ok[u] || !(t_b1 | t_b0 | p_ui | p_lj | p_uj | p_li))
                 continue;
             const int b = e[u].x & 0xffff, i = (uint32_t)e[u].x >> 16, j = e[u].y & 0xffff;
             chg = true;
-            if (t_b1) { join_lb(&lb[b], 1); bad |= ubb[u] < 1; }
-            if (t_b0) { join_ub(&ub[b], 0); bad |= lbb[u] > 0; }
-            if (p_ui) { join_ub(&ub[i], nui); bad |= nui < lbi[u]; }
-            if (p_lj) { join_lb(&lb[j], nlj); bad |= nlj > ubj[u]; }
-            if (p_uj) { join_ub(&ub[j], nuj); bad |= nuj < lbj[u]; }
-            if (p_li) { join_lb(&lb[i], nli); bad |= nli > ubi[u]; }
+            if (t_b1) { tell_lb(st, b, 1); bad |= ubb < 1; }
+            if (t_b0) { tell_ub(st, b, 0); bad |= lbb > 0; }
+            if (p_ui) { tell_ub(st, i, nui); bad |= nui < lbi; }
+            if (p_lj) { tell_lb(st, j, nlj); bad |= nlj > ubj; }
+            if (p_uj) { tell_ub(st, j, nuj); bad |= nuj < lbj; }
+            if (p_li) { tell_lb(st, i, nli); bad |= nli > ubi; }
         }
+        if (io.out) compact<U>(io, keep, idx);
     }
 }
 
@@ -360,17 +479,17 @@ __device__ __forceinline__ bool term_tight(int a, int lbx, int ubx, int rhs, int
     return a > 0 ? rhs - (S - a * lbx) < a * ubx : rhs - (S - a * ubx) < a * lbx;
 }
 
-__device__ __forceinline__ void term_tell(int32_t *lb, int32_t *ub, int x, int a, int lbx, int ubx,
+__device__ __forceinline__ void term_tell(int2 *st, int x, int a, int lbx, int ubx,
                                           int rhs, int S, bool &chg, bool &bad)
 {
     if (a > 0) {
         const int rr = rhs - (S - a * lbx);                 // a x <= rr
         const int nb = a == 1 ? rr : floor_div_pos(rr, a);
-        join_ub(&ub[x], nb); chg = true; bad |= nb < lbx;
+        tell_ub(st, x, nb); chg = true; bad |= nb < lbx;
     } else {
         const int rr = rhs - (S - a * ubx);                 // x >= ceil(rr / a)
         const int nb = a == -1 ? -rr : -floor_div_pos(rr, -a);
-        join_lb(&lb[x], nb); chg = true; bad |= nb > ubx;
+        tell_lb(st, x, nb); chg = true; bad |= nb > ubx;
     }
 }
 
@@ -379,25 +498,34 @@ __device__ __forceinline__ void term_tell(int32_t *lb, int32_t *ub, int x, int a
 // smallest value, §2's lsum generalised) is a DPP sum over the group; each
 // term is then told a_t x_t <= rhs - (S - m_t).  Rows are taken RR at a
 // time per group; when every row fits in one chunk of TK terms per lane the
-// tells use the bounds already in registers.
-template <bool DL>
-__device__ __forceinline__ void sweep_rows(const View<DL> &v, int32_t *lb, int32_t *ub,
+// tells use the bounds already in registers.  Entailed once the sum of the
+// terms' largest values is at most rhs.
+template <bool DL, int RR>
+__device__ __forceinline__ void sweep_rows(const View<DL> &v, int2 *st, const ListIO &io,
                                            bool &chg, bool &bad)
 {
-    constexpr int RR = 4, TK = 2;
-    const int tid = threadIdx.x, W = blockDim.x, n = v.nrows;
+    constexpr int TK = 2;
+    const int tid = threadIdx.x, W = blockDim.x, n = io.n;
     if (n == 0) return;
     const int G = v.row_group, gl = tid & (G - 1), gid = tid / G, NG = W / G;
+    const int g0 = uni((tid & ~63) / G);     // first group of this wavefront
     const int KC = v.row_chunks;            // chunks of G terms in the longest row
-    for (int rbase = gid; rbase < n; rbase += RR * NG) {
+    const bool cmp = io.out != nullptr;
+    for (int rb0 = g0; rb0 < n; rb0 += RR * NG) {
+        const int rbase = rb0 + (gid - g0);
+        int ri[RR];
         int4 rd[RR];
         bool rok[RR];
 #pragma unroll
         for (int q = 0; q < RR; ++q) {
             const int r = rbase + q * NG;
             rok[q] = r < n;
-            rd[q] = v.rows(rok[q] ? r : n - 1);
+            const int rc = rok[q] ? r : n - 1;
+            ri[q] = io.in ? (int)io.in[rc] : rc;
         }
+#pragma unroll
+        for (int q = 0; q < RR; ++q) rd[q] = v.rows(ri[q]);
+        int S[RR], Smax[RR];
         if (KC <= TK) {
             uint32_t tv[RR][TK];
             bool tok[RR][TK];
@@ -409,33 +537,30 @@ __device__ __forceinline__ void sweep_rows(const View<DL> &v, int32_t *lb, int32
                     tok[q][k] = rok[q] && o < rd[q].y;
                     tv[q][k] = v.terms(rd[q].x + (o < rd[q].y ? o : 0));
                 }
-            int tl[RR][TK], tu[RR][TK];
+            int2 td[RR][TK];
 #pragma unroll
             for (int q = 0; q < RR; ++q)
 #pragma unroll
-                for (int k = 0; k < TK; ++k) {
-                    const int x = tv[q][k] & 0xffff;
-                    tl[q][k] = lds_ld(&lb[x]);
-                    tu[q][k] = lds_ld(&ub[x]);
-                }
-            int S[RR];
+                for (int k = 0; k < TK; ++k) td[q][k] = dom(st, tv[q][k] & 0xffff);
 #pragma unroll
             for (int q = 0; q < RR; ++q) {
-                int part = 0;
+                int part = 0, pmax = 0;
 #pragma unroll
                 for (int k = 0; k < TK; ++k) {
                     const int a = (int32_t)tv[q][k] >> 16;
-                    part += tok[q][k] ? (a > 0 ? a * tl[q][k] : a * tu[q][k]) : 0;
+                    part += tok[q][k] ? (a > 0 ? a * td[q][k].x : a * td[q][k].y) : 0;
+                    pmax += tok[q][k] ? (a > 0 ? a * td[q][k].y : a * td[q][k].x) : 0;
                 }
                 S[q] = group_sum(part, G);
+                Smax[q] = cmp ? group_sum(pmax, G) : 0;
             }
             bool tight[RR][TK], any = false;
 #pragma unroll
             for (int q = 0; q < RR; ++q)
 #pragma unroll
                 for (int k = 0; k < TK; ++k) {
-                    tight[q][k] = tok[q][k] && term_tight((int32_t)tv[q][k] >> 16, tl[q][k],
-                                                          tu[q][k], rd[q].z, S[q]);
+                    tight[q][k] = tok[q][k] && term_tight((int32_t)tv[q][k] >> 16, td[q][k].x,
+                                                          td[q][k].y, rd[q].z, S[q]);
                     any |= tight[q][k];
                 }
             if (any) {
@@ -444,27 +569,31 @@ __device__ __forceinline__ void sweep_rows(const View<DL> &v, int32_t *lb, int32
 #pragma unroll
                     for (int k = 0; k < TK; ++k)
                         if (tight[q][k])
-                            term_tell(lb, ub, tv[q][k] & 0xffff, (int32_t)tv[q][k] >> 16,
-                                      tl[q][k], tu[q][k], rd[q].z, S[q], chg, bad);
+                            term_tell(st, tv[q][k] & 0xffff, (int32_t)tv[q][k] >> 16,
+                                      td[q][k].x, td[q][k].y, rd[q].z, S[q], chg, bad);
             }
         } else {
             // long rows: sum chunk by chunk, then tell chunk by chunk
-            int S[RR];
 #pragma unroll
-            for (int q = 0; q < RR; ++q) S[q] = 0;
+            for (int q = 0; q < RR; ++q) S[q] = Smax[q] = 0;
             for (int k = 0; k < KC; ++k) {
                 const int o = gl + k * G;
 #pragma unroll
                 for (int q = 0; q < RR; ++q) {
                     if (rok[q] && o < rd[q].y) {
                         const uint32_t t = v.terms(rd[q].x + o);
-                        const int x = t & 0xffff, a = (int32_t)t >> 16;
-                        S[q] += a > 0 ? a * lds_ld(&lb[x]) : a * lds_ld(&ub[x]);
+                        const int a = (int32_t)t >> 16;
+                        const int2 dx = dom(st, t & 0xffff);
+                        S[q] += a > 0 ? a * dx.x : a * dx.y;
+                        Smax[q] += a > 0 ? a * dx.y : a * dx.x;
                     }
                 }
             }
 #pragma unroll
-            for (int q = 0; q < RR; ++q) S[q] = group_sum(S[q], G);
+            for (int q = 0; q < RR; ++q) {
+                S[q] = group_sum(S[q], G);
+                if (cmp) Smax[q] = group_sum(Smax[q], G);
+            }
             for (int k = 0; k < KC; ++k) {
                 const int o = gl + k * G;
 #pragma unroll
@@ -474,40 +603,218 @@ __device__ __forceinline__ void sweep_rows(const View<DL> &v, int32_t *lb, int32
                         const int x = t & 0xffff, a = (int32_t)t >> 16;
                         // a bound re-read here can only have tightened since S
                         // was formed: the tell is then weaker, never unsound
-                        const int lbx = lds_ld(&lb[x]), ubx = lds_ld(&ub[x]);
-                        if (term_tight(a, lbx, ubx, rd[q].z, S[q]))
-                            term_tell(lb, ub, x, a, lbx, ubx, rd[q].z, S[q], chg, bad);
+                        const int2 dx = dom(st, x);
+                        if (term_tight(a, dx.x, dx.y, rd[q].z, S[q]))
+                            term_tell(st, x, a, dx.x, dx.y, rd[q].z, S[q], chg, bad);
                     }
                 }
             }
         }
+        if (cmp) {
+            bool keep[RR];
+#pragma unroll
+            for (int q = 0; q < RR; ++q) keep[q] = rok[q] && gl == 0 && Smax[q] > rd[q].z;
+            compact<RR>(io, keep, ri);
+#pragma unroll
+            for (int q = 0; q < RR; ++q)
+                if (keep[q])
+                    __hip_atomic_fetch_add(io.tcnt, rd[q].y, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
     }
 }
 
-// Fixed point of the LDS store (lb, ub) under every propagator of `v`.
+// kind 4: sum_t a_t b_t <= rhs with every b_t in [0, 1] and a_t > 0.  This is
+// kind 3's rule on 0/1 domains: with S = the sum of a_t over the terms with
+// lb(b_t) = 1 and slack = rhs - S, a negative slack empties some term's
+// interval (failure), and otherwise every open term (lb = 0 < ub) with
+// a_t > slack is told ub(b_t) <= 0; no other tell of kind 3 tightens a 0/1
+// store.  Products become selects and there is no division.  A group of G
+// lanes takes a row; the terms of row r sit at r * G * KC + lane + G * k, so
+// their addresses do not wait for the row descriptor; unused slots hold
+// a = 0.  Entailed once the sum of a_t over the terms with ub(b_t) = 1 is at
+// most rhs.
+template <bool DL, int RB>
+__device__ __forceinline__ void sweep_brows(const View<DL> &v, int2 *st, const ListIO &io,
+                                            bool &chg, bool &bad)
+{
+    constexpr int TB = 4;                   // term slots per lane held in registers
+    const int tid = threadIdx.x, W = blockDim.x, n = io.n;
+    if (n == 0) return;
+    const int G = v.bgroup, gl = tid & (G - 1), gid = tid / G, NG = W / G;
+    const int g0 = uni((tid & ~63) / G);     // first group of this wavefront
+    const int KC = v.bchunks, SL = G * KC;
+    const bool cmp = io.out != nullptr;
+    for (int rb0 = g0; rb0 < n; rb0 += RB * NG) {
+        const int rbase = rb0 + (gid - g0);
+        int ri[RB];
+        bool rok[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int r = rbase + q * NG;
+            rok[q] = r < n;
+            const int rc = rok[q] ? r : n - 1;
+            ri[q] = io.in ? (int)io.in[rc] : rc;
+        }
+        int2 rd[RB];
+        int S[RB], Smax[RB];
+        if (KC <= TB) {
+            uint32_t tv[RB][TB];
+#pragma unroll
+            for (int q = 0; q < RB; ++q)
+#pragma unroll
+                for (int k = 0; k < TB; ++k)
+                    tv[q][k] = k < KC ? v.bterms(ri[q] * SL + gl + k * G) : 0u;
+#pragma unroll
+            for (int q = 0; q < RB; ++q) rd[q] = v.brows(ri[q]);
+            // per slot only the open bit survives the sums (bit q * TB + k)
+            uint32_t open = 0;
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                int part = 0, pmax = 0;
+#pragma unroll
+                for (int k = 0; k < TB; ++k) {
+                    const int2 d = k < KC ? dom(st, tv[q][k] & 0xffff) : make_int2(0, 0);
+                    const int a = (int)(tv[q][k] >> 16);
+                    part += d.x > 0 ? a : 0;
+                    pmax += d.y > 0 ? a : 0;
+                    open |= (a > 0 && d.x < d.y) ? 1u << (q * TB + k) : 0u;
+                }
+                S[q] = group_sum(part, G);
+                Smax[q] = cmp ? group_sum(pmax, G) : 0;
+            }
+            uint32_t tight = 0;
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                const int slack = rd[q].x - S[q];
+                if (rok[q] && slack < 0) { bad = true; chg = true; }
+#pragma unroll
+                for (int k = 0; k < TB; ++k) {
+                    const int a = (int)(tv[q][k] >> 16);
+                    tight |= (rok[q] && a > slack) ? (open & (1u << (q * TB + k))) : 0u;
+                }
+            }
+            if (__any(tight != 0)) {
+#pragma unroll
+                for (int q = 0; q < RB; ++q)
+#pragma unroll
+                    for (int k = 0; k < TB; ++k)
+                        if (tight & (1u << (q * TB + k))) {
+                            tell_ub(st, tv[q][k] & 0xffff, 0);
+                            chg = true;
+                        }
+            }
+        } else {
+            // long rows: sum chunk by chunk, then tell chunk by chunk
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                rd[q] = v.brows(ri[q]);
+                S[q] = Smax[q] = 0;
+            }
+            for (int k = 0; k < KC; ++k) {
+#pragma unroll
+                for (int q = 0; q < RB; ++q) {
+                    const uint32_t t = v.bterms(ri[q] * SL + gl + k * G);
+                    const int a = (int)(t >> 16);
+                    const int2 dx = dom(st, t & 0xffff);
+                    S[q] += dx.x > 0 ? a : 0;
+                    Smax[q] += dx.y > 0 ? a : 0;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                S[q] = group_sum(S[q], G);
+                if (cmp) Smax[q] = group_sum(Smax[q], G);
+                if (rok[q] && rd[q].x - S[q] < 0) { bad = true; chg = true; }
+            }
+            for (int k = 0; k < KC; ++k) {
+#pragma unroll
+                for (int q = 0; q < RB; ++q) {
+                    const uint32_t t = v.bterms(ri[q] * SL + gl + k * G);
+                    const int a = (int)(t >> 16);
+                    // a bound re-read here can only have tightened since S was
+                    // formed: an open term is still told soundly
+                    const int2 dx = dom(st, t & 0xffff);
+                    if (rok[q] && a > 0 && a > rd[q].x - S[q] && dx.x < dx.y) {
+                        tell_ub(st, t & 0xffff, 0);
+                        chg = true;
+                        bad |= dx.x > 0;
+                    }
+                }
+            }
+        }
+        if (cmp) {
+            bool keep[RB];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) keep[q] = rok[q] && gl == 0 && Smax[q] > rd[q].x;
+            compact<RB>(io, keep, ri);
+#pragma unroll
+            for (int q = 0; q < RB; ++q)
+                if (keep[q])
+                    __hip_atomic_fetch_add(io.tcnt, rd[q].y, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+}
+
+// The item lists of one node, per kind (0 difference rows, 1 reified items,
+// 2 linear rows, 3 Boolean rows): the first sweep runs in[k] (nin[k]
+// entries; nullptr = the whole table; tin = terms of the rows in in[2] and
+// in[3]) and, when out[0] is set, writes the items it keeps to out[k] with
+// their counts in cnt[k] and the kept rows' terms in cnt[4]; later sweeps
+// run the kept lists.
+constexpr int kKinds = 4;
+constexpr int kListWords = kKinds + 1;
+static_assert(C_CNT + 3 * kListWords <= 32, "list counts must stay below the control lane's state");
+struct NodeLists {
+    const uint16_t *in[kKinds];
+    int nin[kKinds];
+    int tin;
+    uint16_t *out[kKinds];
+    int32_t *cnt;
+};
+
+// Fixed point of the LDS store `st` under the propagators of the lists `L`.
 // Returns 1 if the loop saw a failure, 0 at a fixed point (the post scan
-// still has to look for an empty interval the loop did not see).
+// still has to look for an empty interval the loop did not see).  ex[] gets
+// the items run per kind and the row terms visited.
 // Precondition: a barrier separates this call from any earlier read of the
-// control words C_FLAG*, C_POSTFAIL, C_KEY.
-template <bool DL>
-__device__ int propagate_wg(const View<DL> &v, int32_t *lb, int32_t *ub, int32_t *ctl,
-                            uint32_t &nsweeps)
+// control words C_FLAG*, C_POSTFAIL, C_KEY and of the out lists.
+// LIVE: L may carry lists (fewer items per lane per chunk then, which leaves
+// the registers the compaction needs).
+template <bool DL, bool LIVE>
+__device__ int propagate_wg(const View<DL> &v, int2 *st, int32_t *ctl, const NodeLists &L,
+                            uint32_t &nsweeps, unsigned long long (&ex)[4])
 {
     const int tid = threadIdx.x, lane = tid & 63;
+    const bool cmp = L.out[0] != nullptr;
     if (tid == 0) {
         ctl[C_FLAG0] = 0;
         ctl[C_FLAG1] = 0;
         ctl[C_FLAG2] = 0;
         ctl[C_POSTFAIL] = 0;
         *reinterpret_cast<unsigned long long *>(ctl + C_KEY) = ~0ull;
+        if (cmp)
+            for (int k = 0; k < kListWords; ++k) L.cnt[k] = 0;
     }
     lds_barrier();
+    int32_t *tc = cmp ? L.cnt + kKinds : nullptr;
+    ListIO d{L.in[0], L.nin[0], L.out[0], cmp ? L.cnt : nullptr, nullptr};
+    ListIO r{L.in[1], L.nin[1], L.out[1], cmp ? L.cnt + 1 : nullptr, nullptr};
+    ListIO w{L.in[2], L.nin[2], L.out[2], cmp ? L.cnt + 2 : nullptr, tc};
+    ListIO b{L.in[3], L.nin[3], L.out[3], cmp ? L.cnt + 3 : nullptr, tc};
+    int terms = L.tin;
     int slot = 0;
     for (;;) {
         bool chg = false, bad = false;
-        sweep_diff(v, lb, ub, chg, bad);
-        sweep_reif(v, lb, ub, chg, bad);
-        sweep_rows(v, lb, ub, chg, bad);
+        sweep_diff(v, st, d, chg, bad);
+        sweep_reif<DL, LIVE ? 2 : 4>(v, st, r, chg, bad);
+        sweep_rows<DL, LIVE ? 2 : 4>(v, st, w, chg, bad);
+        sweep_brows<DL, LIVE ? 1 : 2>(v, st, b, chg, bad);
+        ex[0] += (unsigned)d.n;
+        ex[1] += (unsigned)r.n;
+        ex[2] += (unsigned)(w.n + b.n);
+        ex[3] += (unsigned)terms;
         const int flags = (__any(chg) ? 1 : 0) | (__any(bad) ? 2 : 0);
         if (lane == 0 && flags)
             __hip_atomic_fetch_or(&ctl[slot], flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -520,6 +827,14 @@ __device__ int propagate_wg(const View<DL> &v, int32_t *lb, int32_t *ub, int32_t
         if (f & 2) return 1;
         if (!(f & 1)) return 0;
         slot = next;
+        if (d.out) {
+            // after the first sweep: run what it kept
+            d = ListIO{d.out, uni(lds_ld(&L.cnt[0])), nullptr, nullptr, nullptr};
+            r = ListIO{r.out, uni(lds_ld(&L.cnt[1])), nullptr, nullptr, nullptr};
+            w = ListIO{w.out, uni(lds_ld(&L.cnt[2])), nullptr, nullptr, nullptr};
+            b = ListIO{b.out, uni(lds_ld(&L.cnt[3])), nullptr, nullptr, nullptr};
+            terms = uni(lds_ld(&L.cnt[kKinds]));
+        }
     }
 }
 
@@ -530,31 +845,34 @@ __device__ int propagate_wg(const View<DL> &v, int32_t *lb, int32_t *ub, int32_t
 //   f3 = degree share, f4 = min(1, min over rows x - y <= c of
 //   (c + ub(y) - lb(x))/H), f5 = static load + (#reified items with si = x
 //   and lb(b) >= 1) / N.
+// The learned-branching tables are read through the instance's DevModel
+// (global memory), so the propagation view stays small.
 template <bool DL>
-__device__ __forceinline__ void candidate_features(const View<DL> &v, int q, const int32_t *lb,
-                                                   const int32_t *ub, float f[kNumFeat])
+__device__ __forceinline__ void candidate_features(const View<DL> &v, const DevModel *m, int q,
+                                                   const int2 *st, float f[kNumFeat])
 {
     const int x = v.dec(q);
-    const float *st = v.fstat + 8 * (size_t)q;
-    const int lo = __float_as_int(gread_f(st + 0));
-    const float invH = gread_f(st + 1), degn = gread_f(st + 2), sl = gread_f(st + 3);
-    const float invN = gread_f(st + 4);
-    const int lbx = lds_ld(&lb[x]), ubx = lds_ld(&ub[x]);
+    const float *fs = m->fstat + 8 * (size_t)q;
+    const int lo = __float_as_int(gread_f(fs + 0));
+    const float invH = gread_f(fs + 1), degn = gread_f(fs + 2), sl = gread_f(fs + 3);
+    const float invN = gread_f(fs + 4);
+    const int2 dx = dom(st, x);
+    const int lbx = dx.x, ubx = dx.y;
     f[0] = (float)(lbx - lo) * invH;
     f[1] = (float)(ubx - lo) * invH;
     f[2] = (float)(ubx - lbx) * invH;
     f[3] = degn;
     float slack = 1.0f;
-    const int r1 = gread(v.fr_ptr + q + 1);
-    for (int k = gread(v.fr_ptr + q); k < r1; ++k) {
-        const int2 e = gread(v.fr + k);
-        slack = fminf(slack, (float)(e.y + lds_ld(&ub[e.x]) - lbx) * invH);
+    const int r1 = gread(m->fr_ptr + q + 1);
+    for (int k = gread(m->fr_ptr + q); k < r1; ++k) {
+        const int2 e = gread(m->fr + k);
+        slack = fminf(slack, (float)(e.y + dom(st, e.x).y - lbx) * invH);
     }
     f[4] = slack;
     int cnt = 0;
-    const int b1 = gread(v.fb_ptr + q + 1);
-    for (int k = gread(v.fb_ptr + q); k < b1; ++k)
-        cnt += lds_ld(&lb[gread(v.fb + k)]) >= 1;
+    const int b1 = gread(m->fb_ptr + q + 1);
+    for (int k = gread(m->fb_ptr + q); k < b1; ++k)
+        cnt += dom(st, gread(m->fb + k)).x >= 1;
     f[5] = sl + (float)cnt * invN;
 }
 
@@ -606,34 +924,33 @@ __device__ __forceinline__ unsigned long long score_key(float s, int q)
 // `branch` is set, find the branching variable (smallest key among unfixed
 // decision variables).  Ends with a barrier; results in ctl[C_POSTFAIL] and
 // the 64-bit word at ctl[C_KEY] (~0 when every decision variable is fixed).
-// The store arrays are 16-byte aligned and padded to a multiple of 4
-// variables; the pad holds lb = 0, ub = 0.
+// The store is 16-byte aligned and padded to a multiple of 4 variables;
+// the pad holds (0, 0).
 // With branching 2 (learned), `fsc` is an LDS scratch of 8 floats per
 // decision variable and `ml` the lane's slice of the network.
 template <bool DL>
-__device__ void post_scan(const View<DL> &v, const int32_t *lb, const int32_t *ub, int32_t *ctl,
+__device__ void post_scan(const View<DL> &v, const int2 *st, int32_t *ctl,
                           int branching, bool branch, float *fsc = nullptr,
-                          const uint16_t *mlp = nullptr)
+                          const uint16_t *mlp = nullptr, const DevModel *m = nullptr)
 {
     const int tid = threadIdx.x, W = blockDim.x, lane = tid & 63;
     bool bad = false;
-    const int nq = (v.nvars + 3) >> 2;
-    const int4 *lb4 = reinterpret_cast<const int4 *>(lb);
-    const int4 *ub4 = reinterpret_cast<const int4 *>(ub);
+    const int nq = ((v.nvars + 3) & ~3) >> 1;     // two variables per 16 bytes
+    const int4 *s4 = reinterpret_cast<const int4 *>(st);
     for (int q = tid; q < nq; q += W) {
-        const int4 l = lb4[q], u = ub4[q];
-        bad |= (l.x > u.x) | (l.y > u.y) | (l.z > u.z) | (l.w > u.w);
+        const int4 a = s4[q];
+        bad |= (a.x > a.y) | (a.z > a.w);
     }
     unsigned long long key = ~0ull;
     if (branch && branching == 2) {
         // features of every unfixed candidate into LDS ...
         for (int q = tid; q < v.ndec; q += W) {
-            const int x = v.dec(q);
-            const bool open = lds_ld(&ub[x]) > lds_ld(&lb[x]);
+            const int2 dx = dom(st, v.dec(q));
+            const bool open = dx.y > dx.x;
             fsc[8 * q + 6] = open ? 1.f : 0.f;
             if (open) {
                 float f[kNumFeat];
-                candidate_features(v, q, lb, ub, f);
+                candidate_features(v, m, q, st, f);
 #pragma unroll
                 for (int k = 0; k < kNumFeat; ++k) fsc[8 * q + k] = f[k];
             }
@@ -653,8 +970,8 @@ __device__ void post_scan(const View<DL> &v, const int32_t *lb, const int32_t *u
         }
     } else if (branch) {
         for (int q = tid; q < v.ndec; q += W) {
-            const int x = v.dec(q);
-            const int w = lds_ld(&ub[x]) - lds_ld(&lb[x]);
+            const int2 dx = dom(st, v.dec(q));
+            const int w = dx.y - dx.x;
             if (w > 0) {
                 const unsigned long long k =
                     branching == 1 ? (unsigned long long)q
@@ -674,39 +991,29 @@ __device__ void post_scan(const View<DL> &v, const int32_t *lb, const int32_t *u
 
 // ------------------------------------------------------ store copies
 // The store of an instance with V variables occupies Vp = round_up(V, 4)
-// entries of each array; entries V..Vp-1 hold (0, 0) so that quad-wise
-// scans never see an empty interval there.
+// pairs; pairs V..Vp-1 hold (0, 0) so that the failure scan never sees an
+// empty interval there.
 
-// lb/ub <- initial box (global, V entries), padding zeroed
-__device__ __forceinline__ void load_box(int32_t *lb, int32_t *ub, const int32_t *lb0,
-                                         const int32_t *ub0, int nvars)
+// st <- initial box (global, V entries per array), padding zeroed
+__device__ __forceinline__ void load_box(int2 *st, const int32_t *lb0, const int32_t *ub0,
+                                         int nvars)
 {
     const int tid = threadIdx.x, W = blockDim.x, Vp = (nvars + 3) & ~3;
-    for (int x = tid; x < Vp; x += W) {
-        lb[x] = x < nvars ? gread(lb0 + x) : 0;
-        ub[x] = x < nvars ? gread(ub0 + x) : 0;
-    }
+    for (int x = tid; x < Vp; x += W)
+        st[x] = x < nvars ? make_int2(gread(lb0 + x), gread(ub0 + x)) : make_int2(0, 0);
 }
 
-// copy Vp entries (16-byte aligned, quad-wise) from (slb, sub) to (dlb, dub);
+// copy Vp pairs (16-byte aligned, two per int4) from src to dst;
 // SG/DG: source/destination in global memory (else LDS)
 template <bool SG, bool DG>
-__device__ __forceinline__ void copy_store(int32_t *dlb, int32_t *dub, const int32_t *slb,
-                                           const int32_t *sub, int nvars)
+__device__ __forceinline__ void copy_store(int2 *dst, const int2 *src, int nvars)
 {
-    const int tid = threadIdx.x, W = blockDim.x, nq = (nvars + 3) >> 2;
+    const int tid = threadIdx.x, W = blockDim.x, nq = ((nvars + 3) & ~3) >> 1;
+    const int4 *s4 = reinterpret_cast<const int4 *>(src);
+    int4 *d4 = reinterpret_cast<int4 *>(dst);
     for (int q = tid; q < nq; q += W) {
-        const int4 l = SG ? gread(reinterpret_cast<const int4 *>(slb) + q)
-                          : reinterpret_cast<const int4 *>(slb)[q];
-        const int4 u = SG ? gread(reinterpret_cast<const int4 *>(sub) + q)
-                          : reinterpret_cast<const int4 *>(sub)[q];
-        if (DG) {
-            gwrite4(reinterpret_cast<int4 *>(dlb) + q, l);
-            gwrite4(reinterpret_cast<int4 *>(dub) + q, u);
-        } else {
-            reinterpret_cast<int4 *>(dlb)[q] = l;
-            reinterpret_cast<int4 *>(dub)[q] = u;
-        }
+        const int4 a = SG ? gread(s4 + q) : s4[q];
+        if (DG) gwrite4(d4 + q, a); else d4[q] = a;
     }
 }
 
@@ -720,16 +1027,15 @@ __global__ __launch_bounds__(1024) void features_kernel(const DevModel *mp, int 
     extern __shared__ __align__(16) char smem[];
     const DevModel m = *mp;
     const int tid = threadIdx.x, W = blockDim.x;
-    int32_t *lb = reinterpret_cast<int32_t *>(smem);
-    int32_t *ub = lb + ((m.nvars + 3) & ~3);
+    int2 *st = reinterpret_cast<int2 *>(smem);
     const View<false> v = view_global(m);
     for (int box = blockIdx.x; box < nbox; box += gridDim.x) {
         const size_t off = (size_t)box * m.nvars;
-        load_box(lb, ub, lb_in + off, ub_in + off, m.nvars);
+        load_box(st, lb_in + off, ub_in + off, m.nvars);
         lds_barrier();
         for (int q = tid; q < m.ndec; q += W) {
             float f[kNumFeat];
-            candidate_features(v, q, lb, ub, f);
+            candidate_features(v, mp, q, st, f);
             for (int k = 0; k < kNumFeat; ++k)
                 out[((size_t)box * m.ndec + q) * kNumFeat + k] = f[k];
         }
@@ -740,7 +1046,7 @@ __global__ __launch_bounds__(1024) void features_kernel(const DevModel *mp, int 
 hipError_t launch_features(const DevModel *m_dev, int nvars, int nbox, const int32_t *lb_in,
                            const int32_t *ub_in, float *out, hipStream_t stream)
 {
-    const size_t lds = 2 * sizeof(int32_t) * (size_t)((nvars + 3) & ~3);
+    const size_t lds = sizeof(int2) * (size_t)((nvars + 3) & ~3);
     const int grid = nbox < 2048 ? nbox : 2048;
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(features_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -763,22 +1069,25 @@ __global__ __launch_bounds__(1024) void propagate_batch_kernel(
     const DevModel m = *mp;
     const int tid = threadIdx.x, W = blockDim.x;
     int32_t *ctl = reinterpret_cast<int32_t *>(smem);
-    int32_t *lb = ctl + kCtlWords;
-    int32_t *ub = lb + ((m.nvars + 3) & ~3);
-    char *dsc = reinterpret_cast<char *>(ub + ((m.nvars + 3) & ~3));
+    int2 *st = reinterpret_cast<int2 *>(ctl + kCtlWords);
+    char *dsc = reinterpret_cast<char *>(st + ((m.nvars + 3) & ~3));
     View<DL> v;
     if constexpr (DL) v = stage_descriptors(m, dsc); else v = view_global(m);
+    const NodeLists L{{nullptr, nullptr, nullptr, nullptr}, {m.ndiff, m.nreif, m.nrows, m.nbrows},
+                      m.nterms + m.nbterms, {nullptr, nullptr, nullptr, nullptr}, nullptr};
     for (int box = blockIdx.x; box < nbox; box += gridDim.x) {
         const size_t off = (size_t)box * m.nvars;
-        load_box(lb, ub, lb_in + off, ub_in + off, m.nvars);
+        load_box(st, lb_in + off, ub_in + off, m.nvars);
         uint32_t nsw = 0;
+        unsigned long long ex[4] = {0, 0, 0, 0};
         lds_barrier();
-        const int st = propagate_wg(v, lb, ub, ctl, nsw);
-        post_scan(v, lb, ub, ctl, 0, false);
-        const int failed = st | lds_ld(&ctl[C_POSTFAIL]);
+        const int rc = propagate_wg<DL, false>(v, st, ctl, L, nsw, ex);
+        post_scan(v, st, ctl, 0, false);
+        const int failed = rc | lds_ld(&ctl[C_POSTFAIL]);
         for (int x = tid; x < m.nvars; x += W) {
-            gwrite(lb_out + off + x, lb[x]);
-            gwrite(ub_out + off + x, ub[x]);
+            const int2 d = st[x];
+            gwrite(lb_out + off + x, d.x);
+            gwrite(ub_out + off + x, d.y);
         }
         if (tid == 0) {
             status[box] = failed;
@@ -845,11 +1154,11 @@ __device__ inline RecHdr *q_slot(const SearchParams &P, unsigned long long pos)
 
 // FNV-1a 64 over the little-endian bytes, finalised by MurmurHash3 fmix64.
 template <bool DL>
-__device__ unsigned long long solution_hash(const int32_t *lb, const View<DL> &v, int n)
+__device__ unsigned long long solution_hash(const int2 *st, const View<DL> &v, int n)
 {
     unsigned long long h = 0xcbf29ce484222325ull;
     for (int i = 0; i < n; ++i) {
-        const uint32_t val = (uint32_t)lb[v.dec(i)];
+        const uint32_t val = (uint32_t)st[v.dec(i)].x;
         for (int k = 0; k < 4; ++k) {
             h ^= (val >> (8 * k)) & 0xffu;
             h *= 0x100000001b3ull;
@@ -864,13 +1173,13 @@ __device__ unsigned long long solution_hash(const int32_t *lb, const View<DL> &v
 }
 
 // apply decision word (var | side << 16, val) to the store as a join
-__device__ __forceinline__ void apply_decision(int32_t *lb, int32_t *ub, int2 dcs)
+__device__ __forceinline__ void apply_decision(int2 *st, int2 dcs)
 {
     const int x = dcs.x & 0xffff;
     if (dcs.x & kSideBit)
-        join_lb(&lb[x], dcs.y + 1);
+        tell_lb(st, x, dcs.y + 1);
     else
-        join_ub(&ub[x], dcs.y);
+        tell_ub(st, x, dcs.y);
 }
 
 // ------------------------------------------------------------ search
@@ -878,12 +1187,11 @@ __device__ __forceinline__ void apply_decision(int32_t *lb, int32_t *ub, int2 dc
 struct Lane0 {
     unsigned long long nodes, fails, sols, sweeps, don, maxd;
     unsigned long long since_flush, known_total, pf_qt, pf_qh;
+    unsigned long long ex[4];     // items run per kind, row terms visited
     long long t_start;
     int32_t local_best, pf_best, pf_abort, pf_idle, idle_reg, pad;
 };
 static_assert(sizeof(Lane0) <= 4 * (kCtlWords - 32), "Lane0 must fit in the control block");
-
-__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // lane 0: publish this workgroup's counters for instance `is`
 __device__ void flush_counters(Lane0 &z, InstState *is, int mode)
@@ -893,14 +1201,19 @@ __device__ void flush_counters(Lane0 &z, InstState *is, int mode)
     g_add(&is->sweeps, z.sweeps);
     g_add(&is->donations, z.don);
     g_add(&is->pops, 1ull);
+    for (int k = 0; k < 4; ++k) g_add(&is->ex[k], z.ex[k]);
     if (mode == 1) g_add(&is->solutions, z.sols);
     __hip_atomic_fetch_max(&is->max_depth, z.maxd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     z.nodes = z.fails = z.sweeps = z.don = z.sols = z.maxd = 0;
+    z.ex[0] = z.ex[1] = z.ex[2] = z.ex[3] = 0;
 }
 
 // Persistent kernel: every workgroup loops { take a subtree record; DFS it }
 // until the queue is empty and no subtree is in progress, or a limit hits.
-template <bool DL, bool RL, bool LEARN>
+// LIVE: item lists (see propagate_wg) in three LDS buffers: R holds the
+// items the subtree root kept, A and B alternate down the current path; a
+// backtrack restarts from R, as the store restarts from the root's.
+template <bool DL, bool RL, bool LEARN, bool LIVE>
 __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
 {
     extern __shared__ __align__(16) char smem[];
@@ -908,28 +1221,32 @@ __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
     const int Vp = (P.max_vars + 3) & ~3;
     int32_t *ctl = reinterpret_cast<int32_t *>(smem);
     Lane0 &z = *reinterpret_cast<Lane0 *>(ctl + 32);
-    int32_t *lb = ctl + kCtlWords;
-    int32_t *ub = lb + Vp;
-    int32_t *rlb, *rub;
-    char *after;
+    int2 *st = reinterpret_cast<int2 *>(ctl + kCtlWords);
+    int2 *rst;
+    char *p;
     if (RL) {
-        rlb = ub + Vp;
-        rub = rlb + Vp;
-        after = reinterpret_cast<char *>(rub + Vp);
+        rst = st + Vp;
+        p = reinterpret_cast<char *>(rst + Vp);
     } else {
-        rlb = P.root_scratch + (size_t)blockIdx.x * 2 * Vp;
-        rub = rlb + Vp;
-        after = reinterpret_cast<char *>(ub + Vp);
+        rst = reinterpret_cast<int2 *>(P.root_scratch) + (size_t)blockIdx.x * Vp;
+        p = reinterpret_cast<char *>(st + Vp);
     }
-    int2 *stack = reinterpret_cast<int2 *>(after);
-    const bool learned = LEARN;   // the host picks this variant only with weights
-    float *fsc = reinterpret_cast<float *>(reinterpret_cast<char *>(after) +
-                                           align16(sizeof(int2) * (size_t)P.max_depth));
-    char *dsc = reinterpret_cast<char *>(fsc) + (learned ? align16(32 * (size_t)P.max_ndec) : 0);
-    const int branching = learned ? 2 : (P.branching == 1 ? 1 : 0);
+    int2 *stack = reinterpret_cast<int2 *>(p);
+    p += align16(sizeof(int2) * (size_t)P.max_depth);
+    float *fsc = reinterpret_cast<float *>(p);
+    if (LEARN) p += align16(32 * (size_t)P.max_ndec);
+    uint16_t *lbuf = reinterpret_cast<uint16_t *>(p);
+    const int lcap = (int)(align16(2 * (size_t)(P.max_items[0] + P.max_items[1] + P.max_items[2] +
+                                                P.max_items[3])) / 2);
+    if (LIVE) p += 2 * 3 * (size_t)lcap;
+    char *dsc = p;
+    const int koff[kKinds] = {0, P.max_items[0], P.max_items[0] + P.max_items[1],
+                              P.max_items[0] + P.max_items[1] + P.max_items[2]};
+    const int branching = LEARN ? 2 : (P.branching == 1 ? 1 : 0);
 
     if (tid == 0) {
         z.nodes = z.fails = z.sols = z.sweeps = z.don = z.maxd = 0;
+        z.ex[0] = z.ex[1] = z.ex[2] = z.ex[3] = 0;
         z.since_flush = z.known_total = z.pf_qt = z.pf_qh = 0;
         z.t_start = g_load(&P.g->t_start);
         z.local_best = INT32_MAX;
@@ -985,10 +1302,10 @@ __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
             cur_inst = inst;
         }
         const int nvars = m.nvars, ndec = m.ndec, objective = m.objective;
-        load_box(lb, ub, m.lb0, m.ub0, nvars);
+        load_box(st, m.lb0, m.ub0, nvars);
         lds_barrier();
         for (int i = tid; i < len; i += W)
-            apply_decision(lb, ub, stack[i]);
+            apply_decision(st, stack[i]);
         full_barrier();  // every lane is done reading the record
         if (tid == 0)
             q_release_slot(P, (unsigned long long)pos);
@@ -997,6 +1314,8 @@ __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
         int depth = len;
         bool first = true;
         bool finished = false;
+        // item lists: 0 = whole tables, 1 = R, 2 = A, 3 = B
+        int in_sel = 0, out_sel = 1;
         InstState *is = &P.inst[inst];
         if (tid == 0) {
             z.pf_best = g_load(&is->best);
@@ -1022,7 +1341,7 @@ __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
                 if (!stop && P.mode == 1) {
                     if (z.pf_best < z.local_best) z.local_best = z.pf_best;
                     if (z.local_best != INT32_MAX)
-                        join_ub(&ub[objective], z.local_best - 1);
+                        tell_ub(st, objective, z.local_best - 1);
                 }
                 // loads consumed at the next node, so their latency overlaps
                 // this node's propagation
@@ -1037,16 +1356,40 @@ __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
             lds_barrier();
             if (uni(lds_ld(&ctl[C_STOP])))
                 break;
+            NodeLists L;
+            if (LIVE && in_sel != 0) {
+                const int32_t *c = ctl + C_CNT + kListWords * (in_sel - 1);
+                uint16_t *b = lbuf + (size_t)(in_sel - 1) * lcap;
+                for (int k = 0; k < kKinds; ++k) {
+                    L.in[k] = b + koff[k];
+                    L.nin[k] = uni(lds_ld(&c[k]));
+                }
+                L.tin = uni(lds_ld(&c[kKinds]));
+            } else {
+                for (int k = 0; k < kKinds; ++k) L.in[k] = nullptr;
+                L.nin[0] = v.ndiff; L.nin[1] = v.nreif; L.nin[2] = v.nrows; L.nin[3] = v.nbrows;
+                L.tin = v.nterms + v.nbterms;
+            }
+            if (LIVE) {
+                uint16_t *b = lbuf + (size_t)(out_sel - 1) * lcap;
+                for (int k = 0; k < kKinds; ++k) L.out[k] = b + koff[k];
+                L.cnt = ctl + C_CNT + kListWords * (out_sel - 1);
+            } else {
+                for (int k = 0; k < kKinds; ++k) L.out[k] = nullptr;
+                L.cnt = nullptr;
+            }
             uint32_t nsw = 0;
-            const int st = propagate_wg(v, lb, ub, ctl, nsw);
-            post_scan(v, lb, ub, ctl, branching, st == 0, fsc, P.mlp);
-            const int failed = uni(st | lds_ld(&ctl[C_POSTFAIL]));
+            unsigned long long ex[4] = {0, 0, 0, 0};
+            const int rc = propagate_wg<DL, LIVE>(v, st, ctl, L, nsw, ex);
+            post_scan(v, st, ctl, branching, rc == 0, fsc, P.mlp, &m);
+            const int failed = uni(rc | lds_ld(&ctl[C_POSTFAIL]));
             const unsigned long long key =
                 *reinterpret_cast<volatile unsigned long long *>(ctl + C_KEY);
             if (tid == 0) {
                 z.nodes += 1;
                 z.since_flush += 1;
                 z.sweeps += nsw;
+                for (int k = 0; k < 4; ++k) z.ex[k] += ex[k];
                 if ((unsigned long long)depth > z.maxd) z.maxd = depth;
                 if (z.since_flush >= 256) {
                     z.known_total = g_add(&P.g->nodes_total, z.since_flush) + z.since_flush;
@@ -1064,10 +1407,10 @@ __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
                         const unsigned long long idx = g_add(&is->solutions, 1ull);
                         if (P.sol_buf && (long long)idx < P.sol_cap)
                             for (int q = 0; q < ndec; ++q)
-                                P.sol_buf[(size_t)idx * ndec + q] = lb[v.dec(q)];
-                        g_add(&is->sol_hash, solution_hash(lb, v, ndec));
+                                P.sol_buf[(size_t)idx * ndec + q] = st[v.dec(q)].x;
+                        g_add(&is->sol_hash, solution_hash(st, v, ndec));
                     } else {
-                        const int32_t obj = lb[objective];
+                        const int32_t obj = st[objective].x;
                         if (obj < z.local_best) z.local_best = obj;
                         const int32_t old = __hip_atomic_fetch_min(
                             &is->best, obj, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
@@ -1076,7 +1419,7 @@ __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
                             while (!g_cas(&is->best_lock, zz, 1)) { zz = 0; __builtin_amdgcn_s_sleep(1); }
                             if (obj < is->pad[0]) {
                                 for (int q = 0; q < ndec; ++q)
-                                    P.best_vals[(size_t)inst * P.max_ndec + q] = lb[v.dec(q)];
+                                    P.best_vals[(size_t)inst * P.max_ndec + q] = st[v.dec(q)].x;
                                 is->pad[0] = obj;
                                 is->best_owner = blockIdx.x;
                             }
@@ -1098,16 +1441,20 @@ __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
                 }
                 if (first) {
                     // the subtree root's fixed point, kept for recomputation
-                    copy_store<false, !RL>(rlb, rub, lb, ub, nvars);
+                    copy_store<false, !RL>(rst, st, nvars);
                     first = false;
                     if (!RL) full_barrier(); else lds_barrier();
+                }
+                if (LIVE) {
+                    in_sel = out_sel;
+                    out_sel = out_sel == 2 ? 3 : 2;
                 }
                 if (tid == 0) {
                     const int q = (int)(uint32_t)(key & 0xffffffffull);
                     const int x = v.dec(q);
-                    const int val = lb[x];
+                    const int val = st[x].x;
                     stack[depth] = make_int2(x, val);
-                    ub[x] = val;  // left child: x = lb(x)
+                    st[x].y = val;  // left child: x = lb(x)
                     // donate the open right branch closest to the subtree
                     // root when other workgroups are waiting for work
                     if (P.donate && z.pf_idle > 0 && z.pf_qt - z.pf_qh < (unsigned long long)z.pf_idle) {
@@ -1157,10 +1504,14 @@ __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
             }
             depth = nd;
             // recompute: subtree root fixed point + decisions below it
-            copy_store<!RL, false>(lb, ub, rlb, rub, nvars);
+            copy_store<!RL, false>(st, rst, nvars);
+            if (LIVE) {
+                in_sel = 1;
+                out_sel = 2;
+            }
             lds_barrier();
             for (int i = depth0 + tid; i < depth; i += W)
-                apply_decision(lb, ub, stack[i]);
+                apply_decision(st, stack[i]);
             lds_barrier();
         }
         // ---- subtree done (or abandoned): publish counters
@@ -1191,6 +1542,7 @@ __global__ void init_search_kernel(SearchParams P)
         InstState &s = P.inst[i];
         s.nodes = s.fails = s.solutions = s.sweeps = 0;
         s.donations = s.pops = s.sol_hash = s.max_depth = 0;
+        s.ex[0] = s.ex[1] = s.ex[2] = s.ex[3] = 0;
         s.t_done = 0;
         s.best = INT32_MAX;
         s.outstanding = 1;
@@ -1437,13 +1789,14 @@ hipError_t launch_mlp_scores(const float *params, const uint16_t *wbf, int use_b
 
 // ------------------------------------------------------------ launchers
 size_t search_lds_bytes(int max_vars, int max_depth, size_t max_desc, bool desc_lds, bool root_lds,
-                        int feat_ndec)
+                        int feat_ndec, int list_items)
 {
     const size_t Vp = (size_t)((max_vars + 3) & ~3);
-    size_t b = sizeof(int32_t) * kCtlWords + 2 * Vp * sizeof(int32_t);
-    if (root_lds) b += 2 * Vp * sizeof(int32_t);
+    size_t b = sizeof(int32_t) * kCtlWords + Vp * sizeof(int2);
+    if (root_lds) b += Vp * sizeof(int2);
     b += align16(sizeof(int2) * (size_t)max_depth);
     if (feat_ndec > 0) b += align16(32 * (size_t)feat_ndec);
+    if (list_items > 0) b += 3 * align16(sizeof(uint16_t) * (size_t)list_items);
     if (desc_lds) b += max_desc;
     return align16(b);
 }
@@ -1451,14 +1804,15 @@ size_t search_lds_bytes(int max_vars, int max_depth, size_t max_desc, bool desc_
 size_t propagate_lds_bytes(int nvars, size_t desc, bool desc_lds)
 {
     const size_t Vp = (size_t)((nvars + 3) & ~3);
-    size_t b = sizeof(int32_t) * kCtlWords + 2 * Vp * sizeof(int32_t);
+    size_t b = sizeof(int32_t) * kCtlWords + Vp * sizeof(int2);
     if (desc_lds) b += desc;
     return align16(b);
 }
 
-size_t model_desc_bytes(int ndiff, int nreif, int nrows, int nterms, int ndec)
+size_t model_desc_bytes(int ndiff, int nreif, int nrows, int nterms, int ndec, int nbrows,
+                        int nbslots)
 {
-    return desc_bytes(ndiff, nreif, nrows, nterms, ndec);
+    return desc_bytes(ndiff, nreif, nrows, nterms, ndec, nbrows, nbslots);
 }
 
 // Raise the kernel's dynamic-LDS limit where the runtime supports it; a
@@ -1491,31 +1845,33 @@ hipError_t launch_propagate_batch(const DevModel *m_dev, int nbox, const int32_t
     return hipGetLastError();
 }
 
-// the search kernel variant for a layout and branching rule
-static const void *search_fn(bool desc_lds, bool root_lds, bool learned)
+// the search kernel variant for a layout, branching rule and list mode
+template <bool L, bool V>
+static const void *search_fn_lv(bool desc_lds, bool root_lds)
 {
-#define PCCP_FN(a, b, c) reinterpret_cast<const void *>(search_kernel<a, b, c>)
-    if (learned) {
-        if (desc_lds && root_lds) return PCCP_FN(true, true, true);
-        if (desc_lds) return PCCP_FN(true, false, true);
-        if (root_lds) return PCCP_FN(false, true, true);
-        return PCCP_FN(false, false, true);
-    }
-    if (desc_lds && root_lds) return PCCP_FN(true, true, false);
-    if (desc_lds) return PCCP_FN(true, false, false);
-    if (root_lds) return PCCP_FN(false, true, false);
-    return PCCP_FN(false, false, false);
-#undef PCCP_FN
+    if (desc_lds && root_lds) return reinterpret_cast<const void *>(search_kernel<true, true, L, V>);
+    if (desc_lds) return reinterpret_cast<const void *>(search_kernel<true, false, L, V>);
+    if (root_lds) return reinterpret_cast<const void *>(search_kernel<false, true, L, V>);
+    return reinterpret_cast<const void *>(search_kernel<false, false, L, V>);
 }
 
-hipError_t launch_search(const SearchParams &P, int grid, int block, size_t lds, bool desc_lds,
-                         bool root_lds, hipStream_t stream)
+static const void *search_fn(const SearchShape &k)
+{
+    if (k.learned)
+        return k.live ? search_fn_lv<true, true>(k.desc_lds, k.root_lds)
+                      : search_fn_lv<true, false>(k.desc_lds, k.root_lds);
+    return k.live ? search_fn_lv<false, true>(k.desc_lds, k.root_lds)
+                  : search_fn_lv<false, false>(k.desc_lds, k.root_lds);
+}
+
+hipError_t launch_search(const SearchParams &P, int grid, int block, size_t lds,
+                         const SearchShape &k, hipStream_t stream)
 {
     const int n = P.qcap > P.ninst ? P.qcap : P.ninst;
     hipLaunchKernelGGL(init_search_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, P);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const void *fn = search_fn(desc_lds, root_lds, P.branching == 2 && P.mlp != nullptr);
+    const void *fn = search_fn(k);
     e = set_lds_limit(fn, lds);
     if (e != hipSuccess) return e;
     SearchParams p = P;
@@ -1528,9 +1884,9 @@ hipError_t launch_search(const SearchParams &P, int grid, int block, size_t lds,
 // The same two launches as one hipGraph (two kernel nodes, the search
 // depending on the initialisation; no memset nodes).
 hipError_t build_search_graph(const SearchParams &P, int grid, int block, size_t lds,
-                              bool desc_lds, bool root_lds, hipGraphExec_t *exec)
+                              const SearchShape &k, hipGraphExec_t *exec)
 {
-    const void *fn = search_fn(desc_lds, root_lds, P.branching == 2 && P.mlp != nullptr);
+    const void *fn = search_fn(k);
     hipError_t e = set_lds_limit(fn, lds);
     if (e != hipSuccess) return e;
     hipGraph_t g = nullptr;
@@ -1560,10 +1916,9 @@ hipError_t build_search_graph(const SearchParams &P, int grid, int block, size_t
     return e;
 }
 
-hipError_t search_occupancy(int block, size_t lds, bool desc_lds, bool root_lds, bool learned,
-                            int *wgs_per_cu)
+hipError_t search_occupancy(int block, size_t lds, const SearchShape &k, int *wgs_per_cu)
 {
-    const void *fn = search_fn(desc_lds, root_lds, learned);
+    const void *fn = search_fn(k);
     hipError_t e = set_lds_limit(fn, lds);
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, fn, block, lds);

@@ -7,9 +7,12 @@
 
 namespace pccp {
 
-size_t model_desc_bytes(int ndiff, int nreif, int nrows, int nterms, int ndec);
+size_t model_desc_bytes(int ndiff, int nreif, int nrows, int nterms, int ndec, int nbrows,
+                        int nbslots);
+// list_items: sum over kinds of the largest table in the launch when the
+// search keeps item lists (three LDS buffers of 16-bit indices), else 0
 size_t search_lds_bytes(int max_vars, int max_depth, size_t max_desc, bool desc_lds, bool root_lds,
-                        int feat_ndec);
+                        int feat_ndec, int list_items);
 size_t propagate_lds_bytes(int nvars, size_t desc, bool desc_lds);
 
 hipError_t launch_propagate_batch(const DevModel *m_dev, int nbox, const int32_t *lb_in,
@@ -17,11 +20,17 @@ hipError_t launch_propagate_batch(const DevModel *m_dev, int nbox, const int32_t
                                   int32_t *status, int32_t *sweeps, int grid, int block,
                                   size_t lds, bool desc_lds, hipStream_t stream);
 
-hipError_t launch_search(const SearchParams &P, int grid, int block, size_t lds, bool desc_lds,
-                         bool root_lds, hipStream_t stream);
+// Which search-kernel variant: descriptor tables in LDS, subtree-root store
+// in LDS, learned branching, item lists of non-entailed propagators.
+struct SearchShape {
+    bool desc_lds = false, root_lds = false, learned = false, live = false;
+};
+
+hipError_t launch_search(const SearchParams &P, int grid, int block, size_t lds,
+                         const SearchShape &k, hipStream_t stream);
 
 hipError_t build_search_graph(const SearchParams &P, int grid, int block, size_t lds,
-                              bool desc_lds, bool root_lds, hipGraphExec_t *exec);
+                              const SearchShape &k, hipGraphExec_t *exec);
 
 hipError_t launch_features(const DevModel *m_dev, int nvars, int nbox, const int32_t *lb_in,
                            const int32_t *ub_in, float *out, hipStream_t stream);
@@ -36,7 +45,6 @@ hipError_t launch_mlp_sync_bf16(const float *params, uint16_t *wbf, hipStream_t 
 hipError_t launch_mlp_scores(const float *params, const uint16_t *wbf, int use_bf16,
                              const float *feat, int ncand, float *scores, hipStream_t stream);
 
-hipError_t search_occupancy(int block, size_t lds, bool desc_lds, bool root_lds, bool learned,
-                            int *wgs_per_cu);
+hipError_t search_occupancy(int block, size_t lds, const SearchShape &k, int *wgs_per_cu);
 
 }  // namespace pccp

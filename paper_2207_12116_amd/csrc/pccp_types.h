@@ -14,7 +14,7 @@ namespace pccp {
 
 constexpr int kMaxVars = 65535;
 constexpr int kMaxWg = 1024;
-constexpr int kCtlWords = 64;   // LDS control block (int32 words)
+constexpr int kCtlWords = 96;   // LDS control block (int32 words)
 
 // Kind 1 - difference row  x - y <= c  (a linear row with coefficients
 // +1 / -1; every precedence s_i + d_i <= s_j is one).
@@ -24,18 +24,28 @@ constexpr int kCtlWords = 64;   // LDS control block (int32 words)
 // Kind 3 - general linear row  sum_t a_t x_t <= rhs.
 //   row = {first term, number of terms, rhs, 0}; term = var | (a << 16)
 //   (a as int16, nonzero)
+// Kind 4 - Boolean knapsack row  sum_t a_t b_t <= rhs, every b_t with an
+//   initial domain inside [0, 1] and every a_t > 0 (kind 3's rule on 0/1
+//   domains).  row = {rhs, number of terms}; terms row-major with a fixed
+//   stride of bgroup * bchunks slots per row, term = var | (a << 16), the
+//   unused slots of a row hold 0 (a = 0).
 struct DevModel {
     int32_t nvars;
     int32_t ndiff, nreif, nrows, nterms;
     int32_t ndec, objective;
     int32_t row_group;            // lanes per linear row in a sweep (4, 8 or 16)
     int32_t row_chunks;           // ceil(longest row / row_group)
+    int32_t nbrows;               // kind 4 rows
+    int32_t bgroup, bchunks;      // kind 4: lanes per row, term slots per lane
+    int32_t nbterms;              // kind 4 terms (without the padding)
     int32_t pad0;
     const int32_t *lb0, *ub0;     // initial box
     const int2 *diff;             // kind 1
     const int2 *reif;             // kind 2
     const int4 *rows;             // kind 3 rows
     const uint32_t *terms;        // kind 3 terms
+    const int2 *brows;            // kind 4 rows {rhs, len}
+    const uint32_t *bterms;       // kind 4 terms [nbrows * bgroup * bchunks]
     const int32_t *dec;           // decision variables (tie-break order)
     // learned branching: per decision variable q, fstat[8q..8q+4] =
     // {lo, 1/H, degree share, static load, 1/N}; rows x - y <= c leaving
@@ -56,6 +66,9 @@ constexpr int kNumParams = kHidden * kNumFeat + kHidden + kHidden + 1;  // 513
 struct InstState {
     unsigned long long nodes, fails, solutions, sweeps;
     unsigned long long donations, pops, sol_hash, max_depth;
+    unsigned long long ex[4];   // propagator executions: difference rows,
+                                // reified items, linear rows (kinds 3 and 4);
+                                // row terms
     long long t_done;           // wall-clock tick when the last subtree finished (0 = not done)
     int32_t best;               // MINIMIZE: best objective so far (INT32_MAX = none)
     int32_t outstanding;        // subtrees queued or in progress
@@ -100,7 +113,7 @@ struct SearchParams {
     char *q_data;               // [qcap * slot_bytes]
     int32_t qcap;
     int32_t slot_bytes;
-    int32_t *root_scratch;      // [grid * 2 * max_vars] (global subproblem roots)
+    int32_t *root_scratch;      // [grid * 2 * Vp] (global subproblem roots, (lb, ub) pairs)
     int32_t max_vars;           // largest instance in the launch
     int32_t donate;             // allow donation (0 in single-workgroup runs)
     long long node_limit;       // 0 = none
@@ -112,6 +125,7 @@ struct SearchParams {
     int32_t max_ndec;
     int32_t pad;
     const uint16_t *mlp;        // learned branching: bf16 parameters (513), or null
+    int32_t max_items[4];       // largest table per kind in the launch (item lists)
 };
 
 }  // namespace pccp

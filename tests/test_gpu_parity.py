@@ -164,14 +164,21 @@ def _gpu_counts(s):
     return (st["nodes"], st["fails"], st["solutions"], st["best"])
 
 
+# item lists on (1) and off (2): dropping entailed propagators must leave
+# every fixed point, and so every counter of the search, unchanged
+LIVE = pytest.mark.parametrize("live", [1, 2], ids=["lists", "tables"])
+
+
+@LIVE
 @pytest.mark.parametrize("seed,dom", [(0, 10), (1, 12), (3, 11), (6, 9)])
-def test_single_wg_enumerate(P, seed, dom):
+def test_single_wg_enumerate(P, seed, dom, live):
     model = I.tiny_csp(seed, dom=dom)
     ref = O.solve(model, sol_cap=10**6)
-    say("enumerate 1wg", seed, dom, ref["solutions"])
-    s = P.Solver(model, num_wgs=1, sol_cap=10**6)
+    say("enumerate 1wg", seed, dom, live, ref["solutions"])
+    s = P.Solver(model, num_wgs=1, sol_cap=10**6, live=live)
     out = s.solve(time_limit=60)
     assert out == P.OUT_ALL
+    assert s.stats()["live"] == (live == 1)
     assert _gpu_counts(s) == _oracle_counts(ref)
     st = s.stats()
     assert st["sol_hash"] == ref["sol_hash"]
@@ -179,12 +186,13 @@ def test_single_wg_enumerate(P, seed, dom):
     assert np.array_equal(sols, ref["solutions_list"])   # same order: sequential DFS
 
 
+@LIVE
 @pytest.mark.parametrize("n,seed", [(4, 0), (5, 1), (6, 2), (6, 3), (8, 4), (10, 5)])
-def test_single_wg_minimize(P, n, seed):
+def test_single_wg_minimize(P, n, seed, live):
     model = I.tiny_rcpsp(n, seed)
     ref = O.solve(model)
-    say("minimize 1wg", n, seed, ref["nodes"])
-    s = P.Solver(model, num_wgs=1)
+    say("minimize 1wg", n, seed, live, ref["nodes"])
+    s = P.Solver(model, num_wgs=1, live=live)
     out = s.solve(time_limit=60)
     assert out == P.OUT_OPTIMAL
     assert _gpu_counts(s) == _oracle_counts(ref)
@@ -193,28 +201,61 @@ def test_single_wg_minimize(P, n, seed):
     assert ok and ms == obj == ref["best"]
 
 
+@LIVE
 @pytest.mark.parametrize("n,seed,limit", [(30, 0, 3000), (30, 4, 2000), (60, 1, 800)])
-def test_single_wg_node_limited_prefix(P, n, seed, limit):
+def test_single_wg_node_limited_prefix(P, n, seed, limit, live):
     """Both searches stop after exactly `limit` nodes of the same depth-first
     order, so every counter and the incumbent agree."""
     model = I.rcpsp(n, seed)
     ref = O.solve(model, node_limit=limit)
-    say("prefix 1wg", n, seed, limit)
-    s = P.Solver(model, num_wgs=1)
+    say("prefix 1wg", n, seed, limit, live)
+    s = P.Solver(model, num_wgs=1, live=live)
     out = s.solve(node_limit=limit, time_limit=60)
     assert out == P.OUT_LIMIT and ref["outcome"] == O.OUT_LIMIT
     assert _gpu_counts(s) == _oracle_counts(ref)
     assert s.stats()["max_depth"] == ref["max_depth"]
 
 
+def test_lists_cut_executions_not_nodes(P):
+    """The same node-limited single-workgroup prefix with and without item
+    lists: identical search counters, fewer propagator executions with them,
+    and with tables every sweep runs every propagator."""
+    model = I.rcpsp(30, 0)
+    res = {}
+    for live in (1, 2):
+        s = P.Solver(model, num_wgs=1, live=live)
+        assert s.solve(node_limit=2000, time_limit=60) == P.OUT_LIMIT
+        res[live] = s.stats()
+    a, b = res[1], res[2]
+    assert (a["nodes"], a["fails"], a["solutions"], a["best"], a["max_depth"]) == \
+        (b["nodes"], b["fails"], b["solutions"], b["best"], b["max_depth"])
+    nd, nr = _ndiff(model), len(model.reif)
+    assert b["prop_reified"] == b["sweeps"] * nr
+    assert b["prop_linear2"] == b["sweeps"] * nd
+    say("executions per node, lists vs tables:",
+        (a["prop_linear2"] + a["prop_reified"] + a["prop_linear"]) / a["nodes"],
+        (b["prop_linear2"] + b["prop_reified"] + b["prop_linear"]) / b["nodes"])
+    assert a["prop_reified"] < b["prop_reified"]
+    assert a["prop_linear2"] + a["prop_reified"] + a["prop_linear"] < \
+        b["prop_linear2"] + b["prop_reified"] + b["prop_linear"]
+
+
+def _ndiff(model):
+    """Rows x - y <= c (two terms, coefficients +1 and -1)."""
+    p, a = np.asarray(model.lin_ptr), np.asarray(model.lin_coef)
+    return sum(1 for i in range(len(p) - 1)
+               if p[i + 1] - p[i] == 2 and sorted(a[p[i]:p[i + 1]].tolist()) == [-1, 1])
+
+
+@LIVE
 @pytest.mark.parametrize("seed", [0, 2])
-def test_multi_wg_enumerate_full_size(P, seed):
+def test_multi_wg_enumerate_full_size(P, seed, live):
     """Tiny CSP at its stated size (8 variables over [0, 20]): the solution
     count, set hash and node count of the whole tree are schedule-free."""
     model = I.tiny_csp(seed)
     ref = O.solve(model)
-    say("enumerate multi", seed, ref["solutions"])
-    s = P.Solver(model)
+    say("enumerate multi", seed, live, ref["solutions"])
+    s = P.Solver(model, live=live)
     out = s.solve(time_limit=120)
     assert out == P.OUT_ALL
     st = s.stats()
@@ -223,12 +264,13 @@ def test_multi_wg_enumerate_full_size(P, seed):
     assert st["grid"] > 1
 
 
+@LIVE
 @pytest.mark.parametrize("n,seed", [(8, 0), (10, 1), (10, 2), (12, 3)])
-def test_multi_wg_minimize(P, n, seed):
+def test_multi_wg_minimize(P, n, seed, live):
     model = I.tiny_rcpsp(n, seed)
     ref = O.solve(model)
-    say("minimize multi", n, seed)
-    s = P.Solver(model)
+    say("minimize multi", n, seed, live)
+    s = P.Solver(model, live=live)
     out = s.solve(time_limit=60)
     assert out == P.OUT_OPTIMAL
     obj, vals = s.best()
