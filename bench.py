@@ -84,50 +84,112 @@ def algorithmic_bytes(st):
             + st["prop_terms"] * BYTES_TERM)
 
 
-def cpu_baseline(n, seed, nodes):
+def _oracle_worker(args):
+    n, seed, nodes = args
     import oracle as O
     from paper_2207_12116_amd import instances as I
     model = I.rcpsp(n, seed)
     t0 = time.perf_counter()
     r = O.solve(model, node_limit=nodes)
+    return r["nodes"], time.perf_counter() - t0
+
+
+def cpu_baseline(n, nodes, procs):
+    """The oracle's sequential DFS on `procs` instances at once (one process
+    each, seeds 0..procs-1), `nodes` nodes each: total nodes / wall time."""
+    import multiprocessing as mp
+    one_nodes, one_s = _oracle_worker((n, 0, nodes))
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(procs) as pool:
+        res = pool.map(_oracle_worker, [(n, s, nodes) for s in range(procs)])
+    wall = time.perf_counter() - t0
+    tot = sum(r[0] for r in res)
+    return {"value": tot / wall, "unit": "nodes/s", "cores": procs, "kind": "oracle",
+            "sample": f"sequential oracle DFS, {procs} processes on the {n}-task instances "
+                      f"seeds 0-{procs - 1}, first {nodes} nodes each ({wall:.1f} s wall)",
+            "single_core": {"value": one_nodes / one_s, "cores": 1,
+                            "sample": f"seed 0, first {one_nodes} nodes ({one_s:.1f} s)"}}
+
+
+def single_instance_leg(n, seed, limit, cfg):
+    """One large instance searched by the whole GPU (plain form): node and
+    propagation rates and the LDS fraction."""
+    from paper_2207_12116_amd import instances as I, pccp
+    s = pccp.Solver(I.rcpsp(n, seed), config=cfg)
+    t0 = time.perf_counter()
+    out = s.solve(pccp.MINIMIZE, time_limit=limit)
     dt = time.perf_counter() - t0
-    return {"value": r["nodes"] / dt, "unit": "nodes/s", "cores": 1, "kind": "oracle",
-            "sample": f"sequential oracle DFS on the {n}-task instance seed {seed}, "
-                      f"first {r['nodes']} nodes ({dt:.1f} s)"}
+    st = s.stats()
+    kern = st["kernel_ms"] / 1e3
+    props = st["prop_linear2"] + st["prop_reified"] + st["prop_linear"]
+    ach = algorithmic_bytes(st) / kern / 1e9
+    return {"tasks": n, "seed": seed, "nodes_per_s": round(st["nodes"] / dt, 1),
+            "propagations_per_s": round(props / dt, 1), "outcome": pccp.OUTCOME_NAMES[out],
+            "lds_achieved_GBs": round(ach, 1), "lds_frac": round(ach / LDS_PEAK_GBS, 4),
+            "grid": st["grid"], "block": st["block"], "time_s": round(dt, 3)}
 
 
-def ttpo_suite(n, seeds, limit, cfg, weights):
-    """Time to proven optimum of the same instances in three forms:
-    plain (one launch per instance, whole GPU), batched (one launch for all)
-    and learned (batched, branching on the trained network).  Instance times
-    are device-clock times from launch start to proof (the limit if not
-    proven); `total_s` is the time to prove the whole set: the sum of the
-    plain launches, the duration of the batched launch."""
+def mixed_batch_leg(count, limit, cfg):
+    """`count` instances of 30, 60 and 90 tasks (by seed mod 3) in one
+    persistent launch."""
+    from paper_2207_12116_amd import instances as I, pccp
+    models = [I.rcpsp(I.batch_sizes(s), s) for s in range(count)]
+    solvers = [pccp.Solver(m, config=cfg) for m in models]
+    t0 = time.perf_counter()
+    outs = pccp.batch_solve(solvers, pccp.MINIMIZE, config=cfg, time_limit=limit)
+    dt = time.perf_counter() - t0
+    sts = [s.stats() for s in solvers]
+    nodes = sum(x["nodes"] for x in sts)
+    props = sum(x["prop_linear2"] + x["prop_reified"] + x["prop_linear"] for x in sts)
+    proven = sum(o in (pccp.OUT_OPTIMAL, pccp.OUT_UNSAT) for o in outs)
+    return {"instances": count, "sizes": "30/60/90 by seed mod 3", "nodes_per_s": round(nodes / dt, 1),
+            "propagations_per_s": round(props / dt, 1), "proven": proven,
+            "with_incumbent": sum(x["best"] is not None for x in sts),
+            "grid": sts[0]["grid"], "block": sts[0]["block"], "time_s": round(dt, 3)}
+
+
+def ttpo_suite(n, seeds, budget, cfg, weights):
+    """Time to proven optimum of the same instances in three forms, each
+    instance allowed `budget` search nodes (then abandoned, outcome LIMIT).
+    plain: one whole-GPU launch per instance.  batched: one launch for all
+    instances.  learned: batched, branching on the trained network.
+    Per-instance TTPO is device-clock time from its launch's start to proof.
+    `total_s` is the device time to settle the whole set (sum of the plain
+    launches; the batched launch), `wall_s` the host time of the calls;
+    `plain_set_s` is the time until every instance the plain form proved is
+    proven (null if one is not), counted from the start of the set."""
     from paper_2207_12116_amd import instances as I, learn, pccp
     models = [I.rcpsp(n, s) for s in seeds]
     solved = (pccp.OUT_OPTIMAL, pccp.OUT_UNSAT)
+    safety = 120.0
 
-    def summary(times, proven, total, best):
-        g = [max(t, 1e-4) for t in times]
-        return {"proven": proven, "instances": len(times), "total_s": round(total, 4),
-                "sum_s": round(sum(times), 4),
-                "geomean_ms": round(1e3 * math.exp(sum(math.log(x) for x in g) / len(g)), 3),
+    def summary(ok, ttpo, total, wall, best, nodes, cover):
+        return {"proven": int(sum(ok)), "instances": len(ok), "total_s": round(total, 4),
+                "wall_s": round(wall, 4), "plain_set_s": None if cover is None else round(cover, 4),
+                "nodes": int(nodes), "ttpo_ms": [None if t is None else round(t, 3) for t in ttpo],
                 "best": best}
 
-    times, proven, best = [], 0, []
+    ok, ttpo, best, kern, nodes = [], [], [], [], 0
+    t0 = time.perf_counter()
     for m in models:
         s = pccp.Solver(m, config=cfg)
-        out = s.solve(pccp.MINIMIZE, time_limit=limit)
+        out = s.solve(pccp.MINIMIZE, node_limit=budget, time_limit=safety)
         st = s.stats()
-        ok = out in solved
-        proven += ok
-        times.append(st["ttpo_ms"] / 1e3 if ok else limit)
+        ok.append(out in solved)
+        ttpo.append(st["ttpo_ms"] if ok[-1] else None)
         best.append(st["best"])
-    res = {"tasks": n, "seeds": f"{seeds[0]}-{seeds[-1]}", "limit_s": limit,
-           "plain": summary(times, proven, sum(times), best)}
+        kern.append(st["kernel_ms"] / 1e3)
+        nodes += st["nodes"]
+    wall = time.perf_counter() - t0
+    # plain set: launches run one after another, so instance i is settled at
+    # the sum of the launches before it plus its own time to proof
+    starts = [sum(kern[:i]) for i in range(len(kern))]
+    cover = max((starts[i] + ttpo[i] / 1e3 for i in range(len(ok)) if ok[i]), default=0.0)
+    res = {"tasks": n, "seeds": f"{seeds[0]}-{seeds[-1]}", "node_budget": budget,
+           "plain": summary(ok, ttpo, sum(kern), wall, best, nodes, cover)}
+    plain_ok = ok
     for form in ("batched", "learned"):
         solvers = [pccp.Solver(m, config=cfg) for m in models]
-        mlp = None
         if form == "learned":
             if not os.path.exists(weights):
                 res[form] = None
@@ -135,30 +197,19 @@ def ttpo_suite(n, seeds, limit, cfg, weights):
             mlp = learn.network(weights)
             for s in solvers:
                 learn.attach(s, mlp)
-        outs = pccp.batch_solve(solvers, pccp.MINIMIZE, config=cfg, time_limit=limit)
+        t0 = time.perf_counter()
+        outs = pccp.batch_solve(solvers, pccp.MINIMIZE, config=cfg, time_limit=safety,
+                                inst_node_limit=budget)
+        wall = time.perf_counter() - t0
         sts = [s.stats() for s in solvers]
-        t = [x["ttpo_ms"] / 1e3 if o in solved else limit for o, x in zip(outs, sts)]
-        pr = sum(o in solved for o in outs)
-        total = max(t) if pr == len(t) else limit
-        res[form] = summary(t, pr, total, [x["best"] for x in sts])
+        fok = [o in solved for o in outs]
+        ft = [x["ttpo_ms"] if o else None for o, x in zip(fok, sts)]
+        cov = None
+        if all(f for f, p in zip(fok, plain_ok) if p):
+            cov = max((t / 1e3 for t, p in zip(ft, plain_ok) if p), default=0.0)
+        res[form] = summary(fok, ft, sts[0]["kernel_ms"] / 1e3, wall, [x["best"] for x in sts],
+                            sum(x["nodes"] for x in sts), cov)
     return res
-
-
-def copy_calibration(gib=2):
-    """One device-to-device copy of `gib` GiB (larger than the last-level
-    cache) through an elementwise kernel: the FETCH_SIZE / WRITE_SIZE that
-    rocprofv3 reports for it calibrate the counters' unit and overheads."""
-    import torch
-    n = gib * (1 << 30) // 4
-    src = torch.empty(n, dtype=torch.int32, device="cuda")
-    src.fill_(7)
-    dst = torch.empty_like(src)
-    flush = torch.empty(512 * (1 << 20) // 4, dtype=torch.int32, device="cuda")
-    flush.fill_(1)                      # evict src from the last-level cache
-    torch.cuda.synchronize()
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes": n * 4, "read_bytes": n * 4, "write_bytes": n * 4}))
 
 
 def main():
@@ -173,6 +224,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-nodes", type=int, default=150000)
+    ap.add_argument("--cpu-procs", type=int, default=0,
+                    help="oracle processes for the CPU baseline (0 = min(16, cores))")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the 120-task and 256-instance legs")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--desc-lds", type=int, default=0, choices=(0, 1, 2),
                     help="with --wg: descriptors 0 chosen by the library, 1 LDS, 2 global")
@@ -185,7 +240,8 @@ def main():
     ap.add_argument("--no-ttpo", action="store_true")
     ap.add_argument("--ttpo-n", type=int, default=18)
     ap.add_argument("--ttpo-seeds", type=int, default=16)
-    ap.add_argument("--ttpo-limit", type=float, default=2.0)
+    ap.add_argument("--ttpo-budget", type=int, default=30_000_000,
+                    help="search nodes each instance may use in the TTPO comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 2 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -280,14 +336,34 @@ def main():
     if not args.no_ttpo:
         from paper_2207_12116_amd import learn
         log(f"time to proven optimum: {args.ttpo_seeds} instances of {args.ttpo_n} tasks")
-        ttpo_cmp = ttpo_suite(args.ttpo_n, list(range(args.ttpo_seeds)), args.ttpo_limit, cfg,
+        ttpo_cmp = ttpo_suite(args.ttpo_n, list(range(args.ttpo_seeds)), args.ttpo_budget, cfg,
                               learn.DEFAULT_WEIGHTS)
         log(f"ttpo: {json.dumps({k: v for k, v in ttpo_cmp.items()})}")
 
+    legs = None
+    if not args.no_legs:
+        from paper_2207_12116_amd import autotune
+        log("120-task instance, whole GPU")
+        c3m = [I.rcpsp(120, 0)]
+        c3cfg, _ = autotune.tune(c3m, pccp.MINIMIZE, budget_s=0.3, cache_path=None,
+                                 wg_sizes=(256, 512, 1024), log=log)
+        legs = {"c3_120tasks": single_instance_leg(120, 0, 2.0, c3cfg)}
+        legs["c3_120tasks"]["config"] = {"wg_size": c3cfg.wg_size, "live": c3cfg.live}
+        log(f"c3: {legs['c3_120tasks']}")
+        log("256 mixed instances, one launch")
+        c4m = [I.rcpsp(I.batch_sizes(s), s) for s in range(0, 256, 16)]
+        c4cfg, _ = autotune.tune(c4m, pccp.MINIMIZE, budget_s=0.3, cache_path=None,
+                                 wg_sizes=(256, 512, 1024), log=log)
+        legs["c4_mixed256"] = mixed_batch_leg(256, 3.0, c4cfg)
+        legs["c4_mixed256"]["config"] = {"wg_size": c4cfg.wg_size, "desc_lds": c4cfg.desc_lds,
+                                         "root_lds": c4cfg.root_lds, "live": c4cfg.live}
+        log(f"c4: {legs['c4_mixed256']}")
+
     cpu = None
     if not args.no_cpu:
-        log("cpu baseline (oracle, 1 core)")
-        cpu = cpu_baseline(args.n, 0, args.cpu_nodes)
+        procs = args.cpu_procs or min(16, os.cpu_count() or 1)
+        log(f"cpu baseline (oracle, {procs} processes)")
+        cpu = cpu_baseline(args.n, args.cpu_nodes, procs)
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "nodes/s", "n_gpus": 1,
@@ -306,7 +382,7 @@ def main():
                    "autotuned": tuned, "launch": "hipGraph"},
         "propagations_per_s": round(tot_props / wall, 1),
         "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "ttpo": ttpo,
-        "ttpo_forms": ttpo_cmp,
+        "ttpo_forms": ttpo_cmp, "legs": legs,
     }
     print(json.dumps(line), flush=True)
 

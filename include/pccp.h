@@ -203,10 +203,16 @@ int32_t pccp_node_features(pccp_solver *s, int32_t nbox, const int32_t *lb, cons
                            float *feat);
 
 typedef struct {
-    int64_t node_limit;           /* 0 = none                                  */
+    int64_t node_limit;           /* 0 = none; all instances of the launch     */
     double time_limit_s;          /* 0 = none; measured on the device clock    */
     const volatile int32_t *cancel; /* host word in pinned memory polled by the
                                      search (nonzero = stop); may be NULL     */
+    int64_t inst_node_limit;      /* 0 = none; an instance that has used this
+                                     many nodes is abandoned (outcome LIMIT)
+                                     while the others go on, so a batch gives
+                                     each instance the budget a plain search
+                                     with node_limit would have; counted in
+                                     steps of up to 256 nodes per workgroup   */
 } pccp_limits;
 
 /* Propagate-and-search on this solver's model (§1, §5): mode is

@@ -17,7 +17,7 @@ import time
 from . import pccp
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pccp_autotune.json")
-WG_SIZES = (64, 128, 256, 512)
+WG_SIZES = (64, 128, 256, 512, 1024)
 PLACEMENTS = ((1, 1), (1, 2), (2, 1), (2, 2))   # (desc_lds, root_lds): 1 = LDS, 2 = HBM
 LIVES = (1, 2)                                    # item lists on, off
 

@@ -743,6 +743,7 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
     P.max_vars = max_vars;
     P.donate = sh.grid > 1 ? 1 : 0;
     P.node_limit = lim ? lim->node_limit : 0;
+    P.inst_node_limit = lim ? lim->inst_node_limit : 0;
     P.t_limit_ticks = (lim && lim->time_limit_s > 0) ? (long long)(lim->time_limit_s * s0->wall_khz * 1000.0) : 0;
     P.cancel = lim ? lim->cancel : nullptr;
     P.sol_buf = keep_sols ? s0->sols.as<int32_t>() : nullptr;
@@ -816,6 +817,10 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
                         : (is.best == INT32_MAX ? PCCP_OUT_UNSAT : PCCP_OUT_OPTIMAL);
         else
             o.outcome = g.abort == 3 ? PCCP_OUT_CANCELLED : PCCP_OUT_LIMIT;
+        if (is.abandon) {
+            o.outcome = PCCP_OUT_LIMIT;
+            o.ttpo_ms = -1.0;
+        }
         if (is.depth_overflow) overflow = true;
         outcomes[i] = o.outcome;
         s->best = is.best;

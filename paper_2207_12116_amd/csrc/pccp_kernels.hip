@@ -176,6 +176,7 @@ enum : int {
     C_STOP = 8,                             // abandon the current subproblem
     C_DEPTH = 9,                            // new depth after a backtrack (-1 = done)
     C_INST = 10, C_LEN = 11,
+    C_SKIP = 27,                            // the record taken was dropped
     C_CNT = 12,                             // item-list counts: 5 words per list
                                             // (R, A, B) = 4 kinds, row terms
 };
@@ -194,13 +195,15 @@ struct View {
     const int2 *brows_;
     const uint32_t *bterms_;
     const int32_t *dec_;
-    __device__ __forceinline__ int2 brows(int t) const { return DL ? brows_[t] : gread(brows_ + t); }
-    __device__ __forceinline__ uint32_t bterms(int t) const { return DL ? bterms_[t] : gread(bterms_ + t); }
-    __device__ __forceinline__ int2 diff(int t) const { return DL ? diff_[t] : gread(diff_ + t); }
-    __device__ __forceinline__ int2 reif(int t) const { return DL ? reif_[t] : gread(reif_ + t); }
-    __device__ __forceinline__ int4 rows(int t) const { return DL ? rows_[t] : gread(rows_ + t); }
-    __device__ __forceinline__ uint32_t terms(int t) const { return DL ? terms_[t] : gread(terms_ + t); }
-    __device__ __forceinline__ int32_t dec(int t) const { return DL ? dec_[t] : gread(dec_ + t); }
+    // Indices are non-negative: taking them as unsigned lets a global load
+    // use a uniform base plus a 32-bit per-lane offset.
+    __device__ __forceinline__ int2 brows(int t) const { return DL ? brows_[(uint32_t)t] : gread(brows_ + (uint32_t)t); }
+    __device__ __forceinline__ uint32_t bterms(int t) const { return DL ? bterms_[(uint32_t)t] : gread(bterms_ + (uint32_t)t); }
+    __device__ __forceinline__ int2 diff(int t) const { return DL ? diff_[(uint32_t)t] : gread(diff_ + (uint32_t)t); }
+    __device__ __forceinline__ int2 reif(int t) const { return DL ? reif_[(uint32_t)t] : gread(reif_ + (uint32_t)t); }
+    __device__ __forceinline__ int4 rows(int t) const { return DL ? rows_[(uint32_t)t] : gread(rows_ + (uint32_t)t); }
+    __device__ __forceinline__ uint32_t terms(int t) const { return DL ? terms_[(uint32_t)t] : gread(terms_ + (uint32_t)t); }
+    __device__ __forceinline__ int32_t dec(int t) const { return DL ? dec_[(uint32_t)t] : gread(dec_ + (uint32_t)t); }
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
@@ -215,6 +218,16 @@ __host__ __device__ inline size_t desc_bytes(int ndiff, int nreif, int nrows, in
 }
 
 // View over global memory.
+// A pointer every lane holds the same value of, kept in scalar registers.
+template <typename T>
+__device__ __forceinline__ const T *uptr(const T *p)
+{
+    const unsigned long long u = reinterpret_cast<unsigned long long>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return reinterpret_cast<const T *>(((unsigned long long)hi << 32) | lo);
+}
+
 __device__ inline View<false> view_global(const DevModel &m)
 {
     View<false> v;
@@ -222,8 +235,9 @@ __device__ inline View<false> view_global(const DevModel &m)
     v.nterms = m.nterms; v.ndec = m.ndec; v.objective = m.objective;
     v.row_group = m.row_group; v.row_chunks = m.row_chunks;
     v.nbrows = m.nbrows; v.bgroup = m.bgroup; v.bchunks = m.bchunks; v.nbterms = m.nbterms;
-    v.diff_ = m.diff; v.reif_ = m.reif; v.rows_ = m.rows; v.terms_ = m.terms; v.dec_ = m.dec;
-    v.brows_ = m.brows; v.bterms_ = m.bterms;
+    v.diff_ = uptr(m.diff); v.reif_ = uptr(m.reif); v.rows_ = uptr(m.rows);
+    v.terms_ = uptr(m.terms); v.dec_ = uptr(m.dec);
+    v.brows_ = uptr(m.brows); v.bterms_ = uptr(m.bterms);
     return v;
 }
 
@@ -1189,7 +1203,7 @@ struct Lane0 {
     unsigned long long since_flush, known_total, pf_qt, pf_qh;
     unsigned long long ex[4];     // items run per kind, row terms visited
     long long t_start;
-    int32_t local_best, pf_best, pf_abort, pf_idle, idle_reg, pad;
+    int32_t local_best, pf_best, pf_abort, pf_idle, idle_reg, pf_iabort;
 };
 static_assert(sizeof(Lane0) <= 4 * (kCtlWords - 32), "Lane0 must fit in the control block");
 
@@ -1281,12 +1295,27 @@ __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
                 ctl[C_INST] = h->inst;
                 ctl[C_LEN] = h->len;
             }
+            ctl[C_SKIP] = 0;
+            if (got >= 0 && P.inst_node_limit > 0 && g_load(&P.inst[ctl[C_INST]].abandon) != 0) {
+                // a subtree of an abandoned instance: drop it
+                InstState *ai = &P.inst[ctl[C_INST]];
+                q_release_slot(P, (unsigned long long)got);
+                if (g_add(&ai->outstanding, -1) == 1)
+                    __hip_atomic_store(&ai->t_done, (long long)wall_clock64(), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                g_add(&P.g->outstanding, -1);
+                ctl[C_SKIP] = 1;
+            }
         }
         full_barrier();
         const long long pos = (long long)(((unsigned long long)(uint32_t)uni(ctl[C_SLOT_HI]) << 32) |
                                           (uint32_t)uni(ctl[C_SLOT]));
         if (pos < 0)
             break;
+        if (uni(ctl[C_SKIP])) {
+            full_barrier();
+            continue;
+        }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const int inst = uni(ctl[C_INST]);
         const int len = uni(ctl[C_LEN]);
@@ -1320,11 +1349,13 @@ __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
         if (tid == 0) {
             z.pf_best = g_load(&is->best);
             z.pf_abort = 0;
+            z.pf_iabort = 0;
         }
+        bool abandoned = false;
         // ---- depth-first search of this subtree
         for (;;) {
             if (tid == 0) {
-                int stop = z.pf_abort != 0;
+                int stop = z.pf_abort != 0 ? 1 : (z.pf_iabort != 0 ? 2 : 0);
                 if (P.node_limit > 0 && z.known_total + z.since_flush >= (unsigned long long)P.node_limit) {
                     g_store_rel(&P.g->abort, 1);
                     stop = 1;
@@ -1333,7 +1364,7 @@ __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
                     g_store_rel(&P.g->abort, 2);
                     stop = 1;
                 }
-                if (P.cancel && (z.nodes & 255) == 0 && *P.cancel != 0) {
+                if (P.cancel && (z.since_flush & 255) == 0 && *P.cancel != 0) {
                     g_store_rel(&P.g->abort, 3);
                     stop = 1;
                 }
@@ -1347,6 +1378,7 @@ __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
                 // this node's propagation
                 z.pf_best = g_load(&is->best);
                 z.pf_abort = g_load(&P.g->abort);
+                if (P.inst_node_limit > 0) z.pf_iabort = g_load(&is->abandon);
                 if (P.donate) {
                     z.pf_idle = g_load(&P.g->idle);
                     z.pf_qt = g_load(&P.g->q_tail);
@@ -1354,8 +1386,10 @@ __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
                 }
             }
             lds_barrier();
-            if (uni(lds_ld(&ctl[C_STOP])))
+            if (const int sv = uni(lds_ld(&ctl[C_STOP]))) {
+                abandoned = sv == 2;
                 break;
+            }
             NodeLists L;
             if (LIVE && in_sel != 0) {
                 const int32_t *c = ctl + C_CNT + kListWords * (in_sel - 1);
@@ -1394,6 +1428,13 @@ __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
                 if (z.since_flush >= 256) {
                     z.known_total = g_add(&P.g->nodes_total, z.since_flush) + z.since_flush;
                     z.since_flush = 0;
+                    if (P.inst_node_limit > 0) {
+                        // the instance's own count, for its node budget
+                        const unsigned long long used = g_add(&is->nodes, z.nodes) + z.nodes;
+                        z.nodes = 0;
+                        if (used >= (unsigned long long)P.inst_node_limit)
+                            g_store_rel(&is->abandon, 1);
+                    }
                 }
             }
             bool descend = false;
@@ -1517,7 +1558,7 @@ __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
         // ---- subtree done (or abandoned): publish counters
         if (tid == 0) {
             flush_counters(z, is, P.mode);
-            if (finished) {
+            if (finished || abandoned) {
                 if (g_add(&is->outstanding, -1) == 1)
                     __hip_atomic_store(&is->t_done, (long long)wall_clock64(), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
@@ -1550,7 +1591,8 @@ __global__ void init_search_kernel(SearchParams P)
         s.best_owner = -1;
         s.depth_overflow = 0;
         s.pad[0] = INT32_MAX;
-        s.pad[1] = s.pad[2] = 0;
+        s.pad[1] = 0;
+        s.abandon = 0;
     }
     if (i == 0) {
         SearchGlobals &g = *P.g;

@@ -75,7 +75,8 @@ struct InstState {
     int32_t best_lock;          // spin lock protecting best_vals
     int32_t best_owner;         // workgroup that wrote best_vals
     int32_t depth_overflow;     // a path exceeded the decision-stack capacity
-    int32_t pad[3];
+    int32_t pad[2];             // pad[0]: objective of best_vals (under best_lock)
+    int32_t abandon;            // the instance used its node budget
 };
 
 // Queue slot header; a slot is followed by max_depth decisions (int2).
@@ -117,6 +118,7 @@ struct SearchParams {
     int32_t max_vars;           // largest instance in the launch
     int32_t donate;             // allow donation (0 in single-workgroup runs)
     long long node_limit;       // 0 = none
+    long long inst_node_limit;  // 0 = none: nodes per instance before it is abandoned
     long long t_limit_ticks;    // 0 = none (wall_clock64 ticks)
     const volatile int32_t *cancel;   // host-visible cancel word (may be null)
     int32_t *sol_buf;           // ENUMERATE: solutions (ndec values each)

@@ -40,7 +40,8 @@ class Config(C.Structure):
 
 
 class Limits(C.Structure):
-    _fields_ = [("node_limit", _I64), ("time_limit_s", C.c_double), ("cancel", _VP)]
+    _fields_ = [("node_limit", _I64), ("time_limit_s", C.c_double), ("cancel", _VP),
+                ("inst_node_limit", _I64)]
 
 
 class Stats(C.Structure):
@@ -154,8 +155,8 @@ def _current_stream():
     return int(torch.cuda.current_stream().cuda_stream)
 
 
-def _limits(node_limit=0, time_limit=0.0, cancel=None):
-    lim = Limits(int(node_limit), float(time_limit), None)
+def _limits(node_limit=0, time_limit=0.0, cancel=None, inst_node_limit=0):
+    lim = Limits(int(node_limit), float(time_limit), None, int(inst_node_limit))
     if cancel is not None:          # a pinned int32 torch tensor
         lim.cancel = C.c_void_p(int(cancel.data_ptr()))
     return lim
@@ -298,12 +299,12 @@ class Solver:
 
 
 def batch_solve(solvers, mode=MINIMIZE, config: Config | None = None, node_limit=0,
-                time_limit=0.0, cancel=None):
+                time_limit=0.0, cancel=None, inst_node_limit=0):
     """One persistent launch over every solver's model; returns outcomes."""
     n = len(solvers)
     arr = (_VP * n)(*[s.h for s in solvers])
     outs = np.zeros(n, dtype=np.int32)
-    lim = _limits(node_limit, time_limit, cancel)
+    lim = _limits(node_limit, time_limit, cancel, inst_node_limit)
     cfg_p = C.byref(config) if config is not None else None
     _chk(lib().pccp_batch_solve(arr, n, int(mode), cfg_p, C.byref(lim), _p(outs)),
          "pccp_batch_solve")

@@ -21,6 +21,10 @@ def P():
     return pccp
 
 
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
 def counts(s):
     st = s.stats()
     return (st["nodes"], st["fails"], st["solutions"], st["sol_hash"], st["best"])
@@ -76,3 +80,24 @@ def test_autotune_picks_a_working_config(P, tmp_path):
     s = P.Solver(small[0], config=cfg)
     assert s.solve(time_limit=60) == P.OUT_OPTIMAL
     assert s.best()[0] == O.solve(small[0])["best"]
+
+
+def test_instance_node_budget_abandons_only_the_hard_instance(P):
+    """A batch with a per-instance node budget: the instance that exhausts it
+    is abandoned (LIMIT) while the small ones are still proven, with the
+    oracle's optima; the abandoned instance stopped near its budget."""
+    easy = [I.rcpsp_model(*I.rcpsp_data(n, s)[:4]) for n, s in [(8, 0), (10, 2), (9, 1)]]
+    hard = I.rcpsp(30, 0)
+    refs = [O.solve(m, node_limit=400000) for m in easy]
+    solvers = [P.Solver(m) for m in easy + [hard]]
+    budget = 2_000_000
+    outs = P.batch_solve(solvers, P.MINIMIZE, time_limit=60, inst_node_limit=budget)
+    say("budget outcomes", outs)
+    for s, o, r, m in zip(solvers, outs, refs, easy):
+        assert o == P.OUT_OPTIMAL
+        assert s.best()[0] == r["best"]
+        ok, ms = O.check_schedule(m.meta, s.best()[1])
+        assert ok and ms == s.best()[0]
+    st = solvers[-1].stats()
+    assert outs[-1] == P.OUT_LIMIT and st["ttpo_ms"] < 0
+    assert budget <= st["nodes"] <= budget + 512 * st["grid"]
