@@ -48,10 +48,12 @@ BYTES_DIFF, BYTES_REIF, BYTES_TERM = 16, 24, 8
 # 2 GiB device copy (`--copy-calibration`) reads back as 1 GiB fetched and
 # 2 GiB written.  A run whose kernel source or shape differs reports null.
 PROFILED_TRAFFIC = [
-    {"kernel_sha256": "f93944629382ade5083d7819b38a25671f393a8fe98934eecca7174463bdd410",
-     "block": 256, "desc_lds": 0, "root_lds": 1, "live": 0,
-     "fetch_bytes_per_node": 4.858, "write_bytes_per_node": 1.394,
-     "profile": "profiles/search_kernel_rcpsp30_traffic.md"},
+    {"kernel_sha256": K, "block": blk, "desc_lds": dl, "root_lds": rl, "live": 0,
+     "fetch_bytes_per_node": f, "write_bytes_per_node": w,
+     "profile": "profiles/search_kernel_rcpsp30_traffic.md"}
+    for K in ["371e0d6c2cfc89dba1f077fcf594c62ce6e0655c0f26c5066e171fdd7644afd2"]
+    for blk, dl, rl, f, w in [(256, 1, 0, 5.007, 1.701), (256, 0, 0, 5.033, 1.570),
+                              (128, 0, 0, 6.214, 5.037)]
 ]
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
@@ -210,6 +212,23 @@ def ttpo_suite(n, seeds, budget, cfg, weights):
         res[form] = summary(fok, ft, sts[0]["kernel_ms"] / 1e3, wall, [x["best"] for x in sts],
                             sum(x["nodes"] for x in sts), cov)
     return res
+
+
+def copy_calibration(gib=2):
+    """One device-to-device copy of `gib` GiB (larger than the last-level
+    cache) through an elementwise kernel: the FETCH_SIZE / WRITE_SIZE that
+    rocprofv3 reports for it calibrate the counters' unit and overheads."""
+    import torch
+    n = gib * (1 << 30) // 4
+    src = torch.empty(n, dtype=torch.int32, device="cuda")
+    src.fill_(7)
+    dst = torch.empty_like(src)
+    flush = torch.empty(512 * (1 << 20) // 4, dtype=torch.int32, device="cuda")
+    flush.fill_(1)                      # evict src from the last-level cache
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 4, "read_bytes": n * 4, "write_bytes": n * 4}))
 
 
 def main():
