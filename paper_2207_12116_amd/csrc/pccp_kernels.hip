@@ -352,7 +352,11 @@ __device__ __forceinline__ void sweep_diff(const View<DL> &v, int2 *st, const Li
 {
     constexpr int U = 2;
     const int tid = threadIdx.x, lane = tid & 63, W = blockDim.x, n = io.n;
-    for (int c0 = uni(tid - lane); c0 < n; c0 += U * W) {
+    // wavefronts take the chunks in reverse order: the reified items that
+    // follow leave their last chunk to the first wavefronts, so the small
+    // table of difference rows evens out the work per wavefront
+    const int wrev = (W >> 6) - 1 - (tid >> 6);
+    for (int c0 = uni(wrev * 64); c0 < n; c0 += U * W) {
         int idx[U];
         bool ok[U];
 #pragma unroll
@@ -1031,6 +1035,16 @@ __device__ __forceinline__ void copy_store(int2 *dst, const int2 *src, int nvars
     }
 }
 
+// apply decision word (var | side << 16, val) to the store as a join
+__device__ __forceinline__ void apply_decision(int2 *st, int2 dcs)
+{
+    const int x = dcs.x & 0xffff;
+    if (dcs.x & kSideBit)
+        tell_lb(st, x, dcs.y + 1);
+    else
+        tell_ub(st, x, dcs.y);
+}
+
 // ------------------------------------------------ features of given stores
 // Features (6 floats per decision variable) of nbox stores, one workgroup
 // per store: out[box][q][f].  The same device function the search uses.
@@ -1186,15 +1200,6 @@ __device__ unsigned long long solution_hash(const int2 *st, const View<DL> &v, i
     return h;
 }
 
-// apply decision word (var | side << 16, val) to the store as a join
-__device__ __forceinline__ void apply_decision(int2 *st, int2 dcs)
-{
-    const int x = dcs.x & 0xffff;
-    if (dcs.x & kSideBit)
-        tell_lb(st, x, dcs.y + 1);
-    else
-        tell_ub(st, x, dcs.y);
-}
 
 // ------------------------------------------------------------ search
 // State only lane 0 uses lives in LDS (not in every lane's registers).
