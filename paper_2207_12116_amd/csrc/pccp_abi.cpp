@@ -649,6 +649,7 @@ static int32_t choose_shape(const pccp_config &cfg, int max_vars, size_t max_des
             k.root_lds = cd.r;
             k.learned = feat_ndec > 0;
             k.live = live != 0;
+            k.hi = sh.block <= 256;
             int occ = 0;
             hipError_t e = search_occupancy(sh.block, lds, k, &occ);
             if (e != hipSuccess) return fail(PCCP_E_DEVICE, std::string("occupancy: ") + hipGetErrorString(e));
@@ -755,10 +756,10 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
 
     if (cfg.launch == 0) {
         // the graph bakes in the launch parameters: rebuild it when they change
-        std::vector<char> key(sizeof(P) + 7 * sizeof(int64_t));
+        std::vector<char> key(sizeof(P) + 8 * sizeof(int64_t));
         memcpy(key.data(), &P, sizeof(P));
-        const int64_t extra[7] = {sh.grid, sh.block, (int64_t)sh.lds, sh.k.desc_lds, sh.k.root_lds,
-                                  sh.k.learned, sh.k.live};
+        const int64_t extra[8] = {sh.grid, sh.block, (int64_t)sh.lds, sh.k.desc_lds, sh.k.root_lds,
+                                  sh.k.learned, sh.k.live, sh.k.hi};
         memcpy(key.data() + sizeof(P), extra, sizeof(extra));
         if (!ws.graph || key != ws.graph_key) {
             if (ws.graph) (void)hipGraphExecDestroy(ws.graph);

@@ -798,9 +798,9 @@ struct NodeLists {
 // the items run per kind and the row terms visited.
 // Precondition: a barrier separates this call from any earlier read of the
 // control words C_FLAG*, C_POSTFAIL, C_KEY and of the out lists.
-// LIVE: L may carry lists (fewer items per lane per chunk then, which leaves
-// the registers the compaction needs).
-template <bool DL, bool LIVE>
+// LIVE: L may carry lists.  LEAN: fewer items per lane per chunk (for the
+// lists' compaction, and for the high-occupancy search kernel).
+template <bool DL, bool LIVE, bool LEAN = LIVE>
 __device__ int propagate_wg(const View<DL> &v, int2 *st, int32_t *ctl, const NodeLists &L,
                             uint32_t &nsweeps, unsigned long long (&ex)[4])
 {
@@ -826,9 +826,9 @@ __device__ int propagate_wg(const View<DL> &v, int2 *st, int32_t *ctl, const Nod
     for (;;) {
         bool chg = false, bad = false;
         sweep_diff(v, st, d, chg, bad);
-        sweep_reif<DL, LIVE ? 2 : 4>(v, st, r, chg, bad);
-        sweep_rows<DL, LIVE ? 2 : 4>(v, st, w, chg, bad);
-        sweep_brows<DL, LIVE ? 1 : 2>(v, st, b, chg, bad);
+        sweep_reif<DL, LEAN ? 2 : 4>(v, st, r, chg, bad);
+        sweep_rows<DL, LEAN ? 2 : 4>(v, st, w, chg, bad);
+        sweep_brows<DL, LEAN ? 1 : 2>(v, st, b, chg, bad);
         ex[0] += (unsigned)d.n;
         ex[1] += (unsigned)r.n;
         ex[2] += (unsigned)(w.n + b.n);
@@ -1232,8 +1232,11 @@ __device__ void flush_counters(Lane0 &z, InstState *is, int mode)
 // LIVE: item lists (see propagate_wg) in three LDS buffers: R holds the
 // items the subtree root kept, A and B alternate down the current path; a
 // backtrack restarts from R, as the store restarts from the root's.
-template <bool DL, bool RL, bool LEARN, bool LIVE>
-__global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
+// HI: workgroups of at most 256 threads and at least 7 wavefronts per SIMD
+// (at most 72 VGPRs): more resident subproblems per CU to hide the latency
+// of the dependent loads, with leaner unrolling.
+template <bool DL, bool RL, bool LEARN, bool LIVE, bool HI>
+__global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(SearchParams P)
 {
     extern __shared__ __align__(16) char smem[];
     const int tid = threadIdx.x, W = blockDim.x;
@@ -1419,7 +1422,7 @@ __global__ __launch_bounds__(1024) void search_kernel(SearchParams P)
             }
             uint32_t nsw = 0;
             unsigned long long ex[4] = {0, 0, 0, 0};
-            const int rc = propagate_wg<DL, LIVE>(v, st, ctl, L, nsw, ex);
+            const int rc = propagate_wg<DL, LIVE, LIVE || HI>(v, st, ctl, L, nsw, ex);
             post_scan(v, st, ctl, branching, rc == 0, fsc, P.mlp, &m);
             const int failed = uni(rc | lds_ld(&ctl[C_POSTFAIL]));
             const unsigned long long key =
@@ -1892,23 +1895,30 @@ hipError_t launch_propagate_batch(const DevModel *m_dev, int nbox, const int32_t
     return hipGetLastError();
 }
 
-// the search kernel variant for a layout, branching rule and list mode
-template <bool L, bool V>
+// the search kernel variant for a layout, branching rule, list mode and
+// occupancy class
+template <bool L, bool V, bool H>
 static const void *search_fn_lv(bool desc_lds, bool root_lds)
 {
-    if (desc_lds && root_lds) return reinterpret_cast<const void *>(search_kernel<true, true, L, V>);
-    if (desc_lds) return reinterpret_cast<const void *>(search_kernel<true, false, L, V>);
-    if (root_lds) return reinterpret_cast<const void *>(search_kernel<false, true, L, V>);
-    return reinterpret_cast<const void *>(search_kernel<false, false, L, V>);
+    if (desc_lds && root_lds) return reinterpret_cast<const void *>(search_kernel<true, true, L, V, H>);
+    if (desc_lds) return reinterpret_cast<const void *>(search_kernel<true, false, L, V, H>);
+    if (root_lds) return reinterpret_cast<const void *>(search_kernel<false, true, L, V, H>);
+    return reinterpret_cast<const void *>(search_kernel<false, false, L, V, H>);
+}
+
+template <bool H>
+static const void *search_fn_h(const SearchShape &k)
+{
+    if (k.learned)
+        return k.live ? search_fn_lv<true, true, H>(k.desc_lds, k.root_lds)
+                      : search_fn_lv<true, false, H>(k.desc_lds, k.root_lds);
+    return k.live ? search_fn_lv<false, true, H>(k.desc_lds, k.root_lds)
+                  : search_fn_lv<false, false, H>(k.desc_lds, k.root_lds);
 }
 
 static const void *search_fn(const SearchShape &k)
 {
-    if (k.learned)
-        return k.live ? search_fn_lv<true, true>(k.desc_lds, k.root_lds)
-                      : search_fn_lv<true, false>(k.desc_lds, k.root_lds);
-    return k.live ? search_fn_lv<false, true>(k.desc_lds, k.root_lds)
-                  : search_fn_lv<false, false>(k.desc_lds, k.root_lds);
+    return k.hi ? search_fn_h<true>(k) : search_fn_h<false>(k);
 }
 
 hipError_t launch_search(const SearchParams &P, int grid, int block, size_t lds,

@@ -21,9 +21,10 @@ hipError_t launch_propagate_batch(const DevModel *m_dev, int nbox, const int32_t
                                   size_t lds, bool desc_lds, hipStream_t stream);
 
 // Which search-kernel variant: descriptor tables in LDS, subtree-root store
-// in LDS, learned branching, item lists of non-entailed propagators.
+// in LDS, learned branching, item lists of non-entailed propagators, and the
+// high-occupancy build for workgroups of at most 256 threads.
 struct SearchShape {
-    bool desc_lds = false, root_lds = false, learned = false, live = false;
+    bool desc_lds = false, root_lds = false, learned = false, live = false, hi = false;
 };
 
 hipError_t launch_search(const SearchParams &P, int grid, int block, size_t lds,
