@@ -48,12 +48,12 @@ BYTES_DIFF, BYTES_REIF, BYTES_TERM = 16, 24, 8
 # 2 GiB device copy (`--copy-calibration`) reads back as 1 GiB fetched and
 # 2 GiB written.  A run whose kernel source or shape differs reports null.
 PROFILED_TRAFFIC = [
-    {"kernel_sha256": K, "block": blk, "desc_lds": dl, "root_lds": rl, "live": 0,
+    {"kernel_sha256": K, "block": blk, "desc_lds": dl, "root_lds": rl, "live": 0, "occupancy": oc,
      "fetch_bytes_per_node": f, "write_bytes_per_node": w,
      "profile": "profiles/search_kernel_rcpsp30_traffic.md"}
     for K in ["371e0d6c2cfc89dba1f077fcf594c62ce6e0655c0f26c5066e171fdd7644afd2"]
-    for blk, dl, rl, f, w in [(256, 1, 0, 5.007, 1.701), (256, 0, 0, 5.033, 1.570),
-                              (128, 0, 0, 6.214, 5.037)]
+    for blk, dl, rl, oc, f, w in [(256, 1, 0, 2, 5.007, 1.701), (256, 0, 0, 2, 5.033, 1.570),
+                                  (128, 0, 0, 2, 6.214, 5.037)]
 ]
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
@@ -71,8 +71,9 @@ def kernel_sha256():
 def profiled_traffic(st, nodes_per_launch):
     sha = kernel_sha256()
     for e in PROFILED_TRAFFIC:
-        if (e["kernel_sha256"], e["block"], e["desc_lds"], e["root_lds"], e["live"]) == \
-                (sha, st["block"], st["desc_lds"], st["root_lds"], st["live"]):
+        if (e["kernel_sha256"], e["block"], e["desc_lds"], e["root_lds"], e["live"],
+                e["occupancy"]) == (sha, st["block"], st["desc_lds"], st["root_lds"], st["live"],
+                                    st["occupancy"]):
             return round((e["fetch_bytes_per_node"] + e["write_bytes_per_node"]) * nodes_per_launch)
     return None
 
@@ -254,6 +255,8 @@ def main():
                     help="with --wg: subtree-root store 0 chosen, 1 LDS, 2 global")
     ap.add_argument("--live", type=int, default=0, choices=(0, 1, 2),
                     help="with --wg: item lists 0 chosen, 1 on, 2 off")
+    ap.add_argument("--occupancy", type=int, default=0, choices=(0, 1, 2),
+                    help="with --wg: search kernel build 0 chosen, 1 high, 2 normal")
     ap.add_argument("--max-depth", type=int, default=0,
                     help="decision-stack capacity per workgroup (0 = library default)")
     ap.add_argument("--no-ttpo", action="store_true")
@@ -289,11 +292,12 @@ def main():
         from paper_2207_12116_amd import autotune
         cfg, rep = autotune.tune(models, pccp.MINIMIZE, budget_s=0.4, cache_path=None, log=log)
         tuned = {"wg_size": cfg.wg_size, "desc_lds": cfg.desc_lds, "root_lds": cfg.root_lds,
-                 "live": cfg.live, "candidates": len(rep["candidates"])}
+                 "live": cfg.live, "occupancy": cfg.occupancy,
+                 "candidates": len(rep["candidates"])}
         log(f"autotuned: {tuned}")
     else:
         cfg = pccp.Config(wg_size=args.wg, desc_lds=args.desc_lds, root_lds=args.root_lds,
-                          live=args.live, max_depth=args.max_depth)
+                          live=args.live, max_depth=args.max_depth, occupancy=args.occupancy)
     solvers = [pccp.Solver(m, config=cfg) for m in models]
 
     def step():
@@ -355,8 +359,14 @@ def main():
     if not args.no_ttpo:
         from paper_2207_12116_amd import learn
         log(f"time to proven optimum: {args.ttpo_seeds} instances of {args.ttpo_n} tasks")
-        ttpo_cmp = ttpo_suite(args.ttpo_n, list(range(args.ttpo_seeds)), args.ttpo_budget, cfg,
+        from paper_2207_12116_amd import autotune
+        tcfg, _ = autotune.tune([I.rcpsp(args.ttpo_n, s) for s in range(args.ttpo_seeds)],
+                                pccp.MINIMIZE, budget_s=0.2, cache_path=None,
+                                wg_sizes=(128, 256), lives=(2,), log=log)
+        ttpo_cmp = ttpo_suite(args.ttpo_n, list(range(args.ttpo_seeds)), args.ttpo_budget, tcfg,
                               learn.DEFAULT_WEIGHTS)
+        ttpo_cmp["config"] = {"wg_size": tcfg.wg_size, "desc_lds": tcfg.desc_lds,
+                              "root_lds": tcfg.root_lds, "occupancy": tcfg.occupancy}
         log(f"ttpo: {json.dumps({k: v for k, v in ttpo_cmp.items()})}")
 
     legs = None
@@ -397,7 +407,7 @@ def main():
                    "step_time_limit_s": args.step_time,
                    "grid": sts[0]["grid"], "block": sts[0]["block"],
                    "desc_lds": sts[0]["desc_lds"], "root_lds": sts[0]["root_lds"],
-                   "live": sts[0]["live"],
+                   "live": sts[0]["live"], "occupancy": sts[0]["occupancy"],
                    "autotuned": tuned, "launch": "hipGraph"},
         "propagations_per_s": round(tot_props / wall, 1),
         "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "ttpo": ttpo,

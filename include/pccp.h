@@ -157,6 +157,11 @@ typedef struct {
                              points, and so the search tree, are unchanged
                              (Theorem 2 of section 3); the lists take three
                              LDS buffers of 2 bytes per propagator          */
+    int32_t occupancy;    /* search kernel build: 0 = choose (high for
+                             wg_size <= 256), 1 = high (at least 7 waves per
+                             SIMD, wg_size <= 256, leaner unrolling),
+                             2 = normal (any wg_size)                       */
+    int32_t reserved;
 } pccp_config;
 
 /* Validate the model, compile it to packed per-kind propagator tables and
@@ -257,7 +262,7 @@ typedef struct {
     int32_t grid, block, desc_lds, root_lds;
     int64_t lds_bytes;
     int32_t live;             /* the search kept item lists                   */
-    int32_t reserved;
+    int32_t occupancy;        /* 1 = high-occupancy build, 2 = normal         */
 } pccp_stats;
 
 int32_t pccp_get_stats(const pccp_solver *s, pccp_stats *st);

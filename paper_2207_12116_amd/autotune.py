@@ -3,8 +3,9 @@
 For a batch of models it times a short search under each candidate launch
 configuration - workgroup size x placement of the propagator tables (LDS or
 HBM/L2) x placement of the subtree-root store (LDS or HBM) x item lists of
-non-entailed propagators (on or off) - and keeps the one with the highest
-node rate.  Results are cached per device and size
+non-entailed propagators (on or off) x kernel build (high occupancy or
+normal, for workgroups of up to 256 threads) - and keeps the one with the
+highest node rate.  Results are cached per device and size
 class (largest store, table sizes, mode) in a JSON file, so a later call with
 the same shapes costs nothing.
 """
@@ -17,7 +18,7 @@ import time
 from . import pccp
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pccp_autotune.json")
-WG_SIZES = (64, 128, 256, 512, 1024)
+WG_SIZES = (128, 256, 512, 1024)
 PLACEMENTS = ((1, 1), (1, 2), (2, 1), (2, 2))   # (desc_lds, root_lds): 1 = LDS, 2 = HBM
 LIVES = (1, 2)                                    # item lists on, off
 
@@ -73,8 +74,10 @@ def tune(models, mode=pccp.MINIMIZE, budget_s=0.4, cache_path=DEFAULT_CACHE, for
         c = cache[key]
         return pccp.Config(**c["config"]), {"cached": True, **c}
     results = []
-    for wg, (d, r), lv in ((w, p, l) for w in wg_sizes for p in placements for l in lives):
-        cfg = pccp.Config(wg_size=wg, desc_lds=d, root_lds=r, live=lv)
+    cands = [(w, p, l, o) for w in wg_sizes for p in placements for l in lives
+             for o in ((1, 2) if w <= 256 else (2,))]
+    for wg, (d, r), lv, oc in cands:
+        cfg = pccp.Config(wg_size=wg, desc_lds=d, root_lds=r, live=lv, occupancy=oc)
         try:
             rate, st = _rate(models, mode, cfg, budget_s)
         except pccp.PccpError as e:
@@ -82,20 +85,20 @@ def tune(models, mode=pccp.MINIMIZE, budget_s=0.4, cache_path=DEFAULT_CACHE, for
                 continue
             raise
         results.append({"wg_size": wg, "desc_lds": d, "root_lds": r, "live": lv,
-                         "nodes_per_s": rate, "grid": st["grid"],
+                         "occupancy": oc, "nodes_per_s": rate, "grid": st["grid"],
                          "placed_desc_lds": st["desc_lds"],
                          "placed_root_lds": st["root_lds"]})
         if log:
-            log(f"autotune wg={wg} desc={d} root={r} live={lv}: {rate / 1e6:.2f} M nodes/s "
+            log(f"autotune wg={wg} desc={d} root={r} live={lv} occ={oc}: {rate / 1e6:.2f} M nodes/s "
                 f"(grid {st['grid']})")
     results.sort(key=lambda x: -x["nodes_per_s"])
     for x in results[:finalists]:
         cfg = pccp.Config(wg_size=x["wg_size"], desc_lds=x["desc_lds"], root_lds=x["root_lds"],
-                          live=x["live"])
+                          live=x["live"], occupancy=x["occupancy"])
         x["nodes_per_s_long"], _ = _rate(models, mode, cfg, 4 * budget_s)
         if log:
             log(f"autotune finalist wg={x['wg_size']} desc={x['desc_lds']} root={x['root_lds']} "
-                f"live={x['live']}: {x['nodes_per_s_long'] / 1e6:.2f} M nodes/s")
+                f"live={x['live']} occ={x['occupancy']}: {x['nodes_per_s_long'] / 1e6:.2f} M nodes/s")
     if not results:
         raise RuntimeError("autotune: no configuration fits")
     # long-run rates within 2 % of the best are ties (searches of different
@@ -104,7 +107,8 @@ def tune(models, mode=pccp.MINIMIZE, budget_s=0.4, cache_path=DEFAULT_CACHE, for
     top = max(x["nodes_per_s_long"] for x in results[:finalists])
     best = next(x for x in results[:finalists] if x["nodes_per_s_long"] >= 0.98 * top)
     entry = {"config": {"wg_size": best["wg_size"], "desc_lds": best["desc_lds"],
-                        "root_lds": best["root_lds"], "live": best["live"]},
+                        "root_lds": best["root_lds"], "live": best["live"],
+                        "occupancy": best["occupancy"]},
              "nodes_per_s": best["nodes_per_s"], "candidates": results}
     if cache_path:
         cache[key] = entry

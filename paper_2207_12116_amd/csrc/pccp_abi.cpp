@@ -397,7 +397,8 @@ static int32_t check_cfg(const pccp_config &cfg)
         return fail(PCCP_E_INVALID_ARG, "launch must be 0 (graph) or 1 (plain)");
     if (cfg.num_wgs < 0 || cfg.queue_cap < 0 || cfg.desc_lds < 0 || cfg.desc_lds > 2 ||
         cfg.root_lds < 0 || cfg.root_lds > 2 || cfg.max_depth > (1 << 16) || cfg.live < 0 ||
-        cfg.live > 2)
+        cfg.live > 2 || cfg.occupancy < 0 || cfg.occupancy > 2 ||
+        (cfg.occupancy == 1 && cfg.wg_size > 256))
         return fail(PCCP_E_INVALID_ARG, "bad config field");
     return PCCP_OK;
 }
@@ -649,7 +650,7 @@ static int32_t choose_shape(const pccp_config &cfg, int max_vars, size_t max_des
             k.root_lds = cd.r;
             k.learned = feat_ndec > 0;
             k.live = live != 0;
-            k.hi = sh.block <= 256;
+            k.hi = cfg.occupancy == 1 || (cfg.occupancy == 0 && sh.block <= 256);
             int occ = 0;
             hipError_t e = search_occupancy(sh.block, lds, k, &occ);
             if (e != hipSuccess) return fail(PCCP_E_DEVICE, std::string("occupancy: ") + hipGetErrorString(e));
@@ -811,6 +812,7 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
         o.root_lds = sh.k.root_lds;
         o.lds_bytes = (int64_t)sh.lds;
         o.live = sh.k.live;
+        o.occupancy = sh.k.hi ? 1 : 2;
         const bool done = is.outstanding == 0;
         o.ttpo_ms = done ? (double)(is.t_done - g.t_start) / (double)s->wall_khz : -1.0;
         if (done)

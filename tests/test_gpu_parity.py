@@ -167,6 +167,9 @@ def _gpu_counts(s):
 # item lists on (1) and off (2): dropping entailed propagators must leave
 # every fixed point, and so every counter of the search, unchanged
 LIVE = pytest.mark.parametrize("live", [1, 2], ids=["lists", "tables"])
+# both builds of the search kernel: high occupancy (workgroups of at most 256
+# threads) and normal
+OCC = pytest.mark.parametrize("occ", [1, 2], ids=["hiocc", "normal"])
 
 
 @LIVE
@@ -186,30 +189,33 @@ def test_single_wg_enumerate(P, seed, dom, live):
     assert np.array_equal(sols, ref["solutions_list"])   # same order: sequential DFS
 
 
+@OCC
 @LIVE
 @pytest.mark.parametrize("n,seed", [(4, 0), (5, 1), (6, 2), (6, 3), (8, 4), (10, 5)])
-def test_single_wg_minimize(P, n, seed, live):
+def test_single_wg_minimize(P, n, seed, live, occ):
     model = I.tiny_rcpsp(n, seed)
     ref = O.solve(model)
-    say("minimize 1wg", n, seed, live, ref["nodes"])
-    s = P.Solver(model, num_wgs=1, live=live)
+    say("minimize 1wg", n, seed, live, occ, ref["nodes"])
+    s = P.Solver(model, num_wgs=1, live=live, occupancy=occ)
     out = s.solve(time_limit=60)
     assert out == P.OUT_OPTIMAL
+    assert s.stats()["occupancy"] == occ
     assert _gpu_counts(s) == _oracle_counts(ref)
     obj, vals = s.best()
     ok, ms = O.check_schedule(model.meta, vals)
     assert ok and ms == obj == ref["best"]
 
 
+@OCC
 @LIVE
 @pytest.mark.parametrize("n,seed,limit", [(30, 0, 3000), (30, 4, 2000), (60, 1, 800)])
-def test_single_wg_node_limited_prefix(P, n, seed, limit, live):
+def test_single_wg_node_limited_prefix(P, n, seed, limit, live, occ):
     """Both searches stop after exactly `limit` nodes of the same depth-first
     order, so every counter and the incumbent agree."""
     model = I.rcpsp(n, seed)
     ref = O.solve(model, node_limit=limit)
-    say("prefix 1wg", n, seed, limit, live)
-    s = P.Solver(model, num_wgs=1, live=live)
+    say("prefix 1wg", n, seed, limit, live, occ)
+    s = P.Solver(model, num_wgs=1, live=live, occupancy=occ)
     out = s.solve(node_limit=limit, time_limit=60)
     assert out == P.OUT_LIMIT and ref["outcome"] == O.OUT_LIMIT
     assert _gpu_counts(s) == _oracle_counts(ref)
@@ -264,13 +270,14 @@ def test_multi_wg_enumerate_full_size(P, seed, live):
     assert st["grid"] > 1
 
 
+@OCC
 @LIVE
 @pytest.mark.parametrize("n,seed", [(8, 0), (10, 1), (10, 2), (12, 3)])
-def test_multi_wg_minimize(P, n, seed, live):
+def test_multi_wg_minimize(P, n, seed, live, occ):
     model = I.tiny_rcpsp(n, seed)
     ref = O.solve(model)
-    say("minimize multi", n, seed, live)
-    s = P.Solver(model, live=live)
+    say("minimize multi", n, seed, live, occ)
+    s = P.Solver(model, live=live, occupancy=occ)
     out = s.solve(time_limit=60)
     assert out == P.OUT_OPTIMAL
     obj, vals = s.best()
