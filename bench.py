@@ -51,9 +51,9 @@ PROFILED_TRAFFIC = [
     {"kernel_sha256": K, "block": blk, "desc_lds": dl, "root_lds": rl, "live": 0, "occupancy": oc,
      "fetch_bytes_per_node": f, "write_bytes_per_node": w,
      "profile": "profiles/search_kernel_rcpsp30_traffic.md"}
-    for K in ["371e0d6c2cfc89dba1f077fcf594c62ce6e0655c0f26c5066e171fdd7644afd2"]
-    for blk, dl, rl, oc, f, w in [(256, 1, 0, 2, 5.007, 1.701), (256, 0, 0, 2, 5.033, 1.570),
-                                  (128, 0, 0, 2, 6.214, 5.037)]
+    for K in ["36da0e10da58f7a05b01a9f60afdf4d3ffe805c09682f04698d949b11680fdf0"]
+    for blk, dl, rl, oc, f, w in [(256, 0, 0, 1, 17.205, 3.654), (256, 1, 0, 2, 4.997, 1.673),
+                                  (256, 0, 0, 2, 5.046, 1.553)]
 ]
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
