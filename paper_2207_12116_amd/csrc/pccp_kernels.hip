@@ -424,7 +424,6 @@ template <bool DL, int U>
 __device__ __forceinline__ void sweep_reif(const View<DL> &v, int2 *st, const ListIO &io,
                                            bool &chg, bool &bad)
 {
-    constexpr int BIG = 0x3fffffff;
     const int tid = threadIdx.x, lane = tid & 63, W = blockDim.x, n = io.n;
     for (int c0 = uni(tid - lane); c0 < n; c0 += U * W) {
         int idx[U];
@@ -455,20 +454,27 @@ __device__ __forceinline__ void sweep_reif(const View<DL> &v, int2 *st, const Li
             const int d = e[u].y >> 16;
             const int lbi = di[u].x, ubi = di[u].y, lbj = dj[u].x, ubj = dj[u].y;
             const int lbb = db[u].x, ubb = db[u].y;
-            const bool E1 = ubi <= lbj;                  // entailed(si <= sj)
-            const bool E2 = ubj <= lbi + d - 1;          // entailed(sj < si + d)
+            // With X = ub(sj) - lb(si) and Y = lb(sj) - ub(si): si <= sj is
+            // entailed iff Y >= 0 and disentailed iff X < 0; sj < si + d is
+            // entailed iff X < d and disentailed iff Y >= d.
+            const int X = ubj - lbi, Y = lbj - ubi;
+            const bool E1 = Y >= 0, E2 = X < d;
             const bool on = lbb >= 1, off = ubb <= 0;
             const bool t_b1 = !on && E1 && E2;           // psi entailed: b >= 1
-            const bool t_b0 = !off && (lbi > ubj || lbj >= ubi + d);  // not psi: b <= 0
-            const bool o1 = off && E1, o2 = off && E2;
-            const int nui = min(on ? ubj : BIG, o1 ? ubj - d : BIG);
-            const int nlj = max(on ? lbi : -BIG, o1 ? lbi + d : -BIG);
-            const int nuj = min(on ? ubi + d - 1 : BIG, o2 ? ubi - 1 : BIG);
-            const int nli = max(on ? lbj - d + 1 : -BIG, o2 ? lbj + 1 : -BIG);
-            const bool p_ui = nui < ubi, p_lj = nlj > lbj;
-            const bool p_uj = nuj < ubj, p_li = nli > lbi;
+            const bool t_b0 = !off && (X < 0 || Y >= d); // not psi: b <= 0
+            // b = 1 tells both conjuncts; b = 0 tells the negation of the
+            // conjunct that is not entailed: with si <= sj entailed,
+            // sj >= si + d (d1 = d); with sj < si + d entailed, sj < si (d2 = 0)
+            const bool a1 = on || (off && E1);           // ub(si), lb(sj)
+            const bool a2 = on || (off && E2);           // ub(sj), lb(si)
+            const int d1 = off ? d : 0, d2 = on ? d : 0;
+            const int nui = ubj - d1, nlj = lbi + d1;
+            const int nuj = ubi + d2 - 1, nli = lbj - d2 + 1;
+            const bool p_ui = a1 && nui < ubi, p_lj = a1 && nlj > lbj;
+            const bool p_uj = a2 && nuj < ubj, p_li = a2 && nli > lbi;
             if (io.out) {
-                const int ui = min(ubi, nui), lj = max(lbj, nlj), uj = min(ubj, nuj), li = max(lbi, nli);
+                const int ui = p_ui ? nui : ubi, lj = p_lj ? nlj : lbj;
+                const int uj = p_uj ? nuj : ubj, li = p_li ? nli : lbi;
                 const bool b1 = on || t_b1, b0 = off || t_b0;
                 const bool ent = (b1 && ui <= lj && uj <= li + d - 1) ||
                                  (b0 && (li > uj || lj >= ui + d));
@@ -685,18 +691,20 @@ __device__ __forceinline__ void sweep_brows(const View<DL> &v, int2 *st, const L
                     tv[q][k] = k < KC ? v.bterms(ri[q] * SL + gl + k * G) : 0u;
 #pragma unroll
             for (int q = 0; q < RB; ++q) rd[q] = v.brows(ri[q]);
-            // per slot only the open bit survives the sums (bit q * TB + k)
-            uint32_t open = 0;
+            // per slot only a (open term) or 0 (fixed term) survives the sums;
+            // products with a 0/1 bound are 24-bit multiply-adds (a store
+            // where a bound left [0, 1] has already failed)
+            int rv[RB][TB];
 #pragma unroll
             for (int q = 0; q < RB; ++q) {
                 int part = 0, pmax = 0;
 #pragma unroll
                 for (int k = 0; k < TB; ++k) {
                     const int2 d = k < KC ? dom(st, tv[q][k] & 0xffff) : make_int2(0, 0);
-                    const int a = (int)(tv[q][k] >> 16);
-                    part += d.x > 0 ? a : 0;
-                    pmax += d.y > 0 ? a : 0;
-                    open |= (a > 0 && d.x < d.y) ? 1u << (q * TB + k) : 0u;
+                    const uint32_t a = tv[q][k] >> 16;
+                    part = (int)__umul24(a, (uint32_t)d.x) + part;
+                    pmax = (int)__umul24(a, (uint32_t)d.y) + pmax;
+                    rv[q][k] = d.x < d.y ? (int)a : 0;
                 }
                 S[q] = group_sum(part, G);
                 Smax[q] = cmp ? group_sum(pmax, G) : 0;
@@ -707,10 +715,8 @@ __device__ __forceinline__ void sweep_brows(const View<DL> &v, int2 *st, const L
                 const int slack = rd[q].x - S[q];
                 if (rok[q] && slack < 0) { bad = true; chg = true; }
 #pragma unroll
-                for (int k = 0; k < TB; ++k) {
-                    const int a = (int)(tv[q][k] >> 16);
-                    tight |= (rok[q] && a > slack) ? (open & (1u << (q * TB + k))) : 0u;
-                }
+                for (int k = 0; k < TB; ++k)
+                    tight |= (rok[q] && slack >= 0 && rv[q][k] > slack) ? 1u << (q * TB + k) : 0u;
             }
             if (__any(tight != 0)) {
 #pragma unroll
