@@ -51,9 +51,10 @@ PROFILED_TRAFFIC = [
     {"kernel_sha256": K, "block": blk, "desc_lds": dl, "root_lds": rl, "live": 0, "occupancy": oc,
      "fetch_bytes_per_node": f, "write_bytes_per_node": w,
      "profile": "profiles/search_kernel_rcpsp30_traffic.md"}
-    for K in ["36da0e10da58f7a05b01a9f60afdf4d3ffe805c09682f04698d949b11680fdf0"]
-    for blk, dl, rl, oc, f, w in [(256, 0, 0, 1, 17.205, 3.654), (256, 1, 0, 2, 4.997, 1.673),
-                                  (256, 0, 0, 2, 5.046, 1.553)]
+    for K in ["c5eafc6937bfcfe275291cb373c457d5e08a0d9a022915d2b2c9044f281ae18f"]
+    for blk, dl, rl, oc, f, w in [(256, 0, 0, 1, 5.688, 3.527), (256, 1, 0, 2, 4.920, 1.458),
+                                  (256, 0, 0, 2, 4.949, 1.400)]
+]
 ]
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
