@@ -161,7 +161,20 @@ typedef struct {
                              wg_size <= 256), 1 = high (at least 7 waves per
                              SIMD, wg_size <= 256, leaner unrolling),
                              2 = normal (any wg_size)                       */
-    int32_t reserved;
+    int32_t dep;          /* dependency-driven propagation: 1 = on; 0
+                             (default) or 2 = off.  On: after the first sweep
+                             of a node, a sweep runs only the propagators that
+                             read a bound tightened in the sweep before (the
+                             improvement of the naive loop that section 6
+                             points to; the fixed point is unchanged,
+                             Theorem 2 of section 3), and a backtrack
+                             restores the parent's store from a trail in
+                             global memory instead of recomputing it from
+                             the subtree root; excludes live = 1           */
+    int32_t trail_cap;    /* trail entries per workgroup with dep = 1; 0 = 8
+                             per store variable within [4096, 2^18].  A path
+                             whose changes do not fit is recomputed from the
+                             subtree root instead                          */
 } pccp_config;
 
 /* Validate the model, compile it to packed per-kind propagator tables and
@@ -263,6 +276,8 @@ typedef struct {
     int64_t lds_bytes;
     int32_t live;             /* the search kept item lists                   */
     int32_t occupancy;        /* 1 = high-occupancy build, 2 = normal         */
+    int32_t dep;              /* dependency-driven propagation with a trail   */
+    int32_t pad;
 } pccp_stats;
 
 int32_t pccp_get_stats(const pccp_solver *s, pccp_stats *st);

@@ -140,7 +140,53 @@ struct Compiled {
     std::vector<float> fstat;
     std::vector<int32_t> fr_ptr, fb_ptr, fb;
     std::vector<int2> fr;
+    // propagators reading each variable (see DevModel::adj)
+    std::vector<int32_t> adj_ptr;
+    std::vector<uint32_t> adj;
 };
+
+// Which propagators read which bound of which variable: a propagator has to
+// run again only after a bound it reads was tightened.  Difference row
+// x - y <= c reads lb(x) and ub(y); a reified item reads both bounds of b,
+// si and sj; a linear row reads lb of its positive terms and ub of its
+// negative ones (the tell on a term does not depend on that term's own
+// bound); a Boolean row reads lb of its terms.  Entries of one variable are
+// grouped by kind.
+static void compile_adjacency(Compiled &c)
+{
+    const int32_t V = c.nvars;
+    std::vector<std::vector<uint32_t>> a(V);
+    auto add = [&](int32_t x, uint32_t idx, uint32_t kind, uint32_t reads) {
+        a[x].push_back(idx | (kind << 16) | reads);
+    };
+    for (size_t i = 0; i < c.diff.size(); ++i) {
+        const uint32_t w = (uint32_t)c.diff[i].x;
+        add((int32_t)(w & 0xffff), (uint32_t)i, 0, kAdjLb);
+        add((int32_t)(w >> 16), (uint32_t)i, 0, kAdjUb);
+    }
+    for (size_t i = 0; i < c.reif.size(); ++i) {
+        const uint32_t w0 = (uint32_t)c.reif[i].x, w1 = (uint32_t)c.reif[i].y;
+        add((int32_t)(w0 & 0xffff), (uint32_t)i, 1, kAdjLb | kAdjUb);
+        if ((w0 >> 16) != (w0 & 0xffff)) add((int32_t)(w0 >> 16), (uint32_t)i, 1, kAdjLb | kAdjUb);
+        if ((w1 & 0xffff) != (w0 >> 16) && (w1 & 0xffff) != (w0 & 0xffff))
+            add((int32_t)(w1 & 0xffff), (uint32_t)i, 1, kAdjLb | kAdjUb);
+    }
+    for (size_t i = 0; i < c.rows.size(); ++i)
+        for (int32_t t = c.rows[i].x; t < c.rows[i].x + c.rows[i].y; ++t) {
+            const int32_t coef = (int32_t)c.terms[t] >> 16;
+            add((int32_t)(c.terms[t] & 0xffff), (uint32_t)i, 2, coef > 0 ? kAdjLb : kAdjUb);
+        }
+    const size_t SL = (size_t)c.bgroup * c.bchunks;
+    for (size_t i = 0; i < c.brows.size(); ++i)
+        for (int32_t t = 0; t < c.brows[i].y; ++t)
+            add((int32_t)(c.bterms[SL * i + t] & 0xffff), (uint32_t)i, 3, kAdjLb);
+    c.adj_ptr.assign(V + 1, 0);
+    c.adj.clear();
+    for (int32_t x = 0; x < V; ++x) {
+        c.adj.insert(c.adj.end(), a[x].begin(), a[x].end());
+        c.adj_ptr[x + 1] = (int32_t)c.adj.size();
+    }
+}
 
 // Static part of the branching features of every decision variable q
 // (x = dec[q], H = max(1, ub0 - lb0)): 1/H, the share of the largest
@@ -310,6 +356,12 @@ static int32_t compile_model(const pccp_model *m, Compiled &c)
                                    (int32_t)((uint32_t)it[2] | ((uint32_t)(uint16_t)(int16_t)it[3] << 16))));
     }
     compile_features(m, c);
+    // adjacency entries hold 16-bit indices
+    if (c.diff.size() <= 65536 && c.reif.size() <= 65536 && c.rows.size() <= 65536 &&
+        c.brows.size() <= 65536)
+        compile_adjacency(c);
+    else
+        c.adj_ptr.assign(c.nvars + 1, 0);
     return PCCP_OK;
 }
 
@@ -342,13 +394,13 @@ struct DevBuf {
 
 // search workspace (grow-only), and the graph of the last launch
 struct Workspace {
-    DevBuf models, inst, globals, qseq, qdata, roots, best;
+    DevBuf models, inst, globals, qseq, qdata, roots, best, trail, tstart;
     hipGraphExec_t graph = nullptr;
     std::vector<char> graph_key;
     void release()
     {
         models.release(); inst.release(); globals.release(); qseq.release();
-        qdata.release(); roots.release(); best.release();
+        qdata.release(); roots.release(); best.release(); trail.release(); tstart.release();
         if (graph) (void)hipGraphExecDestroy(graph);
         graph = nullptr;
         graph_key.clear();
@@ -398,8 +450,11 @@ static int32_t check_cfg(const pccp_config &cfg)
     if (cfg.num_wgs < 0 || cfg.queue_cap < 0 || cfg.desc_lds < 0 || cfg.desc_lds > 2 ||
         cfg.root_lds < 0 || cfg.root_lds > 2 || cfg.max_depth > (1 << 16) || cfg.live < 0 ||
         cfg.live > 2 || cfg.occupancy < 0 || cfg.occupancy > 2 ||
-        (cfg.occupancy == 1 && cfg.wg_size > 256))
+        (cfg.occupancy == 1 && cfg.wg_size > 256) || cfg.dep < 0 || cfg.dep > 2 ||
+        cfg.trail_cap < 0 || cfg.trail_cap > (1 << 24))
         return fail(PCCP_E_INVALID_ARG, "bad config field");
+    if (cfg.live == 1 && cfg.dep == 1)
+        return fail(PCCP_E_INVALID_ARG, "item lists and dependency-driven propagation exclude each other");
     return PCCP_OK;
 }
 
@@ -446,7 +501,9 @@ extern "C" int32_t pccp_solver_create(const pccp_model *m, const pccp_config *cf
     const size_t o_fr = o_frp + al(4 * c.fr_ptr.size());
     const size_t o_fbp = o_fr + al(8 * c.fr.size());
     const size_t o_fb = o_fbp + al(4 * c.fb_ptr.size());
-    const size_t total = o_fb + al(4 * c.fb.size()) + 256;
+    const size_t o_adjp = o_fb + al(4 * c.fb.size());
+    const size_t o_adj = o_adjp + al(4 * c.adj_ptr.size());
+    const size_t total = o_adj + al(4 * c.adj.size()) + 256;
     rc = s->tables.ensure(total);
     if (rc == PCCP_OK) rc = s->dmodel.ensure(sizeof(DevModel));
     if (rc != PCCP_OK) { delete s; return rc; }
@@ -467,6 +524,8 @@ extern "C" int32_t pccp_solver_create(const pccp_model *m, const pccp_config *cf
     put(o_fr, c.fr.data(), 8 * c.fr.size());
     put(o_fbp, c.fb_ptr.data(), 4 * c.fb_ptr.size());
     put(o_fb, c.fb.data(), 4 * c.fb.size());
+    put(o_adjp, c.adj_ptr.data(), 4 * c.adj_ptr.size());
+    put(o_adj, c.adj.data(), 4 * c.adj.size());
     DevModel &dm = s->hmodel;
     dm.nvars = c.nvars;
     dm.ndiff = (int32_t)c.diff.size();
@@ -502,6 +561,8 @@ extern "C" int32_t pccp_solver_create(const pccp_model *m, const pccp_config *cf
     dm.fr = reinterpret_cast<const int2 *>(base + o_fr);
     dm.fb_ptr = reinterpret_cast<const int32_t *>(base + o_fbp);
     dm.fb = reinterpret_cast<const int32_t *>(base + o_fb);
+    dm.adj_ptr = reinterpret_cast<const int32_t *>(base + o_adjp);
+    dm.adj = reinterpret_cast<const uint32_t *>(base + o_adj);
     e = hipMemcpyAsync(base, host.data(), total, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->dmodel.p, &dm, sizeof(DevModel), hipMemcpyHostToDevice, s->stream);
@@ -615,58 +676,110 @@ extern "C" int32_t pccp_get_domains(pccp_solver *s, int32_t *lb, int32_t *ub, in
 }
 
 // ------------------------------------------------------------------ search
+
+// What a search launch has to hold: the largest instance, its tables and
+// whether its propagator counts allow 16-bit list entries.
+struct ShapeNeed {
+    int max_vars = 0;
+    size_t max_desc = 0;
+    int max_items[4] = {0, 0, 0, 0};
+    int feat_ndec = 0;        // learned branching: feature scratch per candidate
+    bool lists_ok = false;    // item lists (every kind <= 65536 propagators)
+    bool dep_ok = false;      // adjacency of every instance built
+};
+
+// LDS layout of dependency-driven propagation: variable bitmaps of the
+// smallest power-of-two word count with 32 bits per word covering the
+// store, one mark bit per propagator, work lists of 1/scale of each table
+// (at least 64 entries; a sweep whose list would overflow runs the whole
+// table of that kind) and the trail starts of the path levels in LDS or in
+// global memory.
+struct DepLayout {
+    int vshift = 0, qw = 0;
+    int wcap[4] = {0, 0, 0, 0};
+    bool tstart_lds = true;
+};
+
+static DepLayout dep_layout(int max_vars, const int items[4], int scale, bool tstart_lds)
+{
+    DepLayout d;
+    const int Vp = (max_vars + 3) & ~3;
+    while ((32 << d.vshift) < Vp) ++d.vshift;
+    const int64_t tot = (int64_t)items[0] + items[1] + items[2] + items[3];
+    d.qw = (int)((tot + 31) / 32);
+    for (int k = 0; k < 4; ++k)
+        d.wcap[k] = std::min(items[k], std::max(64, (items[k] + scale - 1) / scale));
+    d.tstart_lds = tstart_lds;
+    return d;
+}
+
 struct LaunchShape {
     int block = 256, grid = 1, wgs_per_cu = 1;
     SearchShape k;
     size_t lds = 0;
+    DepLayout dep;
 };
 
 // Launch shape of a search: the kernel variant (descriptor tables and
 // subtree-root store in LDS or global memory) with the most resident
-// workgroups.  Item lists are used only when asked for (cfg.live == 1): on
-// the workloads measured they cut propagator executions by half but cost
-// more time per node than they save, so the default leaves them to the
-// autotuner.
-static int32_t choose_shape(const pccp_config &cfg, int max_vars, size_t max_desc, int list_items,
-                            bool lists_ok, int num_cus, size_t lds_max, LaunchShape &sh,
-                            int feat_ndec = 0)
+// workgroups.  Item lists (cfg.live == 1) and dependency-driven
+// propagation (cfg.dep == 1) are used only when asked for.
+static int32_t choose_shape(const pccp_config &cfg, const ShapeNeed &nd, int num_cus,
+                            size_t lds_max, LaunchShape &sh)
 {
     sh.block = cfg.wg_size;
+    const int pm = cfg.dep == 1 ? 2 : (cfg.live == 1 ? 1 : 0);
+    if (pm == 1 && !nd.lists_ok)
+        return fail(PCCP_E_UNSUPPORTED, "item lists need at most 65536 propagators of each kind");
+    if (pm == 2 && !nd.dep_ok)
+        return fail(PCCP_E_UNSUPPORTED,
+                    "dependency-driven propagation needs at most 65536 propagators of each kind");
+    const int list_items = pm == 1 ? nd.max_items[0] + nd.max_items[1] + nd.max_items[2] + nd.max_items[3] : 0;
     struct Cand { bool d, r; };
     const Cand cands[4] = {{true, true}, {false, true}, {true, false}, {false, false}};
-    int best_occ[2] = {-1, -1};
-    LaunchShape best[2];
-    for (int live = 0; live < 2; ++live) {
-        if ((cfg.live == 1) != (live == 1)) continue;
-        if (live && !lists_ok) continue;
-        for (const Cand &cd : cands) {
-            if (cfg.desc_lds != 0 && cd.d != (cfg.desc_lds == 1)) continue;
-            if (cfg.root_lds != 0 && cd.r != (cfg.root_lds == 1)) continue;
-            const size_t lds = search_lds_bytes(max_vars, cfg.max_depth, max_desc, cd.d, cd.r,
-                                                feat_ndec, live ? list_items : 0);
+    int best_occ = -1;
+    for (const Cand &cd : cands) {
+        if (cfg.desc_lds != 0 && cd.d != (cfg.desc_lds == 1)) continue;
+        if (cfg.root_lds != 0 && cd.r != (cfg.root_lds == 1)) continue;
+        const size_t base = search_lds_bytes(nd.max_vars, cfg.max_depth, nd.max_desc, cd.d, cd.r,
+                                             nd.feat_ndec, list_items, 0);
+        if (base > lds_max) continue;
+        SearchShape k;
+        k.desc_lds = cd.d;
+        k.root_lds = cd.r;
+        k.learned = nd.feat_ndec > 0;
+        k.live = pm == 1;
+        k.dep = pm == 2;
+        k.hi = cfg.occupancy == 1 || (cfg.occupancy == 0 && sh.block <= 256);
+        // dependency-driven: the layouts from whole-table lists with the
+        // trail starts in LDS down to short lists with them in global
+        // memory; the first with the most resident workgroups
+        const int nlay = pm == 2 ? 16 : 1;
+        for (int li = 0; li < nlay; ++li) {
+            DepLayout dl;
+            size_t depb = 0;
+            if (pm == 2) {
+                dl = dep_layout(nd.max_vars, nd.max_items, 1 << (li % 8), li < 8);
+                depb = dep_lds_bytes(cfg.max_depth, dl.tstart_lds, dl.vshift, dl.qw, dl.wcap);
+            }
+            const size_t lds = search_lds_bytes(nd.max_vars, cfg.max_depth, nd.max_desc, cd.d, cd.r,
+                                                nd.feat_ndec, list_items, depb);
             if (lds > lds_max) continue;
-            SearchShape k;
-            k.desc_lds = cd.d;
-            k.root_lds = cd.r;
-            k.learned = feat_ndec > 0;
-            k.live = live != 0;
-            k.hi = cfg.occupancy == 1 || (cfg.occupancy == 0 && sh.block <= 256);
             int occ = 0;
             hipError_t e = search_occupancy(sh.block, lds, k, &occ);
-            if (e != hipSuccess) return fail(PCCP_E_DEVICE, std::string("occupancy: ") + hipGetErrorString(e));
-            if (occ > best_occ[live]) {  // candidates are in order of preference
-                best_occ[live] = occ;
-                best[live].k = k;
-                best[live].lds = lds;
+            if (e != hipSuccess)
+                return fail(PCCP_E_DEVICE, std::string("occupancy: ") + hipGetErrorString(e));
+            if (occ > best_occ) {  // candidates are in order of preference
+                best_occ = occ;
+                sh.k = k;
+                sh.lds = lds;
+                sh.dep = dl;
             }
         }
     }
-    const int pick = cfg.live == 1 ? 1 : 0;
-    if (best_occ[pick] <= 0)
+    if (best_occ <= 0)
         return fail(PCCP_E_LDS_CAPACITY, "no store layout fits in LDS with this wg_size/max_depth");
-    sh.k = best[pick].k;
-    sh.lds = best[pick].lds;
-    sh.wgs_per_cu = best_occ[pick];
+    sh.wgs_per_cu = best_occ;
     const int resident = sh.wgs_per_cu * num_cus;
     sh.grid = cfg.num_wgs > 0 ? std::min(cfg.num_wgs, resident) : resident;
     return PCCP_OK;
@@ -702,12 +815,15 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
     HIPCHK(hipSetDevice(s0->device));
     const bool learned = s0->branching == PCCP_BRANCH_MLP && s0->mlp != nullptr;
     LaunchShape sh;
+    ShapeNeed need;
+    need.max_vars = max_vars;
+    need.max_desc = max_desc;
+    for (int k = 0; k < 4; ++k) need.max_items[k] = max_items[k];
+    need.feat_ndec = learned ? max_ndec : 0;
     // list entries are 16-bit descriptor indices
-    const bool lists_ok = *std::max_element(max_items, max_items + 4) <= 65536;
-    if (cfg.live == 1 && !lists_ok)
-        return fail(PCCP_E_UNSUPPORTED, "item lists need at most 65536 propagators of each kind");
-    rc = choose_shape(cfg, max_vars, max_desc, max_items[0] + max_items[1] + max_items[2] + max_items[3],
-                      lists_ok, s0->num_cus, s0->lds_max, sh, learned ? max_ndec : 0);
+    need.lists_ok = *std::max_element(max_items, max_items + 4) <= 65536;
+    need.dep_ok = need.lists_ok;
+    rc = choose_shape(cfg, need, s0->num_cus, s0->lds_max, sh);
     if (rc != PCCP_OK) return rc;
     const int qcap = cfg.queue_cap > 0 ? std::max(cfg.queue_cap, n) : std::max(4 * sh.grid, n + sh.grid);
     const int slot_bytes = (int)(((size_t)sizeof(RecHdr) + sizeof(int2) * (size_t)cfg.max_depth + 15) & ~size_t(15));
@@ -721,6 +837,16 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
         (rc = ws.best.ensure(sizeof(int32_t) * (size_t)n * max_ndec)))
         return rc;
     if (!sh.k.root_lds && (rc = ws.roots.ensure(sizeof(int32_t) * 2 * (size_t)Vp * sh.grid)))
+        return rc;
+    // trail: 8 entries of 16 bytes per store variable per workgroup, within
+    // [4096, 2^18] entries; a path whose changes do not fit falls back to
+    // recomputation
+    const int tcap = !sh.k.dep ? 0 : cfg.trail_cap > 0 ? cfg.trail_cap
+                                                       : std::min(std::max(8 * Vp, 4096), 1 << 18);
+    if (sh.k.dep && (rc = ws.trail.ensure(sizeof(int4) * (size_t)tcap * sh.grid)))
+        return rc;
+    const bool tstart_g = sh.k.dep && !sh.dep.tstart_lds;
+    if (tstart_g && (rc = ws.tstart.ensure(sizeof(int32_t) * (size_t)(cfg.max_depth + 1) * sh.grid)))
         return rc;
     const bool keep_sols = (mode == PCCP_ENUMERATE && n == 1 && cfg.sol_cap > 0);
     if (keep_sols && (rc = s0->sols.ensure(sizeof(int32_t) * (size_t)cfg.sol_cap * std::max(s0->c.ndec, 1))))
@@ -754,13 +880,19 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
     P.max_ndec = max_ndec;
     P.mlp = learned ? reinterpret_cast<const uint16_t *>(s0->mlp) : nullptr;
     for (int k = 0; k < 4; ++k) P.max_items[k] = max_items[k];
+    P.dep_vshift = sh.dep.vshift;
+    P.dep_qw = sh.dep.qw;
+    for (int k = 0; k < 4; ++k) P.dep_wcap[k] = sh.dep.wcap[k];
+    P.trail = sh.k.dep ? ws.trail.as<int4>() : nullptr;
+    P.tcap = tcap;
+    P.tstart_g = tstart_g ? ws.tstart.as<int32_t>() : nullptr;
 
     if (cfg.launch == 0) {
         // the graph bakes in the launch parameters: rebuild it when they change
         std::vector<char> key(sizeof(P) + 8 * sizeof(int64_t));
         memcpy(key.data(), &P, sizeof(P));
         const int64_t extra[8] = {sh.grid, sh.block, (int64_t)sh.lds, sh.k.desc_lds, sh.k.root_lds,
-                                  sh.k.learned, sh.k.live, sh.k.hi};
+                                  sh.k.learned, sh.k.live | (sh.k.dep << 1), sh.k.hi};
         memcpy(key.data() + sizeof(P), extra, sizeof(extra));
         if (!ws.graph || key != ws.graph_key) {
             if (ws.graph) (void)hipGraphExecDestroy(ws.graph);
@@ -813,6 +945,7 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
         o.lds_bytes = (int64_t)sh.lds;
         o.live = sh.k.live;
         o.occupancy = sh.k.hi ? 1 : 2;
+        o.dep = sh.k.dep;
         const bool done = is.outstanding == 0;
         o.ttpo_ms = done ? (double)(is.t_done - g.t_start) / (double)s->wall_khz : -1.0;
         if (done)
@@ -910,11 +1043,16 @@ extern "C" int32_t pccp_solver_capacity(const pccp_solver *s, int32_t *wgs_per_c
     fill_defaults(cfg);
     LaunchShape sh;
     HIPCHK(hipSetDevice(s->device));
-    const int items = (int)(s->c.diff.size() + s->c.reif.size() + s->c.rows.size() + s->c.brows.size());
-    const bool lists_ok = std::max(std::max(s->c.diff.size(), s->c.reif.size()),
-                                   std::max(s->c.rows.size(), s->c.brows.size())) <= 65536;
-    int32_t rc = choose_shape(cfg, s->c.nvars, s->desc_bytes, items, lists_ok, s->num_cus,
-                              s->lds_max, sh);
+    ShapeNeed need;
+    need.max_vars = s->c.nvars;
+    need.max_desc = s->desc_bytes;
+    need.max_items[0] = (int)s->c.diff.size();
+    need.max_items[1] = (int)s->c.reif.size();
+    need.max_items[2] = (int)s->c.rows.size();
+    need.max_items[3] = (int)s->c.brows.size();
+    need.lists_ok = *std::max_element(need.max_items, need.max_items + 4) <= 65536;
+    need.dep_ok = need.lists_ok;
+    int32_t rc = choose_shape(cfg, need, s->num_cus, s->lds_max, sh);
     if (rc != PCCP_OK) return rc;
     if (wgs_per_cu) *wgs_per_cu = sh.wgs_per_cu;
     if (num_cus) *num_cus = s->num_cus;

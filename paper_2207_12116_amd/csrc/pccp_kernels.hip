@@ -179,6 +179,10 @@ enum : int {
     C_SKIP = 27,                            // the record taken was dropped
     C_CNT = 12,                             // item-list counts: 5 words per list
                                             // (R, A, B) = 4 kinds, row terms
+    C_DCNT = 12,                            // or work-list counts: 6 words per set
+                                            // (2 sets) = 4 kinds, terms of kinds 3, 4
+    C_TTOP = 24,                            // entries pushed on the trail
+    C_THI = 25,                             // deepest path level without a whole trail
 };
 
 // ------------------------------------------------------------ descriptors
@@ -195,6 +199,8 @@ struct View {
     const int2 *brows_;
     const uint32_t *bterms_;
     const int32_t *dec_;
+    const int32_t *adjp_;         // always global memory
+    const uint32_t *adj_;
     // Indices are non-negative: taking them as unsigned lets a global load
     // use a uniform base plus a 32-bit per-lane offset.
     __device__ __forceinline__ int2 brows(int t) const { return DL ? brows_[(uint32_t)t] : gread(brows_ + (uint32_t)t); }
@@ -204,6 +210,8 @@ struct View {
     __device__ __forceinline__ int4 rows(int t) const { return DL ? rows_[(uint32_t)t] : gread(rows_ + (uint32_t)t); }
     __device__ __forceinline__ uint32_t terms(int t) const { return DL ? terms_[(uint32_t)t] : gread(terms_ + (uint32_t)t); }
     __device__ __forceinline__ int32_t dec(int t) const { return DL ? dec_[(uint32_t)t] : gread(dec_ + (uint32_t)t); }
+    __device__ __forceinline__ int32_t adjp(int x) const { return gread(adjp_ + (uint32_t)x); }
+    __device__ __forceinline__ uint32_t adj(int t) const { return gread(adj_ + (uint32_t)t); }
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
@@ -238,6 +246,7 @@ __device__ inline View<false> view_global(const DevModel &m)
     v.diff_ = uptr(m.diff); v.reif_ = uptr(m.reif); v.rows_ = uptr(m.rows);
     v.terms_ = uptr(m.terms); v.dec_ = uptr(m.dec);
     v.brows_ = uptr(m.brows); v.bterms_ = uptr(m.bterms);
+    v.adjp_ = uptr(m.adj_ptr); v.adj_ = uptr(m.adj);
     return v;
 }
 
@@ -275,6 +284,7 @@ __device__ inline View<true> stage_descriptors(const DevModel &m, char *dst)
     for (int i = tid; i < m.ndec; i += W) dec[i] = gread(m.dec + i);
     v.rows_ = rows; v.diff_ = diff; v.reif_ = reif; v.terms_ = terms; v.dec_ = dec;
     v.brows_ = brows; v.bterms_ = bterms;
+    v.adjp_ = uptr(m.adj_ptr); v.adj_ = uptr(m.adj);
     return v;
 }
 
@@ -333,6 +343,61 @@ __device__ __forceinline__ void compact(const ListIO &io, const bool (&keep)[U],
     }
 }
 
+// ------------------------------------------- dependency-driven propagation
+// A propagator has to run again only after a bound it reads was tightened
+// (chaotic iteration reaches the same least fixed point, §3 Theorem 2, as
+// long as no propagator whose input changed is left out).  With marks on,
+// every tell also sets its variable's bit in the sweep's change bitmap of
+// that bound (lm / um); between sweeps the bitmaps are expanded through the
+// variable -> propagator adjacency into the next sweep's work lists.
+//
+// The trail.  With trail_on, the first tell of a node on a variable also
+// pushes the variable's (lb, ub) as the lane read it onto the workgroup's
+// trail, so that a backtrack can restore the parent's store instead of
+// recomputing it.  The value pushed is the one before the node: every tell
+// is issued after its lane's test-and-set of the variable's trail bit (tm),
+// LDS operations of a wavefront execute in issue order, and the lane that
+// wins the bit read the variable before its own test-and-set, so before any
+// tell of the node (each of which follows a losing or winning test-and-set
+// that came later).
+struct Dep {
+    uint32_t *lm, *um;        // bounds tightened in this sweep (lb / ub)
+    uint32_t *tm;             // variables already on this node's trail
+    uint32_t *qm;             // propagators already on the next work lists
+    uint16_t *wl;             // work lists: kind k at wl + woff[k], wcap[k] entries
+    int4 *trail;              // this workgroup's trail (global), tcap entries
+    int32_t *ttop;            // LDS word: entries pushed (may pass tcap)
+    int vshift, vmask, vw, qw;
+    int woff[4], wcap[4], qoff[4];
+    int tcap;
+    bool trail_on;
+};
+
+__device__ __forceinline__ void trail_push(const Dep &dp, int x, int2 rd)
+{
+    const int pos = __hip_atomic_fetch_add(dp.ttop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (pos < dp.tcap) gwrite4(dp.trail + pos, make_int4(x, rd.x, rd.y, 0));
+}
+
+// tell lb(x) >= v (or ub(x) <= v) with marks: rd = (lb, ub) of x as the lane
+// read it before deciding to tell
+template <bool MK, bool LB>
+__device__ __forceinline__ void tell_m(int2 *st, const Dep &dp, int x, int32_t v, int2 rd)
+{
+    if constexpr (MK) {
+        const uint32_t w = (uint32_t)x & (uint32_t)dp.vmask, bit = 1u << ((uint32_t)x >> dp.vshift);
+        uint32_t old = bit;
+        if (dp.trail_on)
+            old = __hip_atomic_fetch_or(dp.tm + w, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __builtin_amdgcn_sched_barrier(0);
+        if (LB) tell_lb(st, x, v); else tell_ub(st, x, v);
+        __hip_atomic_fetch_or((LB ? dp.lm : dp.um) + w, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (!(old & bit)) trail_push(dp, x, rd);
+    } else {
+        if (LB) tell_lb(st, x, v); else tell_ub(st, x, v);
+    }
+}
+
 // Sum over the `G` lanes of a row group (G = 4, 8 or 16; groups are aligned
 // so that every DPP source lane is in the same group).
 __device__ __forceinline__ int group_sum(int x, int G)
@@ -346,9 +411,9 @@ __device__ __forceinline__ int group_sum(int x, int G)
 
 // kind 1: x - y <= c  =>  ub(x) <= c + ub(y),  lb(y) >= lb(x) - c;
 // entailed once ub(x) - lb(y) <= c.
-template <bool DL>
+template <bool DL, bool MK = false>
 __device__ __forceinline__ void sweep_diff(const View<DL> &v, int2 *st, const ListIO &io,
-                                           bool &chg, bool &bad)
+                                           const Dep &dp, bool &chg, bool &bad)
 {
     constexpr int U = 2;
     const int tid = threadIdx.x, lane = tid & 63, W = blockDim.x, n = io.n;
@@ -392,8 +457,8 @@ __device__ __forceinline__ void sweep_diff(const View<DL> &v, int2 *st, const Li
             for (int u = 0; u < U; ++u) {
                 const int x = e[u].x & 0xffff, y = (uint32_t)e[u].x >> 16, c = e[u].y;
                 const int nu = c + dy[u].y, nl = dx[u].x - c;
-                if (pu[u]) { tell_ub(st, x, nu); chg = true; bad |= nu < dx[u].x; }
-                if (pl[u]) { tell_lb(st, y, nl); chg = true; bad |= nl > dy[u].y; }
+                if (pu[u]) { tell_m<MK, false>(st, dp, x, nu, dx[u]); chg = true; bad |= nu < dx[u].x; }
+                if (pl[u]) { tell_m<MK, true>(st, dp, y, nl, dy[u]); chg = true; bad |= nl > dy[u].y; }
             }
         }
         if (io.out) {
@@ -420,9 +485,9 @@ __device__ __forceinline__ void sweep_diff(const View<DL> &v, int2 *st, const Li
 // and is told only if that value is tighter than the bound read.
 // Entailed once b = 1 with both conjuncts entailed, or b = 0 with one of
 // them disentailed (lb(si) > ub(sj), or lb(sj) >= ub(si) + d).
-template <bool DL, int U>
+template <bool DL, int U, bool MK = false>
 __device__ __forceinline__ void sweep_reif(const View<DL> &v, int2 *st, const ListIO &io,
-                                           bool &chg, bool &bad)
+                                           const Dep &dp, bool &chg, bool &bad)
 {
     const int tid = threadIdx.x, lane = tid & 63, W = blockDim.x, n = io.n;
     for (int c0 = uni(tid - lane); c0 < n; c0 += U * W) {
@@ -484,12 +549,12 @@ __device__ __forceinline__ void sweep_reif(const View<DL> &v, int2 *st, const Li
                 continue;
             const int b = e[u].x & 0xffff, i = (uint32_t)e[u].x >> 16, j = e[u].y & 0xffff;
             chg = true;
-            if (t_b1) { tell_lb(st, b, 1); bad |= ubb < 1; }
-            if (t_b0) { tell_ub(st, b, 0); bad |= lbb > 0; }
-            if (p_ui) { tell_ub(st, i, nui); bad |= nui < lbi; }
-            if (p_lj) { tell_lb(st, j, nlj); bad |= nlj > ubj; }
-            if (p_uj) { tell_ub(st, j, nuj); bad |= nuj < lbj; }
-            if (p_li) { tell_lb(st, i, nli); bad |= nli > ubi; }
+            if (t_b1) { tell_m<MK, true>(st, dp, b, 1, db[u]); bad |= ubb < 1; }
+            if (t_b0) { tell_m<MK, false>(st, dp, b, 0, db[u]); bad |= lbb > 0; }
+            if (p_ui) { tell_m<MK, false>(st, dp, i, nui, di[u]); bad |= nui < lbi; }
+            if (p_lj) { tell_m<MK, true>(st, dp, j, nlj, dj[u]); bad |= nlj > ubj; }
+            if (p_uj) { tell_m<MK, false>(st, dp, j, nuj, dj[u]); bad |= nuj < lbj; }
+            if (p_li) { tell_m<MK, true>(st, dp, i, nli, di[u]); bad |= nli > ubi; }
         }
         if (io.out) compact<U>(io, keep, idx);
     }
@@ -503,17 +568,18 @@ __device__ __forceinline__ bool term_tight(int a, int lbx, int ubx, int rhs, int
     return a > 0 ? rhs - (S - a * lbx) < a * ubx : rhs - (S - a * ubx) < a * lbx;
 }
 
-__device__ __forceinline__ void term_tell(int2 *st, int x, int a, int lbx, int ubx,
+template <bool MK = false>
+__device__ __forceinline__ void term_tell(int2 *st, const Dep &dp, int x, int a, int lbx, int ubx,
                                           int rhs, int S, bool &chg, bool &bad)
 {
     if (a > 0) {
         const int rr = rhs - (S - a * lbx);                 // a x <= rr
         const int nb = a == 1 ? rr : floor_div_pos(rr, a);
-        tell_ub(st, x, nb); chg = true; bad |= nb < lbx;
+        tell_m<MK, false>(st, dp, x, nb, make_int2(lbx, ubx)); chg = true; bad |= nb < lbx;
     } else {
         const int rr = rhs - (S - a * ubx);                 // x >= ceil(rr / a)
         const int nb = a == -1 ? -rr : -floor_div_pos(rr, -a);
-        tell_lb(st, x, nb); chg = true; bad |= nb > ubx;
+        tell_m<MK, true>(st, dp, x, nb, make_int2(lbx, ubx)); chg = true; bad |= nb > ubx;
     }
 }
 
@@ -524,9 +590,9 @@ __device__ __forceinline__ void term_tell(int2 *st, int x, int a, int lbx, int u
 // time per group; when every row fits in one chunk of TK terms per lane the
 // tells use the bounds already in registers.  Entailed once the sum of the
 // terms' largest values is at most rhs.
-template <bool DL, int RR>
+template <bool DL, int RR, bool MK = false>
 __device__ __forceinline__ void sweep_rows(const View<DL> &v, int2 *st, const ListIO &io,
-                                           bool &chg, bool &bad)
+                                           const Dep &dp, bool &chg, bool &bad)
 {
     constexpr int TK = 2;
     const int tid = threadIdx.x, W = blockDim.x, n = io.n;
@@ -593,8 +659,8 @@ __device__ __forceinline__ void sweep_rows(const View<DL> &v, int2 *st, const Li
 #pragma unroll
                     for (int k = 0; k < TK; ++k)
                         if (tight[q][k])
-                            term_tell(st, tv[q][k] & 0xffff, (int32_t)tv[q][k] >> 16,
-                                      td[q][k].x, td[q][k].y, rd[q].z, S[q], chg, bad);
+                            term_tell<MK>(st, dp, tv[q][k] & 0xffff, (int32_t)tv[q][k] >> 16,
+                                          td[q][k].x, td[q][k].y, rd[q].z, S[q], chg, bad);
             }
         } else {
             // long rows: sum chunk by chunk, then tell chunk by chunk
@@ -629,7 +695,7 @@ __device__ __forceinline__ void sweep_rows(const View<DL> &v, int2 *st, const Li
                         // was formed: the tell is then weaker, never unsound
                         const int2 dx = dom(st, x);
                         if (term_tight(a, dx.x, dx.y, rd[q].z, S[q]))
-                            term_tell(st, x, a, dx.x, dx.y, rd[q].z, S[q], chg, bad);
+                            term_tell<MK>(st, dp, x, a, dx.x, dx.y, rd[q].z, S[q], chg, bad);
                     }
                 }
             }
@@ -658,9 +724,9 @@ __device__ __forceinline__ void sweep_rows(const View<DL> &v, int2 *st, const Li
 // their addresses do not wait for the row descriptor; unused slots hold
 // a = 0.  Entailed once the sum of a_t over the terms with ub(b_t) = 1 is at
 // most rhs.
-template <bool DL, int RB>
+template <bool DL, int RB, bool MK = false>
 __device__ __forceinline__ void sweep_brows(const View<DL> &v, int2 *st, const ListIO &io,
-                                            bool &chg, bool &bad)
+                                            const Dep &dp, bool &chg, bool &bad)
 {
     constexpr int TB = 4;                   // term slots per lane held in registers
     const int tid = threadIdx.x, W = blockDim.x, n = io.n;
@@ -724,7 +790,8 @@ __device__ __forceinline__ void sweep_brows(const View<DL> &v, int2 *st, const L
 #pragma unroll
                     for (int k = 0; k < TB; ++k)
                         if (tight & (1u << (q * TB + k))) {
-                            tell_ub(st, tv[q][k] & 0xffff, 0);
+                            // an open term of a 0/1 variable reads (0, 1)
+                            tell_m<MK, false>(st, dp, tv[q][k] & 0xffff, 0, make_int2(0, 1));
                             chg = true;
                         }
             }
@@ -760,7 +827,7 @@ __device__ __forceinline__ void sweep_brows(const View<DL> &v, int2 *st, const L
                     // formed: an open term is still told soundly
                     const int2 dx = dom(st, t & 0xffff);
                     if (rok[q] && a > 0 && a > rd[q].x - S[q] && dx.x < dx.y) {
-                        tell_ub(st, t & 0xffff, 0);
+                        tell_m<MK, false>(st, dp, t & 0xffff, 0, dx);
                         chg = true;
                         bad |= dx.x > 0;
                     }
@@ -788,6 +855,7 @@ __device__ __forceinline__ void sweep_brows(const View<DL> &v, int2 *st, const L
 // their counts in cnt[k] and the kept rows' terms in cnt[4]; later sweeps
 // run the kept lists.
 constexpr int kKinds = 4;
+constexpr int kKindsDep = 4;
 constexpr int kListWords = kKinds + 1;
 static_assert(C_CNT + 3 * kListWords <= 32, "list counts must stay below the control lane's state");
 struct NodeLists {
@@ -829,12 +897,13 @@ __device__ int propagate_wg(const View<DL> &v, int2 *st, int32_t *ctl, const Nod
     ListIO b{L.in[3], L.nin[3], L.out[3], cmp ? L.cnt + 3 : nullptr, tc};
     int terms = L.tin;
     int slot = 0;
+    const Dep nodep{};
     for (;;) {
         bool chg = false, bad = false;
-        sweep_diff(v, st, d, chg, bad);
-        sweep_reif<DL, LEAN ? 2 : 4>(v, st, r, chg, bad);
-        sweep_rows<DL, LEAN ? 2 : 4>(v, st, w, chg, bad);
-        sweep_brows<DL, LEAN ? 1 : 2>(v, st, b, chg, bad);
+        sweep_diff(v, st, d, nodep, chg, bad);
+        sweep_reif<DL, LEAN ? 2 : 4>(v, st, r, nodep, chg, bad);
+        sweep_rows<DL, LEAN ? 2 : 4>(v, st, w, nodep, chg, bad);
+        sweep_brows<DL, LEAN ? 1 : 2>(v, st, b, nodep, chg, bad);
         ex[0] += (unsigned)d.n;
         ex[1] += (unsigned)r.n;
         ex[2] += (unsigned)(w.n + b.n);
@@ -859,6 +928,168 @@ __device__ int propagate_wg(const View<DL> &v, int2 *st, int32_t *ctl, const Nod
             b = ListIO{b.out, uni(lds_ld(&L.cnt[3])), nullptr, nullptr, nullptr};
             terms = uni(lds_ld(&L.cnt[kKinds]));
         }
+    }
+}
+
+// Work lists of the next sweep from the change bitmaps of the last one:
+// every propagator that reads a tightened bound, once (the queued bit qm of
+// a propagator is set when it is listed).  Clears the bitmaps.  cnt: list
+// counts of the 4 kinds, then the terms of the listed rows of kinds 3 and
+// 4; zeroed by the caller before a barrier.  A count past its list's
+// capacity means the next sweep runs that kind's whole table.
+// Bitmap word w is read by wavefront w % nw, so the variables of one
+// region of the store (the start times, say) spread over all wavefronts.
+template <bool DL>
+__device__ void dep_expand(const View<DL> &v, const Dep &dp, int32_t *cnt)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int base = 0; base < dp.vw; base += 64 * nw) {
+        const int w = base + wid + nw * lane;
+        uint32_t bl = 0, bu = 0;
+        if (w < dp.vw) {
+            bl = dp.lm[w];
+            bu = dp.um[w];
+            if (bl | bu) {
+                dp.lm[w] = 0;
+                dp.um[w] = 0;
+            }
+        }
+        unsigned long long act = __ballot((bl | bu) != 0);
+        while (act) {
+            const int L = __builtin_ctzll(act);
+            act &= act - 1;
+            const uint32_t ml = (uint32_t)__builtin_amdgcn_readlane((int)bl, L);
+            const uint32_t mu = (uint32_t)__builtin_amdgcn_readlane((int)bu, L);
+            const int wl = base + wid + nw * L;
+            uint32_t bits = ml | mu;
+            while (bits) {
+                const int b = __builtin_ctz(bits);
+                bits &= bits - 1;
+                const int x = (b << dp.vshift) | wl;
+                const uint32_t reads = (((ml >> b) & 1u) ? kAdjLb : 0u) | (((mu >> b) & 1u) ? kAdjUb : 0u);
+                const int a0 = uni(v.adjp(x)), a1 = uni(v.adjp(x + 1));
+                for (int a = a0; a < a1; a += 64) {
+                    const int ai = a + lane;
+                    const uint32_t e = ai < a1 ? v.adj(ai) : 0u;
+                    const int k = (int)((e >> 16) & 3u), idx = (int)(e & 0xffffu);
+                    bool fire = (e & reads) != 0;
+                    if (fire) {
+                        const int p = idx + (k == 0 ? dp.qoff[0] : k == 1 ? dp.qoff[1]
+                                             : k == 2 ? dp.qoff[2] : dp.qoff[3]);
+                        const uint32_t qb = 1u << (p & 31);
+                        fire = !(__hip_atomic_fetch_or(dp.qm + (p >> 5), qb, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP) & qb);
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < kKindsDep; ++kk) {
+                        const unsigned long long mk = __ballot(fire && k == kk);
+                        if (mk == 0) continue;
+                        int pos = 0;
+                        if (lane == 0)
+                            pos = __hip_atomic_fetch_add(cnt + kk, __popcll(mk), __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+                        pos = __builtin_amdgcn_readfirstlane(pos);
+                        if (fire && k == kk) {
+                            const int r = pos + (int)__builtin_amdgcn_mbcnt_hi(
+                                                    (uint32_t)(mk >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+                            if (r < dp.wcap[kk]) dp.wl[dp.woff[kk] + r] = (uint16_t)idx;
+                            if (kk >= 2)
+                                __hip_atomic_fetch_add(cnt + 2 + kk,
+                                                       kk == 2 ? v.rows(idx).y : v.brows(idx).y,
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Fixed point of `st` with dependency-driven sweeps.  full: the first sweep
+// runs every table (the store is new: a subtree root or a recomputed node;
+// marks left by an earlier node are cleared); otherwise the store is a
+// fixed point joined with the tells marked since (a decision, the objective
+// bound), and the first sweep runs what they make ready.  Returns as
+// propagate_wg; ex[] counts the items and row terms run.
+template <bool DL, bool LEAN>
+__device__ int propagate_dep(const View<DL> &v, int2 *st, int32_t *ctl, const Dep &dp, bool full,
+                             uint32_t &nsweeps, unsigned long long (&ex)[4])
+{
+    const int tid = threadIdx.x, lane = tid & 63, W = blockDim.x;
+    if (tid == 0) {
+        ctl[C_FLAG0] = 0;
+        ctl[C_FLAG1] = 0;
+        ctl[C_FLAG2] = 0;
+        ctl[C_POSTFAIL] = 0;
+        *reinterpret_cast<unsigned long long *>(ctl + C_KEY) = ~0ull;
+        for (int k = 0; k < 12; ++k) ctl[C_DCNT + k] = 0;
+    }
+    if (full)
+        for (int w = tid; w < dp.vw; w += W) {
+            dp.lm[w] = 0;
+            dp.um[w] = 0;
+            dp.tm[w] = 0;
+        }
+    lds_barrier();
+    int set = 0;   // count set of the lists the next sweep runs
+    if (!full) {
+        dep_expand(v, dp, ctl + C_DCNT);
+        lds_barrier();
+    }
+    const int tab[4] = {v.ndiff, v.nreif, v.nrows, v.nbrows};
+    int slot = 0;
+    bool all = full;
+    for (;;) {
+        const int32_t *c = ctl + C_DCNT + 6 * set;
+        ListIO io[4];
+        bool whole[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int n = all ? 0 : uni(lds_ld(&c[k]));
+            whole[k] = all || n > dp.wcap[k];
+            io[k] = whole[k] ? ListIO{nullptr, tab[k], nullptr, nullptr, nullptr}
+                             : ListIO{dp.wl + dp.woff[k], n, nullptr, nullptr, nullptr};
+        }
+        const int terms = (whole[2] ? v.nterms : uni(lds_ld(&c[4]))) +
+                          (whole[3] ? v.nbterms : uni(lds_ld(&c[5])));
+        if (tid == 0)
+            for (int k = 0; k < 6; ++k) ctl[C_DCNT + 6 * (set ^ 1) + k] = 0;
+        // the queued bits of the lists run now are cleared for the next expansion
+        for (int w = tid; w < dp.qw; w += W) dp.qm[w] = 0;
+        bool chg = false, bad = false;
+        sweep_diff<DL, true>(v, st, io[0], dp, chg, bad);
+        sweep_reif<DL, LEAN ? 2 : 4, true>(v, st, io[1], dp, chg, bad);
+        sweep_rows<DL, LEAN ? 2 : 4, true>(v, st, io[2], dp, chg, bad);
+        sweep_brows<DL, LEAN ? 1 : 2, true>(v, st, io[3], dp, chg, bad);
+        ex[0] += (unsigned)io[0].n;
+        ex[1] += (unsigned)io[1].n;
+        ex[2] += (unsigned)(io[2].n + io[3].n);
+        ex[3] += (unsigned)terms;
+        const int flags = (__any(chg) ? 1 : 0) | (__any(bad) ? 2 : 0);
+        if (lane == 0 && flags)
+            __hip_atomic_fetch_or(&ctl[slot], flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int next = slot == 2 ? 0 : slot + 1;
+        if (tid == 0)
+            ctl[next] = 0;
+        lds_barrier();
+        ++nsweeps;
+        const int f = lds_ld(&ctl[slot]);
+        if (f & 2) {
+            // marks of the failed sweep: the next node starts from a store
+            // where none of them applies
+            for (int w = tid; w < dp.vw; w += W) {
+                dp.lm[w] = 0;
+                dp.um[w] = 0;
+            }
+            return 1;
+        }
+        if (!(f & 1)) return 0;
+        slot = next;
+        set ^= 1;
+        all = false;
+        dep_expand(v, dp, ctl + C_DCNT + 6 * set);
+        lds_barrier();
     }
 }
 
@@ -1208,6 +1439,16 @@ __device__ unsigned long long solution_hash(const int2 *st, const View<DL> &v, i
 
 
 // ------------------------------------------------------------ search
+// A tell by one thread outside the sweeps (a decision, the objective
+// bound), with marks and, with dp.trail_on, the trail.
+template <bool LB>
+__device__ __forceinline__ void tell_one(int2 *st, const Dep &dp, int x, int32_t v)
+{
+    const int2 d = st[x];
+    if (LB ? v <= d.x : v >= d.y) return;
+    tell_m<true, LB>(st, dp, x, v, d);
+}
+
 // State only lane 0 uses lives in LDS (not in every lane's registers).
 struct Lane0 {
     unsigned long long nodes, fails, sols, sweeps, don, maxd;
@@ -1241,9 +1482,10 @@ __device__ void flush_counters(Lane0 &z, InstState *is, int mode)
 // HI: workgroups of at most 256 threads and at least 7 wavefronts per SIMD
 // (at most 72 VGPRs): more resident subproblems per CU to hide the latency
 // of the dependent loads, with leaner unrolling.
-template <bool DL, bool RL, bool LEARN, bool LIVE, bool HI>
+template <bool DL, bool RL, bool LEARN, int PM, bool HI>
 __global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(SearchParams P)
 {
+    constexpr bool LIVE = PM == 1, DEP = PM == 2;
     extern __shared__ __align__(16) char smem[];
     const int tid = threadIdx.x, W = blockDim.x;
     const int Vp = (P.max_vars + 3) & ~3;
@@ -1267,6 +1509,43 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(Sea
     const int lcap = (int)(align16(2 * (size_t)(P.max_items[0] + P.max_items[1] + P.max_items[2] +
                                                 P.max_items[3])) / 2);
     if (LIVE) p += 2 * 3 * (size_t)lcap;
+    // dependency-driven propagation: trail start of every path level, the
+    // three variable bitmaps, the propagator marks and the work lists
+    // (the trail starts go to global memory when LDS is short: then the
+    // pointer is generic)
+    int32_t *tstart = P.tstart_g ? P.tstart_g + (size_t)blockIdx.x * (size_t)(P.max_depth + 1)
+                                 : reinterpret_cast<int32_t *>(p);
+    Dep dp{};
+    if (DEP) {
+        if (!P.tstart_g) p += align16(4 * (size_t)(P.max_depth + 1));
+        const int vw = 1 << P.dep_vshift;
+        dp.lm = reinterpret_cast<uint32_t *>(p);
+        dp.um = dp.lm + vw;
+        dp.tm = dp.um + vw;
+        p += align16(12 * (size_t)vw);
+        dp.qm = reinterpret_cast<uint32_t *>(p);
+        p += align16(4 * (size_t)P.dep_qw);
+        dp.wl = reinterpret_cast<uint16_t *>(p);
+        p += align16(2 * (size_t)(P.dep_wcap[0] + P.dep_wcap[1] + P.dep_wcap[2] + P.dep_wcap[3]));
+        dp.vshift = P.dep_vshift;
+        dp.vmask = vw - 1;
+        dp.vw = vw;
+        dp.qw = P.dep_qw;
+        int wo = 0, qo = 0;
+        for (int k = 0; k < 4; ++k) {
+            dp.woff[k] = wo;
+            dp.wcap[k] = P.dep_wcap[k];
+            dp.qoff[k] = qo;
+            wo += P.dep_wcap[k];
+            qo += P.max_items[k];
+        }
+        dp.trail = P.trail + (size_t)blockIdx.x * (size_t)P.tcap;
+        dp.tcap = P.tcap;
+        dp.ttop = ctl + C_TTOP;
+        dp.trail_on = false;
+        for (int w = tid; w < 3 * vw; w += W) dp.lm[w] = 0;
+        for (int w = tid; w < P.dep_qw; w += W) dp.qm[w] = 0;
+    }
     char *dsc = p;
     const int koff[kKinds] = {0, P.max_items[0], P.max_items[0] + P.max_items[1],
                               P.max_items[0] + P.max_items[1] + P.max_items[2]};
@@ -1356,6 +1635,13 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(Sea
         const int depth0 = len;
         int depth = len;
         bool first = true;
+        // DEP: the node's store is new (subtree root, recomputed node): the
+        // first sweep runs every table and nothing goes on the trail
+        bool node_full = true;
+        if (DEP && tid == 0) {
+            ctl[C_TTOP] = 0;
+            ctl[C_THI] = depth0;
+        }
         bool finished = false;
         // item lists: 0 = whole tables, 1 = R, 2 = A, 3 = B
         int in_sel = 0, out_sel = 1;
@@ -1385,8 +1671,14 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(Sea
                 ctl[C_STOP] = stop;
                 if (!stop && P.mode == 1) {
                     if (z.pf_best < z.local_best) z.local_best = z.pf_best;
-                    if (z.local_best != INT32_MAX)
-                        tell_ub(st, objective, z.local_best - 1);
+                    if (z.local_best != INT32_MAX) {
+                        if constexpr (DEP) {
+                            dp.trail_on = !node_full;
+                            tell_one<false>(st, dp, objective, z.local_best - 1);
+                        } else {
+                            tell_ub(st, objective, z.local_best - 1);
+                        }
+                    }
                 }
                 // loads consumed at the next node, so their latency overlaps
                 // this node's propagation
@@ -1428,7 +1720,17 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(Sea
             }
             uint32_t nsw = 0;
             unsigned long long ex[4] = {0, 0, 0, 0};
-            const int rc = propagate_wg<DL, LIVE, LIVE || HI>(v, st, ctl, L, nsw, ex);
+            int rc;
+            if constexpr (DEP) {
+                dp.trail_on = !node_full;
+                rc = propagate_dep<DL, HI>(v, st, ctl, dp, node_full, nsw, ex);
+                // the next node's trail marks start empty; a node whose
+                // changes did not all fit on the trail cannot be undone
+                for (int w = tid; w < dp.vw; w += W) dp.tm[w] = 0;
+                if (tid == 0 && !node_full && lds_ld(ctl + C_TTOP) > dp.tcap) ctl[C_THI] = depth;
+            } else {
+                rc = propagate_wg<DL, LIVE, LIVE || HI>(v, st, ctl, L, nsw, ex);
+            }
             post_scan(v, st, ctl, branching, rc == 0, fsc, P.mlp, &m);
             const int failed = uni(rc | lds_ld(&ctl[C_POSTFAIL]));
             const unsigned long long key =
@@ -1509,7 +1811,15 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(Sea
                     const int x = v.dec(q);
                     const int val = st[x].x;
                     stack[depth] = make_int2(x, val);
-                    st[x].y = val;  // left child: x = lb(x)
+                    if constexpr (DEP) {
+                        // left child: x = lb(x), the first entry of its trail
+                        tstart[depth + 1] = ctl[C_TTOP];
+                        Dep d1 = dp;
+                        d1.trail_on = true;
+                        tell_one<false>(st, d1, x, val);
+                    } else {
+                        st[x].y = val;  // left child: x = lb(x)
+                    }
                     // donate the open right branch closest to the subtree
                     // root when other workgroups are waiting for work
                     if (P.donate && z.pf_idle > 0 && z.pf_qt - z.pf_qh < (unsigned long long)z.pf_idle) {
@@ -1537,6 +1847,7 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(Sea
                     }
                 }
                 ++depth;
+                node_full = false;
                 lds_barrier();
                 continue;
             }
@@ -1556,6 +1867,40 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(Sea
             if (nd < 0) {
                 finished = true;
                 break;
+            }
+            if constexpr (DEP) {
+                if (nd > uni(lds_ld(ctl + C_THI))) {
+                    // undo the trail of the levels below nd, deepest first
+                    // (a variable changed at several levels gets the value
+                    // of the shallowest), then the flipped decision
+                    full_barrier();  // the trail stores of every lane are visible
+                    const int top = uni(lds_ld(ctl + C_TTOP));
+                    for (int k = depth; k >= nd; --k) {
+                        const int e0 = uni(tstart[k]);
+                        const int e1 = k == depth ? top : uni(tstart[k + 1]);
+                        for (int i = e0 + tid; i < e1; i += W) {
+                            const int4 t = gread(dp.trail + i);
+                            st[t.x] = make_int2(t.y, t.z);
+                        }
+                        lds_barrier();
+                    }
+                    depth = nd;
+                    if (tid == 0) {
+                        ctl[C_TTOP] = tstart[nd];
+                        const int2 dcs = stack[nd - 1];
+                        Dep d1 = dp;
+                        d1.trail_on = true;
+                        tell_one<true>(st, d1, dcs.x & 0xffff, dcs.y + 1);
+                    }
+                    node_full = false;
+                    lds_barrier();
+                    continue;
+                }
+                if (tid == 0) {
+                    ctl[C_THI] = nd;
+                    ctl[C_TTOP] = tstart[nd];
+                }
+                node_full = true;
             }
             depth = nd;
             // recompute: subtree root fixed point + decisions below it
@@ -1845,7 +2190,7 @@ hipError_t launch_mlp_scores(const float *params, const uint16_t *wbf, int use_b
 
 // ------------------------------------------------------------ launchers
 size_t search_lds_bytes(int max_vars, int max_depth, size_t max_desc, bool desc_lds, bool root_lds,
-                        int feat_ndec, int list_items)
+                        int feat_ndec, int list_items, size_t dep_bytes)
 {
     const size_t Vp = (size_t)((max_vars + 3) & ~3);
     size_t b = sizeof(int32_t) * kCtlWords + Vp * sizeof(int2);
@@ -1853,8 +2198,16 @@ size_t search_lds_bytes(int max_vars, int max_depth, size_t max_desc, bool desc_
     b += align16(sizeof(int2) * (size_t)max_depth);
     if (feat_ndec > 0) b += align16(32 * (size_t)feat_ndec);
     if (list_items > 0) b += 3 * align16(sizeof(uint16_t) * (size_t)list_items);
+    b += dep_bytes;
     if (desc_lds) b += max_desc;
     return align16(b);
+}
+
+size_t dep_lds_bytes(int max_depth, bool tstart_lds, int vshift, int qw, const int wcap[4])
+{
+    return (tstart_lds ? align16(4 * (size_t)(max_depth + 1)) : 0) +
+           align16(12 * ((size_t)1 << vshift)) + align16(4 * (size_t)qw) +
+           align16(2 * (size_t)(wcap[0] + wcap[1] + wcap[2] + wcap[3]));
 }
 
 size_t propagate_lds_bytes(int nvars, size_t desc, bool desc_lds)
@@ -1901,25 +2254,30 @@ hipError_t launch_propagate_batch(const DevModel *m_dev, int nbox, const int32_t
     return hipGetLastError();
 }
 
-// the search kernel variant for a layout, branching rule, list mode and
+// the search kernel variant for a layout, branching rule, propagation mode
+// (0 every propagator every sweep, 1 item lists, 2 dependency-driven) and
 // occupancy class
-template <bool L, bool V, bool H>
+template <bool L, int PM, bool H>
 static const void *search_fn_lv(bool desc_lds, bool root_lds)
 {
-    if (desc_lds && root_lds) return reinterpret_cast<const void *>(search_kernel<true, true, L, V, H>);
-    if (desc_lds) return reinterpret_cast<const void *>(search_kernel<true, false, L, V, H>);
-    if (root_lds) return reinterpret_cast<const void *>(search_kernel<false, true, L, V, H>);
-    return reinterpret_cast<const void *>(search_kernel<false, false, L, V, H>);
+    if (desc_lds && root_lds) return reinterpret_cast<const void *>(search_kernel<true, true, L, PM, H>);
+    if (desc_lds) return reinterpret_cast<const void *>(search_kernel<true, false, L, PM, H>);
+    if (root_lds) return reinterpret_cast<const void *>(search_kernel<false, true, L, PM, H>);
+    return reinterpret_cast<const void *>(search_kernel<false, false, L, PM, H>);
+}
+
+template <bool L, bool H>
+static const void *search_fn_l(const SearchShape &k)
+{
+    if (k.dep) return search_fn_lv<L, 2, H>(k.desc_lds, k.root_lds);
+    if (k.live) return search_fn_lv<L, 1, H>(k.desc_lds, k.root_lds);
+    return search_fn_lv<L, 0, H>(k.desc_lds, k.root_lds);
 }
 
 template <bool H>
 static const void *search_fn_h(const SearchShape &k)
 {
-    if (k.learned)
-        return k.live ? search_fn_lv<true, true, H>(k.desc_lds, k.root_lds)
-                      : search_fn_lv<true, false, H>(k.desc_lds, k.root_lds);
-    return k.live ? search_fn_lv<false, true, H>(k.desc_lds, k.root_lds)
-                  : search_fn_lv<false, false, H>(k.desc_lds, k.root_lds);
+    return k.learned ? search_fn_l<true, H>(k) : search_fn_l<false, H>(k);
 }
 
 static const void *search_fn(const SearchShape &k)

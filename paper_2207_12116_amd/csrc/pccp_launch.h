@@ -12,7 +12,12 @@ size_t model_desc_bytes(int ndiff, int nreif, int nrows, int nterms, int ndec, i
 // list_items: sum over kinds of the largest table in the launch when the
 // search keeps item lists (three LDS buffers of 16-bit indices), else 0
 size_t search_lds_bytes(int max_vars, int max_depth, size_t max_desc, bool desc_lds, bool root_lds,
-                        int feat_ndec, int list_items);
+                        int feat_ndec, int list_items, size_t dep_bytes);
+// LDS of dependency-driven propagation: trail starts of max_depth + 1 path
+// levels (unless they are in global memory), three variable bitmaps of
+// 1 << vshift words, qw words of propagator marks and work lists of wcap[k]
+// 16-bit entries
+size_t dep_lds_bytes(int max_depth, bool tstart_lds, int vshift, int qw, const int wcap[4]);
 size_t propagate_lds_bytes(int nvars, size_t desc, bool desc_lds);
 
 hipError_t launch_propagate_batch(const DevModel *m_dev, int nbox, const int32_t *lb_in,
@@ -21,10 +26,12 @@ hipError_t launch_propagate_batch(const DevModel *m_dev, int nbox, const int32_t
                                   size_t lds, bool desc_lds, hipStream_t stream);
 
 // Which search-kernel variant: descriptor tables in LDS, subtree-root store
-// in LDS, learned branching, item lists of non-entailed propagators, and the
-// high-occupancy build for workgroups of at most 256 threads.
+// in LDS, learned branching, item lists of non-entailed propagators,
+// dependency-driven propagation with a trail, and the high-occupancy build
+// for workgroups of at most 256 threads.
 struct SearchShape {
     bool desc_lds = false, root_lds = false, learned = false, live = false, hi = false;
+    bool dep = false;
 };
 
 hipError_t launch_search(const SearchParams &P, int grid, int block, size_t lds,

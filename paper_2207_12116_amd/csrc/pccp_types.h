@@ -56,7 +56,15 @@ struct DevModel {
     const int2 *fr;
     const int32_t *fb_ptr;
     const int32_t *fb;
+    // dependency-driven propagation: the propagators that read variable x
+    // are adj[adj_ptr[x]..adj_ptr[x+1]), entry = index in its kind's table
+    // | kind << 16 (0 difference rows, 1 reified items, 2 linear rows,
+    // 3 Boolean rows) | reads lb(x) << 18 | reads ub(x) << 19
+    const int32_t *adj_ptr;
+    const uint32_t *adj;
 };
+constexpr uint32_t kAdjLb = 1u << 18;
+constexpr uint32_t kAdjUb = 1u << 19;
 
 constexpr int kNumFeat = 6;
 constexpr int kHidden = 64;
@@ -128,6 +136,17 @@ struct SearchParams {
     int32_t pad;
     const uint16_t *mlp;        // learned branching: bf16 parameters (513), or null
     int32_t max_items[4];       // largest table per kind in the launch (item lists)
+    // dependency-driven propagation (see the search kernel): variable
+    // bitmaps of 1 << dep_vshift words (x at word x & mask, bit x >> shift),
+    // dep_qw words of propagator marks, work lists of dep_wcap[k] entries,
+    // and a trail of tcap entries per workgroup in global memory
+    int32_t dep_vshift, dep_qw;
+    int32_t dep_wcap[4];
+    int4 *trail;                // [grid * tcap] {x, lb, ub, 0}
+    int32_t tcap;
+    int32_t pad2;
+    int32_t *tstart_g;          // trail start of each path level, [grid * (max_depth + 1)],
+                                // or null: in LDS
 };
 
 }  // namespace pccp

@@ -37,7 +37,7 @@ class Config(C.Structure):
     _fields_ = [("wg_size", _I32), ("num_wgs", _I32), ("desc_lds", _I32),
                 ("root_lds", _I32), ("max_depth", _I32), ("queue_cap", _I32),
                 ("sol_cap", _I64), ("launch", _I32), ("live", _I32),
-                ("occupancy", _I32), ("reserved", _I32)]
+                ("occupancy", _I32), ("dep", _I32), ("trail_cap", _I32)]
 
 
 class Limits(C.Structure):
@@ -52,7 +52,8 @@ class Stats(C.Structure):
                 ("prop_terms", _I64), ("sol_hash", C.c_uint64), ("best", _I32),
                 ("outcome", _I32), ("kernel_ms", C.c_double), ("ttpo_ms", C.c_double),
                 ("grid", _I32), ("block", _I32), ("desc_lds", _I32), ("root_lds", _I32),
-                ("lds_bytes", _I64), ("live", _I32), ("occupancy", _I32)]
+                ("lds_bytes", _I64), ("live", _I32), ("occupancy", _I32), ("dep", _I32),
+                ("pad", _I32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

@@ -164,9 +164,20 @@ def _gpu_counts(s):
     return (st["nodes"], st["fails"], st["solutions"], st["best"])
 
 
-# item lists on (1) and off (2): dropping entailed propagators must leave
-# every fixed point, and so every counter of the search, unchanged
-LIVE = pytest.mark.parametrize("live", [1, 2], ids=["lists", "tables"])
+# propagation modes: item lists (1), every table every sweep (2) and
+# dependency-driven sweeps with a trail (3).  Dropping entailed propagators,
+# or running only those whose inputs changed, must leave every fixed point,
+# and so every counter of the search, unchanged
+LIVE = pytest.mark.parametrize("live", [1, 2, 3], ids=["lists", "tables", "dep"])
+
+
+def pm(live):
+    return {1: dict(live=1), 2: dict(live=2), 3: dict(dep=1)}[live]
+
+
+def check_mode(st, live):
+    assert st["live"] == (live == 1)
+    assert st["dep"] == (live == 3)
 # both builds of the search kernel: high occupancy (workgroups of at most 256
 # threads) and normal
 OCC = pytest.mark.parametrize("occ", [1, 2], ids=["hiocc", "normal"])
@@ -178,10 +189,10 @@ def test_single_wg_enumerate(P, seed, dom, live):
     model = I.tiny_csp(seed, dom=dom)
     ref = O.solve(model, sol_cap=10**6)
     say("enumerate 1wg", seed, dom, live, ref["solutions"])
-    s = P.Solver(model, num_wgs=1, sol_cap=10**6, live=live)
+    s = P.Solver(model, num_wgs=1, sol_cap=10**6, **pm(live))
     out = s.solve(time_limit=60)
     assert out == P.OUT_ALL
-    assert s.stats()["live"] == (live == 1)
+    check_mode(s.stats(), live)
     assert _gpu_counts(s) == _oracle_counts(ref)
     st = s.stats()
     assert st["sol_hash"] == ref["sol_hash"]
@@ -196,10 +207,11 @@ def test_single_wg_minimize(P, n, seed, live, occ):
     model = I.tiny_rcpsp(n, seed)
     ref = O.solve(model)
     say("minimize 1wg", n, seed, live, occ, ref["nodes"])
-    s = P.Solver(model, num_wgs=1, live=live, occupancy=occ)
+    s = P.Solver(model, num_wgs=1, occupancy=occ, **pm(live))
     out = s.solve(time_limit=60)
     assert out == P.OUT_OPTIMAL
     assert s.stats()["occupancy"] == occ
+    check_mode(s.stats(), live)
     assert _gpu_counts(s) == _oracle_counts(ref)
     obj, vals = s.best()
     ok, ms = O.check_schedule(model.meta, vals)
@@ -215,7 +227,7 @@ def test_single_wg_node_limited_prefix(P, n, seed, limit, live, occ):
     model = I.rcpsp(n, seed)
     ref = O.solve(model, node_limit=limit)
     say("prefix 1wg", n, seed, limit, live, occ)
-    s = P.Solver(model, num_wgs=1, live=live, occupancy=occ)
+    s = P.Solver(model, num_wgs=1, occupancy=occ, **pm(live))
     out = s.solve(node_limit=limit, time_limit=60)
     assert out == P.OUT_LIMIT and ref["outcome"] == O.OUT_LIMIT
     assert _gpu_counts(s) == _oracle_counts(ref)
@@ -246,6 +258,46 @@ def test_lists_cut_executions_not_nodes(P):
         b["prop_linear2"] + b["prop_reified"] + b["prop_linear"]
 
 
+def test_dep_cuts_executions_not_nodes(P):
+    """The same node-limited single-workgroup prefix with dependency-driven
+    sweeps and with every table every sweep: identical search counters,
+    several times fewer propagator executions."""
+    model = I.rcpsp(30, 0)
+    res = {}
+    for kw in (dict(dep=1), dict(dep=2)):
+        s = P.Solver(model, num_wgs=1, **kw)
+        assert s.solve(node_limit=2000, time_limit=60) == P.OUT_LIMIT
+        res[kw["dep"]] = s.stats()
+    a, b = res[1], res[2]
+    assert a["dep"] == 1 and b["dep"] == 0
+    assert (a["nodes"], a["fails"], a["solutions"], a["best"], a["max_depth"]) == \
+        (b["nodes"], b["fails"], b["solutions"], b["best"], b["max_depth"])
+    ea = a["prop_linear2"] + a["prop_reified"] + a["prop_linear"]
+    eb = b["prop_linear2"] + b["prop_reified"] + b["prop_linear"]
+    say("executions per node, dependency-driven vs tables:", ea / a["nodes"], eb / b["nodes"],
+        "terms", a["prop_terms"] / a["nodes"], b["prop_terms"] / b["nodes"])
+    assert 3 * ea < eb
+    assert a["prop_terms"] < b["prop_terms"]
+
+
+@pytest.mark.parametrize("n,seed,limit,wg,cap", [(60, 2, 600, 256, 0), (120, 0, 300, 1024, 0),
+                                                  (30, 1, 1500, 256, 64), (60, 3, 600, 512, 300)])
+def test_dep_prefix_large_and_small_trail(P, n, seed, limit, wg, cap):
+    """Dependency-driven prefixes of the larger shapes (the 120-task store
+    fills most of a workgroup's LDS), and with a trail too short for the
+    path, so that backtracks fall back to recomputing from the subtree root:
+    every counter and the incumbent as in the oracle's depth-first order."""
+    model = I.rcpsp(n, seed)
+    ref = O.solve(model, node_limit=limit)
+    say("dep prefix", n, seed, limit, wg, cap)
+    s = P.Solver(model, num_wgs=1, wg_size=wg, dep=1, trail_cap=cap)
+    out = s.solve(node_limit=limit, time_limit=60)
+    assert out == P.OUT_LIMIT and ref["outcome"] == O.OUT_LIMIT
+    assert s.stats()["dep"] == 1
+    assert _gpu_counts(s) == _oracle_counts(ref)
+    assert s.stats()["max_depth"] == ref["max_depth"]
+
+
 def _ndiff(model):
     """Rows x - y <= c (two terms, coefficients +1 and -1)."""
     p, a = np.asarray(model.lin_ptr), np.asarray(model.lin_coef)
@@ -261,7 +313,7 @@ def test_multi_wg_enumerate_full_size(P, seed, live):
     model = I.tiny_csp(seed)
     ref = O.solve(model)
     say("enumerate multi", seed, live, ref["solutions"])
-    s = P.Solver(model, live=live)
+    s = P.Solver(model, **pm(live))
     out = s.solve(time_limit=120)
     assert out == P.OUT_ALL
     st = s.stats()
@@ -277,9 +329,10 @@ def test_multi_wg_minimize(P, n, seed, live, occ):
     model = I.tiny_rcpsp(n, seed)
     ref = O.solve(model)
     say("minimize multi", n, seed, live, occ)
-    s = P.Solver(model, live=live, occupancy=occ)
+    s = P.Solver(model, occupancy=occ, **pm(live))
     out = s.solve(time_limit=60)
     assert out == P.OUT_OPTIMAL
+    check_mode(s.stats(), live)
     obj, vals = s.best()
     assert obj == ref["best"]
     ok, ms = O.check_schedule(model.meta, vals)
