@@ -49,12 +49,12 @@ BYTES_DIFF, BYTES_REIF, BYTES_TERM = 16, 24, 8
 # 2 GiB written.  A run whose kernel source or shape differs reports null.
 PROFILED_TRAFFIC = [
     {"kernel_sha256": K, "block": blk, "desc_lds": dl, "root_lds": rl, "live": 0, "occupancy": oc,
+     "dep": 0,
      "fetch_bytes_per_node": f, "write_bytes_per_node": w,
      "profile": "profiles/search_kernel_rcpsp30_traffic.md"}
     for K in ["c5eafc6937bfcfe275291cb373c457d5e08a0d9a022915d2b2c9044f281ae18f"]
     for blk, dl, rl, oc, f, w in [(256, 0, 0, 1, 5.688, 3.527), (256, 1, 0, 2, 4.920, 1.458),
                                   (256, 0, 0, 2, 4.949, 1.400)]
-]
 ]
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
@@ -73,8 +73,8 @@ def profiled_traffic(st, nodes_per_launch):
     sha = kernel_sha256()
     for e in PROFILED_TRAFFIC:
         if (e["kernel_sha256"], e["block"], e["desc_lds"], e["root_lds"], e["live"],
-                e["occupancy"]) == (sha, st["block"], st["desc_lds"], st["root_lds"], st["live"],
-                                    st["occupancy"]):
+                e["occupancy"], e["dep"]) == (sha, st["block"], st["desc_lds"], st["root_lds"],
+                                              st["live"], st["occupancy"], st["dep"]):
             return round((e["fetch_bytes_per_node"] + e["write_bytes_per_node"]) * nodes_per_launch)
     return None
 
@@ -258,6 +258,8 @@ def main():
                     help="with --wg: item lists 0 chosen, 1 on, 2 off")
     ap.add_argument("--occupancy", type=int, default=0, choices=(0, 1, 2),
                     help="with --wg: search kernel build 0 chosen, 1 high, 2 normal")
+    ap.add_argument("--dep", type=int, default=0, choices=(0, 1, 2),
+                    help="with --wg: dependency-driven propagation 0/2 off, 1 on")
     ap.add_argument("--max-depth", type=int, default=0,
                     help="decision-stack capacity per workgroup (0 = library default)")
     ap.add_argument("--no-ttpo", action="store_true")
@@ -293,12 +295,13 @@ def main():
         from paper_2207_12116_amd import autotune
         cfg, rep = autotune.tune(models, pccp.MINIMIZE, budget_s=0.4, cache_path=None, log=log)
         tuned = {"wg_size": cfg.wg_size, "desc_lds": cfg.desc_lds, "root_lds": cfg.root_lds,
-                 "live": cfg.live, "occupancy": cfg.occupancy,
+                 "prop": rep["prop"], "occupancy": cfg.occupancy,
                  "candidates": len(rep["candidates"])}
         log(f"autotuned: {tuned}")
     else:
         cfg = pccp.Config(wg_size=args.wg, desc_lds=args.desc_lds, root_lds=args.root_lds,
-                          live=args.live, max_depth=args.max_depth, occupancy=args.occupancy)
+                          live=args.live, max_depth=args.max_depth, occupancy=args.occupancy,
+                          dep=args.dep)
     solvers = [pccp.Solver(m, config=cfg) for m in models]
 
     def step():
@@ -363,11 +366,12 @@ def main():
         from paper_2207_12116_amd import autotune
         tcfg, _ = autotune.tune([I.rcpsp(args.ttpo_n, s) for s in range(args.ttpo_seeds)],
                                 pccp.MINIMIZE, budget_s=0.2, cache_path=None,
-                                wg_sizes=(128, 256), lives=(2,), log=log)
+                                wg_sizes=(128, 256), log=log)
         ttpo_cmp = ttpo_suite(args.ttpo_n, list(range(args.ttpo_seeds)), args.ttpo_budget, tcfg,
                               learn.DEFAULT_WEIGHTS)
         ttpo_cmp["config"] = {"wg_size": tcfg.wg_size, "desc_lds": tcfg.desc_lds,
-                              "root_lds": tcfg.root_lds, "occupancy": tcfg.occupancy}
+                              "root_lds": tcfg.root_lds, "occupancy": tcfg.occupancy,
+                              "dep": tcfg.dep}
         log(f"ttpo: {json.dumps({k: v for k, v in ttpo_cmp.items()})}")
 
     legs = None
@@ -375,18 +379,22 @@ def main():
         from paper_2207_12116_amd import autotune
         log("120-task instance, whole GPU")
         c3m = [I.rcpsp(120, 0)]
-        c3cfg, _ = autotune.tune(c3m, pccp.MINIMIZE, budget_s=0.3, cache_path=None,
-                                 wg_sizes=(256, 512, 1024), log=log)
+        # deeper stacks than the default for the larger instances: the
+        # faster modes reach depths past 1024 within the time limit
+        c3cfg, c3rep = autotune.tune(c3m, pccp.MINIMIZE, budget_s=0.3, cache_path=None,
+                                     wg_sizes=(256, 512, 1024), max_depth=2048, log=log)
         legs = {"c3_120tasks": single_instance_leg(120, 0, 2.0, c3cfg)}
-        legs["c3_120tasks"]["config"] = {"wg_size": c3cfg.wg_size, "live": c3cfg.live}
+        legs["c3_120tasks"]["config"] = {"wg_size": c3cfg.wg_size, "prop": c3rep["prop"],
+                                         "max_depth": c3cfg.max_depth}
         log(f"c3: {legs['c3_120tasks']}")
         log("256 mixed instances, one launch")
         c4m = [I.rcpsp(I.batch_sizes(s), s) for s in range(0, 256, 16)]
-        c4cfg, _ = autotune.tune(c4m, pccp.MINIMIZE, budget_s=0.3, cache_path=None,
-                                 wg_sizes=(256, 512, 1024), log=log)
+        c4cfg, c4rep = autotune.tune(c4m, pccp.MINIMIZE, budget_s=0.3, cache_path=None,
+                                     wg_sizes=(256, 512, 1024), max_depth=2048, log=log)
         legs["c4_mixed256"] = mixed_batch_leg(256, 3.0, c4cfg)
         legs["c4_mixed256"]["config"] = {"wg_size": c4cfg.wg_size, "desc_lds": c4cfg.desc_lds,
-                                         "root_lds": c4cfg.root_lds, "live": c4cfg.live}
+                                         "root_lds": c4cfg.root_lds, "prop": c4rep["prop"],
+                                         "max_depth": c4cfg.max_depth}
         log(f"c4: {legs['c4_mixed256']}")
 
     cpu = None
@@ -409,6 +417,7 @@ def main():
                    "grid": sts[0]["grid"], "block": sts[0]["block"],
                    "desc_lds": sts[0]["desc_lds"], "root_lds": sts[0]["root_lds"],
                    "live": sts[0]["live"], "occupancy": sts[0]["occupancy"],
+                   "dep": sts[0]["dep"], "max_depth_reached": max(s["max_depth"] for s in sts),
                    "autotuned": tuned, "launch": "hipGraph"},
         "propagations_per_s": round(tot_props / wall, 1),
         "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "ttpo": ttpo,

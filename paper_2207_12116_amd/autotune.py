@@ -2,10 +2,11 @@
 
 For a batch of models it times a short search under each candidate launch
 configuration - workgroup size x placement of the propagator tables (LDS or
-HBM/L2) x placement of the subtree-root store (LDS or HBM) x item lists of
-non-entailed propagators (on or off) x kernel build (high occupancy or
-normal, for workgroups of up to 256 threads) - and keeps the one with the
-highest node rate.  Results are cached per device and size
+HBM/L2) x placement of the subtree-root store (LDS or HBM) x propagation
+mode (every propagator every sweep, or dependency-driven sweeps with a
+trail; item lists of non-entailed propagators on request) x kernel build
+(high occupancy or normal, for workgroups of up to 256 threads) - and keeps
+the one with the highest node rate.  Results are cached per device and size
 class (largest store, table sizes, mode) in a JSON file, so a later call with
 the same shapes costs nothing.
 """
@@ -20,7 +21,10 @@ from . import pccp
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pccp_autotune.json")
 WG_SIZES = (128, 256, 512, 1024)
 PLACEMENTS = ((1, 1), (1, 2), (2, 1), (2, 2))   # (desc_lds, root_lds): 1 = LDS, 2 = HBM
-LIVES = (1, 2)                                    # item lists on, off
+# propagation modes: every table every sweep, dependency-driven, item lists
+MODES = {"tables": {"live": 2, "dep": 2}, "dep": {"live": 2, "dep": 1},
+         "lists": {"live": 1, "dep": 2}}
+DEFAULT_MODES = ("tables", "dep")
 
 
 def size_class(models, mode) -> str:
@@ -61,44 +65,53 @@ def _rate(models, mode, cfg, budget_s):
     return nodes / max(st[0]["kernel_ms"] / 1e3, 1e-9), st[0]
 
 
+def _cfg(x, max_depth):
+    return pccp.Config(wg_size=x["wg_size"], desc_lds=x["desc_lds"], root_lds=x["root_lds"],
+                       occupancy=x["occupancy"], max_depth=max_depth, **MODES[x["prop"]])
+
+
 def tune(models, mode=pccp.MINIMIZE, budget_s=0.4, cache_path=DEFAULT_CACHE, force=False,
-         wg_sizes=WG_SIZES, placements=PLACEMENTS, lives=LIVES, log=None, finalists=3):
+         wg_sizes=WG_SIZES, placements=PLACEMENTS, modes=DEFAULT_MODES, log=None, finalists=3,
+         max_depth=0):
     """Return (Config, report) for searching `models` together in one launch.
     Every candidate is timed for `budget_s` of device time; the `finalists`
     best are timed again for four times as long (a short run over-weights the
     start-up while the queue fills) and the best of those is kept, rates
     within 2 % counting as ties."""
-    key = f"{_device_name()}|{size_class(models, mode)}"
+    key = f"{_device_name()}|{size_class(models, mode)}|d{max_depth}|{'+'.join(modes)}"
     cache = _load(cache_path) if cache_path else {}
     if not force and key in cache:
         c = cache[key]
         return pccp.Config(**c["config"]), {"cached": True, **c}
     results = []
-    cands = [(w, p, l, o) for w in wg_sizes for p in placements for l in lives
+    cands = [(w, p, pm, o) for w in wg_sizes for p in placements for pm in modes
              for o in ((1, 2) if w <= 256 else (2,))]
-    for wg, (d, r), lv, oc in cands:
-        cfg = pccp.Config(wg_size=wg, desc_lds=d, root_lds=r, live=lv, occupancy=oc)
+    for wg, (d, r), pm, oc in cands:
+        x = {"wg_size": wg, "desc_lds": d, "root_lds": r, "prop": pm, "occupancy": oc}
         try:
-            rate, st = _rate(models, mode, cfg, budget_s)
+            rate, st = _rate(models, mode, _cfg(x, max_depth), budget_s)
         except pccp.PccpError as e:
-            if e.code in (pccp.E_LDS_CAPACITY,):
+            # a layout that does not fit, or a path deeper than the stack
+            if e.code in (pccp.E_LDS_CAPACITY, pccp.E_DEPTH):
                 continue
             raise
-        results.append({"wg_size": wg, "desc_lds": d, "root_lds": r, "live": lv,
-                         "occupancy": oc, "nodes_per_s": rate, "grid": st["grid"],
-                         "placed_desc_lds": st["desc_lds"],
-                         "placed_root_lds": st["root_lds"]})
+        x.update({"nodes_per_s": rate, "grid": st["grid"], "placed_desc_lds": st["desc_lds"],
+                  "placed_root_lds": st["root_lds"]})
+        results.append(x)
         if log:
-            log(f"autotune wg={wg} desc={d} root={r} live={lv} occ={oc}: {rate / 1e6:.2f} M nodes/s "
+            log(f"autotune wg={wg} desc={d} root={r} prop={pm} occ={oc}: {rate / 1e6:.2f} M nodes/s "
                 f"(grid {st['grid']})")
     results.sort(key=lambda x: -x["nodes_per_s"])
     for x in results[:finalists]:
-        cfg = pccp.Config(wg_size=x["wg_size"], desc_lds=x["desc_lds"], root_lds=x["root_lds"],
-                          live=x["live"], occupancy=x["occupancy"])
-        x["nodes_per_s_long"], _ = _rate(models, mode, cfg, 4 * budget_s)
+        try:
+            x["nodes_per_s_long"], _ = _rate(models, mode, _cfg(x, max_depth), 4 * budget_s)
+        except pccp.PccpError as e:
+            if e.code != pccp.E_DEPTH:
+                raise
+            x["nodes_per_s_long"] = 0.0
         if log:
             log(f"autotune finalist wg={x['wg_size']} desc={x['desc_lds']} root={x['root_lds']} "
-                f"live={x['live']} occ={x['occupancy']}: {x['nodes_per_s_long'] / 1e6:.2f} M nodes/s")
+                f"prop={x['prop']} occ={x['occupancy']}: {x['nodes_per_s_long'] / 1e6:.2f} M nodes/s")
     if not results:
         raise RuntimeError("autotune: no configuration fits")
     # long-run rates within 2 % of the best are ties (searches of different
@@ -107,9 +120,9 @@ def tune(models, mode=pccp.MINIMIZE, budget_s=0.4, cache_path=DEFAULT_CACHE, for
     top = max(x["nodes_per_s_long"] for x in results[:finalists])
     best = next(x for x in results[:finalists] if x["nodes_per_s_long"] >= 0.98 * top)
     entry = {"config": {"wg_size": best["wg_size"], "desc_lds": best["desc_lds"],
-                        "root_lds": best["root_lds"], "live": best["live"],
-                        "occupancy": best["occupancy"]},
-             "nodes_per_s": best["nodes_per_s"], "candidates": results}
+                        "root_lds": best["root_lds"], "occupancy": best["occupancy"],
+                        "max_depth": max_depth, **MODES[best["prop"]]},
+             "prop": best["prop"], "nodes_per_s": best["nodes_per_s"], "candidates": results}
     if cache_path:
         cache[key] = entry
         _store(cache_path, cache)

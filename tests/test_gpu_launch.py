@@ -30,14 +30,15 @@ def counts(s):
     return (st["nodes"], st["fails"], st["solutions"], st["sol_hash"], st["best"])
 
 
-def test_graph_replays_match_plain_launch(P):
+@pytest.mark.parametrize("dep", [2, 1], ids=["tables", "dep"])
+def test_graph_replays_match_plain_launch(P, dep):
     model = I.tiny_csp(1, dom=12)
     ref = O.solve(model)
-    plain = P.Solver(model, num_wgs=1, launch=1)
+    plain = P.Solver(model, num_wgs=1, launch=1, dep=dep)
     assert plain.solve(time_limit=60) == P.OUT_ALL
     want = counts(plain)
     assert want[:4] == (ref["nodes"], ref["fails"], ref["solutions"], ref["sol_hash"])
-    g = P.Solver(model, num_wgs=1, launch=0)
+    g = P.Solver(model, num_wgs=1, launch=0, dep=dep)
     other = P.Solver(I.rcpsp(30, 1))
     for rep in range(4):
         print("graph replay", rep, file=sys.stderr, flush=True)
@@ -45,7 +46,7 @@ def test_graph_replays_match_plain_launch(P):
         assert counts(g) == want
         other.propagate()        # eager work between replays
     # multi-workgroup graph: ENUMERATE counts are schedule-free
-    gm = P.Solver(I.tiny_csp(2, dom=14), launch=0)
+    gm = P.Solver(I.tiny_csp(2, dom=14), launch=0, dep=dep)
     refm = O.solve(I.tiny_csp(2, dom=14))
     for rep in range(3):
         assert gm.solve(time_limit=60) == P.OUT_ALL
@@ -82,7 +83,8 @@ def test_autotune_picks_a_working_config(P, tmp_path):
     assert s.best()[0] == O.solve(small[0])["best"]
 
 
-def test_instance_node_budget_abandons_only_the_hard_instance(P):
+@pytest.mark.parametrize("dep", [2, 1], ids=["tables", "dep"])
+def test_instance_node_budget_abandons_only_the_hard_instance(P, dep):
     """A batch with a per-instance node budget: the instance that exhausts it
     is abandoned (LIMIT) while the small ones are still proven, with the
     oracle's optima; the abandoned instance stopped near its budget."""
@@ -91,7 +93,8 @@ def test_instance_node_budget_abandons_only_the_hard_instance(P):
     refs = [O.solve(m, node_limit=400000) for m in easy]
     solvers = [P.Solver(m) for m in easy + [hard]]
     budget = 2_000_000
-    outs = P.batch_solve(solvers, P.MINIMIZE, time_limit=60, inst_node_limit=budget)
+    outs = P.batch_solve(solvers, P.MINIMIZE, config=P.Config(dep=dep), time_limit=60,
+                         inst_node_limit=budget)
     say("budget outcomes", outs)
     for s, o, r, m in zip(solvers, outs, refs, easy):
         assert o == P.OUT_OPTIMAL
