@@ -49,12 +49,10 @@ BYTES_DIFF, BYTES_REIF, BYTES_TERM = 16, 24, 8
 # 2 GiB written.  A run whose kernel source or shape differs reports null.
 PROFILED_TRAFFIC = [
     {"kernel_sha256": K, "block": blk, "desc_lds": dl, "root_lds": rl, "live": 0, "occupancy": oc,
-     "dep": 0,
-     "fetch_bytes_per_node": f, "write_bytes_per_node": w,
+     "dep": dep, "fetch_bytes_per_node": f, "write_bytes_per_node": w,
      "profile": "profiles/search_kernel_rcpsp30_traffic.md"}
-    for K in ["c5eafc6937bfcfe275291cb373c457d5e08a0d9a022915d2b2c9044f281ae18f"]
-    for blk, dl, rl, oc, f, w in [(256, 0, 0, 1, 5.688, 3.527), (256, 1, 0, 2, 4.920, 1.458),
-                                  (256, 0, 0, 2, 4.949, 1.400)]
+    for K in ["aac757300a5864bea7771c03728868fb0d48b81f640ef23bfcbcebbac58fca93"]
+    for blk, dl, rl, oc, dep, f, w in [(128, 0, 0, 2, 1, 5.30, 173.9)]
 ]
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
