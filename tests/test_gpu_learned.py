@@ -200,3 +200,25 @@ def test_learned_search_optimum_and_gain(P):
     say("total time to proven optimum: first-fail", round(ff, 3), "learned", round(ln, 3),
         "speedup", round(ff / ln, 2))
     assert ln < ff
+
+
+def test_learned_branching_dep_same_tree(P):
+    """Learned branching with dependency-driven propagation: the same
+    single-workgroup depth-first prefix (every counter) as with every table
+    every sweep, since the stores, and so the features and choices, are the
+    same."""
+    from paper_2207_12116_amd import learn
+    if not os.path.exists(learn.DEFAULT_WEIGHTS):
+        pytest.fail(f"trained weights missing: {learn.DEFAULT_WEIGHTS}")
+    mlp = learn.network()
+    res = []
+    for dep in (1, 2):
+        for n, seed, limit in ((30, 5, 1500), (14, 7, 4000)):
+            s = P.Solver(I.rcpsp_model(*I.rcpsp_data(n, seed)[:4]), num_wgs=1, dep=dep)
+            learn.attach(s, mlp)
+            s.solve(node_limit=limit, time_limit=60)
+            st = s.stats()
+            assert st["dep"] == (dep == 1)
+            res.append((n, st["nodes"], st["fails"], st["solutions"], st["best"], st["max_depth"]))
+    say("learned prefixes dep / tables", res)
+    assert res[:2] == res[2:]

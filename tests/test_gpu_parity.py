@@ -339,12 +339,13 @@ def test_multi_wg_minimize(P, n, seed, live, occ):
     assert ok and ms == obj
 
 
-def test_batch_solve_matches_oracle(P):
+@pytest.mark.parametrize("dep", [2, 1], ids=["tables", "dep"])
+def test_batch_solve_matches_oracle(P, dep):
     models = [I.tiny_rcpsp(n, s) for n, s in [(6, 0), (8, 1), (10, 2), (5, 3), (9, 4), (7, 5)]]
     refs = [O.solve(m) for m in models]
     solvers = [P.Solver(m) for m in models]
-    say("batch minimize", len(models))
-    outs = P.batch_solve(solvers, P.MINIMIZE, time_limit=60)
+    say("batch minimize", len(models), dep)
+    outs = P.batch_solve(solvers, P.MINIMIZE, config=P.Config(dep=dep), time_limit=60)
     assert outs == [P.OUT_OPTIMAL] * len(models)
     for s, r in zip(solvers, refs):
         assert s.best()[0] == r["best"]
@@ -352,7 +353,7 @@ def test_batch_solve_matches_oracle(P):
     cs = [I.tiny_csp(k, dom=10) for k in range(4)]
     crefs = [O.solve(m) for m in cs]
     csol = [P.Solver(m) for m in cs]
-    outs = P.batch_solve(csol, P.ENUMERATE, time_limit=60)
+    outs = P.batch_solve(csol, P.ENUMERATE, config=P.Config(dep=dep), time_limit=60)
     assert outs == [P.OUT_ALL] * 4
     for s, r in zip(csol, crefs):
         st = s.stats()
