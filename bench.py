@@ -378,9 +378,11 @@ def main():
         log("120-task instance, whole GPU")
         c3m = [I.rcpsp(120, 0)]
         # deeper stacks than the default for the larger instances: the
-        # faster modes reach depths past 1024 within the time limit
+        # faster modes reach depths past 1024 within the time limit (the
+        # stack beyond its deepest 256 levels lives in HBM, so depth costs
+        # no LDS)
         c3cfg, c3rep = autotune.tune(c3m, pccp.MINIMIZE, budget_s=0.3, cache_path=None,
-                                     wg_sizes=(256, 512, 1024), max_depth=2048, log=log)
+                                     wg_sizes=(256, 512, 1024), max_depth=4096, log=log)
         legs = {"c3_120tasks": single_instance_leg(120, 0, 2.0, c3cfg)}
         legs["c3_120tasks"]["config"] = {"wg_size": c3cfg.wg_size, "prop": c3rep["prop"],
                                          "max_depth": c3cfg.max_depth}
@@ -388,7 +390,7 @@ def main():
         log("256 mixed instances, one launch")
         c4m = [I.rcpsp(I.batch_sizes(s), s) for s in range(0, 256, 16)]
         c4cfg, c4rep = autotune.tune(c4m, pccp.MINIMIZE, budget_s=0.3, cache_path=None,
-                                     wg_sizes=(256, 512, 1024), max_depth=2048, log=log)
+                                     wg_sizes=(256, 512, 1024), max_depth=4096, log=log)
         legs["c4_mixed256"] = mixed_batch_leg(256, 3.0, c4cfg)
         legs["c4_mixed256"]["config"] = {"wg_size": c4cfg.wg_size, "desc_lds": c4cfg.desc_lds,
                                          "root_lds": c4cfg.root_lds, "prop": c4rep["prop"],

@@ -394,13 +394,13 @@ struct DevBuf {
 
 // search workspace (grow-only), and the graph of the last launch
 struct Workspace {
-    DevBuf models, inst, globals, qseq, qdata, roots, best, trail, tstart;
+    DevBuf models, inst, globals, qseq, qdata, roots, best, trail, gstack;
     hipGraphExec_t graph = nullptr;
     std::vector<char> graph_key;
     void release()
     {
         models.release(); inst.release(); globals.release(); qseq.release();
-        qdata.release(); roots.release(); best.release(); trail.release(); tstart.release();
+        qdata.release(); roots.release(); best.release(); trail.release(); gstack.release();
         if (graph) (void)hipGraphExecDestroy(graph);
         graph = nullptr;
         graph_key.clear();
@@ -692,15 +692,13 @@ struct ShapeNeed {
 // smallest power-of-two word count with 32 bits per word covering the
 // store, one mark bit per propagator, work lists of 1/scale of each table
 // (at least 64 entries; a sweep whose list would overflow runs the whole
-// table of that kind) and the trail starts of the path levels in LDS or in
-// global memory.
+// table of that kind).
 struct DepLayout {
     int vshift = 0, qw = 0;
     int wcap[4] = {0, 0, 0, 0};
-    bool tstart_lds = true;
 };
 
-static DepLayout dep_layout(int max_vars, const int items[4], int scale, bool tstart_lds)
+static DepLayout dep_layout(int max_vars, const int items[4], int scale)
 {
     DepLayout d;
     const int Vp = (max_vars + 3) & ~3;
@@ -709,7 +707,6 @@ static DepLayout dep_layout(int max_vars, const int items[4], int scale, bool ts
     d.qw = (int)((tot + 31) / 32);
     for (int k = 0; k < 4; ++k)
         d.wcap[k] = std::min(items[k], std::max(64, (items[k] + scale - 1) / scale));
-    d.tstart_lds = tstart_lds;
     return d;
 }
 
@@ -737,7 +734,7 @@ static int32_t choose_shape(const pccp_config &cfg, const ShapeNeed &nd, int num
     const int list_items = pm == 1 ? nd.max_items[0] + nd.max_items[1] + nd.max_items[2] + nd.max_items[3] : 0;
     struct Cand { bool d, r; };
     const Cand cands[4] = {{true, true}, {false, true}, {true, false}, {false, false}};
-    int best_occ = -1;
+    int best_occ = -1, best_li = 1 << 30;
     for (const Cand &cd : cands) {
         if (cfg.desc_lds != 0 && cd.d != (cfg.desc_lds == 1)) continue;
         if (cfg.root_lds != 0 && cd.r != (cfg.root_lds == 1)) continue;
@@ -751,16 +748,15 @@ static int32_t choose_shape(const pccp_config &cfg, const ShapeNeed &nd, int num
         k.live = pm == 1;
         k.dep = pm == 2;
         k.hi = cfg.occupancy == 1 || (cfg.occupancy == 0 && sh.block <= 256);
-        // dependency-driven: the layouts from whole-table lists with the
-        // trail starts in LDS down to short lists with them in global
-        // memory; the first with the most resident workgroups
-        const int nlay = pm == 2 ? 16 : 1;
+        // dependency-driven: the layouts from whole-table lists down to
+        // short ones; the first with the most resident workgroups
+        const int nlay = pm == 2 ? 8 : 1;
         for (int li = 0; li < nlay; ++li) {
             DepLayout dl;
             size_t depb = 0;
             if (pm == 2) {
-                dl = dep_layout(nd.max_vars, nd.max_items, 1 << (li % 8), li < 8);
-                depb = dep_lds_bytes(cfg.max_depth, dl.tstart_lds, dl.vshift, dl.qw, dl.wcap);
+                dl = dep_layout(nd.max_vars, nd.max_items, 1 << li);
+                depb = dep_lds_bytes(dl.vshift, dl.qw, dl.wcap);
             }
             const size_t lds = search_lds_bytes(nd.max_vars, cfg.max_depth, nd.max_desc, cd.d, cd.r,
                                                 nd.feat_ndec, list_items, depb);
@@ -769,8 +765,11 @@ static int32_t choose_shape(const pccp_config &cfg, const ShapeNeed &nd, int num
             hipError_t e = search_occupancy(sh.block, lds, k, &occ);
             if (e != hipSuccess)
                 return fail(PCCP_E_DEVICE, std::string("occupancy: ") + hipGetErrorString(e));
-            if (occ > best_occ) {  // candidates are in order of preference
+            // the most resident workgroups, then the longest work lists,
+            // then the candidates' order of preference
+            if (occ > best_occ || (occ == best_occ && li < best_li)) {
                 best_occ = occ;
+                best_li = li;
                 sh.k = k;
                 sh.lds = lds;
                 sh.dep = dl;
@@ -845,8 +844,7 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
                                                        : std::min(std::max(8 * Vp, 4096), 1 << 18);
     if (sh.k.dep && (rc = ws.trail.ensure(sizeof(int4) * (size_t)tcap * sh.grid)))
         return rc;
-    const bool tstart_g = sh.k.dep && !sh.dep.tstart_lds;
-    if (tstart_g && (rc = ws.tstart.ensure(sizeof(int32_t) * (size_t)(cfg.max_depth + 1) * sh.grid)))
+    if ((rc = ws.gstack.ensure(sizeof(int4) * (size_t)cfg.max_depth * sh.grid)))
         return rc;
     const bool keep_sols = (mode == PCCP_ENUMERATE && n == 1 && cfg.sol_cap > 0);
     if (keep_sols && (rc = s0->sols.ensure(sizeof(int32_t) * (size_t)cfg.sol_cap * std::max(s0->c.ndec, 1))))
@@ -885,7 +883,7 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
     for (int k = 0; k < 4; ++k) P.dep_wcap[k] = sh.dep.wcap[k];
     P.trail = sh.k.dep ? ws.trail.as<int4>() : nullptr;
     P.tcap = tcap;
-    P.tstart_g = tstart_g ? ws.tstart.as<int32_t>() : nullptr;
+    P.gstack = ws.gstack.as<int4>();
 
     if (cfg.launch == 0) {
         // the graph bakes in the launch parameters: rebuild it when they change

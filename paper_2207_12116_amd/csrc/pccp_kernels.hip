@@ -183,6 +183,7 @@ enum : int {
                                             // (2 sets) = 4 kinds, terms of kinds 3, 4
     C_TTOP = 24,                            // entries pushed on the trail
     C_THI = 25,                             // deepest path level without a whole trail
+    C_MAXW = 26,                            // deepest decision-stack level written
 };
 
 // ------------------------------------------------------------ descriptors
@@ -1449,6 +1450,34 @@ __device__ __forceinline__ void tell_one(int2 *st, const Dep &dp, int x, int32_t
     tell_m<true, LB>(st, dp, x, v, d);
 }
 
+// The decision stack.  Level k of the path is {var | side << 16 |
+// donated << 17, value, trail start of level k + 1, 0}; every level is kept
+// in this workgroup's slice of global memory and the kRing deepest levels
+// written are also kept in an LDS ring (slot k mod kRing), so that the LDS
+// a workgroup needs does not grow with the stack capacity.  `maxw` (an LDS
+// word) is the deepest level written since the subtree was taken: level k
+// is in the ring while k > maxw - kRing, since only a write of a level
+// k + j kRing (j >= 1) reuses its slot.  put() is called by one lane at a
+// time; reads of global levels by other lanes follow a full barrier.
+constexpr int kRing = 256;
+struct Stack {
+    int4 *ring;          // LDS, kRing entries
+    int4 *g;             // global, max_depth entries
+    int32_t *maxw;       // LDS word
+    __device__ __forceinline__ bool in_ring(int k) const { return k > lds_ld(maxw) - kRing; }
+    __device__ __forceinline__ int4 get(int k) const
+    {
+        return in_ring(k) ? ring[k & (kRing - 1)] : gread(g + k);
+    }
+    __device__ __forceinline__ void put(int k, int4 e) const
+    {
+        const int mw = lds_ld(maxw);
+        if (k > mw) *maxw = k;
+        if (k > mw - kRing) ring[k & (kRing - 1)] = e;
+        gwrite4(g + k, e);
+    }
+};
+
 // State only lane 0 uses lives in LDS (not in every lane's registers).
 struct Lane0 {
     unsigned long long nodes, fails, sols, sweeps, don, maxd;
@@ -1501,23 +1530,19 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(Sea
         rst = reinterpret_cast<int2 *>(P.root_scratch) + (size_t)blockIdx.x * Vp;
         p = reinterpret_cast<char *>(st + Vp);
     }
-    int2 *stack = reinterpret_cast<int2 *>(p);
-    p += align16(sizeof(int2) * (size_t)P.max_depth);
+    const Stack stk{reinterpret_cast<int4 *>(p),
+                    P.gstack + (size_t)blockIdx.x * (size_t)P.max_depth, ctl + C_MAXW};
+    p += align16(sizeof(int4) * (size_t)kRing);
     float *fsc = reinterpret_cast<float *>(p);
     if (LEARN) p += align16(32 * (size_t)P.max_ndec);
     uint16_t *lbuf = reinterpret_cast<uint16_t *>(p);
     const int lcap = (int)(align16(2 * (size_t)(P.max_items[0] + P.max_items[1] + P.max_items[2] +
                                                 P.max_items[3])) / 2);
     if (LIVE) p += 2 * 3 * (size_t)lcap;
-    // dependency-driven propagation: trail start of every path level, the
-    // three variable bitmaps, the propagator marks and the work lists
-    // (the trail starts go to global memory when LDS is short: then the
-    // pointer is generic)
-    int32_t *tstart = P.tstart_g ? P.tstart_g + (size_t)blockIdx.x * (size_t)(P.max_depth + 1)
-                                 : reinterpret_cast<int32_t *>(p);
+    // dependency-driven propagation: the three variable bitmaps, the
+    // propagator marks and the work lists
     Dep dp{};
     if (DEP) {
-        if (!P.tstart_g) p += align16(4 * (size_t)(P.max_depth + 1));
         const int vw = 1 << P.dep_vshift;
         dp.lm = reinterpret_cast<uint32_t *>(p);
         dp.um = dp.lm + vw;
@@ -1613,10 +1638,6 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(Sea
         const int inst = uni(ctl[C_INST]);
         const int len = uni(ctl[C_LEN]);
         const int2 *rec = reinterpret_cast<const int2 *>(q_slot(P, (unsigned long long)pos) + 1);
-        for (int i = tid; i < len; i += W) {
-            const int2 dcs = gread(rec + i);
-            stack[i] = make_int2(dcs.x & (0xffff | (int)kSideBit), dcs.y);
-        }
         const DevModel &m = P.models[inst];
         if (inst != cur_inst) {
             if (tid == 0) z.local_best = INT32_MAX;
@@ -1626,8 +1647,16 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(Sea
         const int nvars = m.nvars, ndec = m.ndec, objective = m.objective;
         load_box(st, m.lb0, m.ub0, nvars);
         lds_barrier();
-        for (int i = tid; i < len; i += W)
-            apply_decision(st, stack[i]);
+        // the record's decisions: onto the stack (the deepest kRing also in
+        // the ring) and into the store
+        for (int i = tid; i < len; i += W) {
+            const int2 dcs = gread(rec + i);
+            const int4 e = make_int4(dcs.x & (0xffff | (int)kSideBit), dcs.y, 0, 0);
+            gwrite4(stk.g + i, e);
+            if (i >= len - kRing) stk.ring[i & (kRing - 1)] = e;
+            apply_decision(st, make_int2(e.x, e.y));
+        }
+        if (tid == 0) ctl[C_MAXW] = len - 1;
         full_barrier();  // every lane is done reading the record
         if (tid == 0)
             q_release_slot(P, (unsigned long long)pos);
@@ -1723,7 +1752,8 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(Sea
             int rc;
             if constexpr (DEP) {
                 dp.trail_on = !node_full;
-                rc = propagate_dep<DL, HI>(v, st, ctl, dp, node_full, nsw, ex);
+                // work lists are short: lean unrolling (fewer registers)
+                rc = propagate_dep<DL, true>(v, st, ctl, dp, node_full, nsw, ex);
                 // the next node's trail marks start empty; a node whose
                 // changes did not all fit on the trail cannot be undone
                 for (int w = tid; w < dp.vw; w += W) dp.tm[w] = 0;
@@ -1810,10 +1840,11 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(Sea
                     const int q = (int)(uint32_t)(key & 0xffffffffull);
                     const int x = v.dec(q);
                     const int val = st[x].x;
-                    stack[depth] = make_int2(x, val);
+                    // level depth; with DEP its entry also keeps where the
+                    // child's trail segment starts
+                    stk.put(depth, make_int4(x, val, DEP ? ctl[C_TTOP] : 0, 0));
                     if constexpr (DEP) {
                         // left child: x = lb(x), the first entry of its trail
-                        tstart[depth + 1] = ctl[C_TTOP];
                         Dep d1 = dp;
                         d1.trail_on = true;
                         tell_one<false>(st, d1, x, val);
@@ -1825,22 +1856,25 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(Sea
                     if (P.donate && z.pf_idle > 0 && z.pf_qt - z.pf_qh < (unsigned long long)z.pf_idle) {
                         int k = -1;
                         for (int e = depth0; e <= depth; ++e)
-                            if (!(stack[e].x & (kSideBit | kDonatedBit))) { k = e; break; }
+                            if (!(stk.get(e).x & (kSideBit | kDonatedBit))) { k = e; break; }
                         if (k >= 0) {
                             const long long pp = q_claim_push(P);
                             if (pp >= 0) {
                                 RecHdr *h = q_slot(P, (unsigned long long)pp);
                                 int2 *dd = reinterpret_cast<int2 *>(h + 1);
-                                for (int e = 0; e < k; ++e)
-                                    dd[e] = make_int2(stack[e].x & (0xffff | (int)kSideBit), stack[e].y);
-                                dd[k] = make_int2((stack[k].x & 0xffff) | (int)kSideBit, stack[k].y);
+                                for (int e = 0; e < k; ++e) {
+                                    const int4 se = stk.get(e);
+                                    dd[e] = make_int2(se.x & (0xffff | (int)kSideBit), se.y);
+                                }
+                                const int4 sk = stk.get(k);
+                                dd[k] = make_int2((sk.x & 0xffff) | (int)kSideBit, sk.y);
                                 h->inst = inst;
                                 h->len = k + 1;
                                 g_add(&is->outstanding, 1);
                                 g_add(&P.g->outstanding, 1);
                                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                                 q_publish(P, (unsigned long long)pp);
-                                stack[k].x |= (int)kDonatedBit;
+                                stk.put(k, make_int4(sk.x | (int)kDonatedBit, sk.y, sk.z, sk.w));
                                 z.don += 1;
                             }
                         }
@@ -1854,11 +1888,15 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(Sea
             // ---- backtrack: drop exhausted entries, flip the deepest open one
             if (tid == 0) {
                 int d = depth;
-                while (d > depth0 && (stack[d - 1].x & (kSideBit | kDonatedBit))) --d;
+                int4 sd = d > depth0 ? stk.get(d - 1) : make_int4(0, 0, 0, 0);
+                while (d > depth0 && (sd.x & (kSideBit | kDonatedBit))) {
+                    --d;
+                    if (d > depth0) sd = stk.get(d - 1);
+                }
                 if (d == depth0) {
                     ctl[C_DEPTH] = -1;
                 } else {
-                    stack[d - 1].x |= (int)kSideBit;
+                    stk.put(d - 1, make_int4(sd.x | (int)kSideBit, sd.y, sd.z, sd.w));
                     ctl[C_DEPTH] = d;
                 }
             }
@@ -1875,9 +1913,12 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(Sea
                     // of the shallowest), then the flipped decision
                     full_barrier();  // the trail stores of every lane are visible
                     const int top = uni(lds_ld(ctl + C_TTOP));
+                    // trail segment of level k: [start kept at level k - 1,
+                    // start kept at level k, or the top for the current one)
+                    int e0 = uni(stk.get(depth - 1).z);
                     for (int k = depth; k >= nd; --k) {
-                        const int e0 = uni(tstart[k]);
-                        const int e1 = k == depth ? top : uni(tstart[k + 1]);
+                        const int e1 = k == depth ? top : e0;
+                        if (k < depth) e0 = uni(stk.get(k - 1).z);
                         for (int i = e0 + tid; i < e1; i += W) {
                             const int4 t = gread(dp.trail + i);
                             st[t.x] = make_int2(t.y, t.z);
@@ -1886,8 +1927,8 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(Sea
                     }
                     depth = nd;
                     if (tid == 0) {
-                        ctl[C_TTOP] = tstart[nd];
-                        const int2 dcs = stack[nd - 1];
+                        const int4 dcs = stk.get(nd - 1);
+                        ctl[C_TTOP] = dcs.z;
                         Dep d1 = dp;
                         d1.trail_on = true;
                         tell_one<true>(st, d1, dcs.x & 0xffff, dcs.y + 1);
@@ -1898,7 +1939,7 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(Sea
                 }
                 if (tid == 0) {
                     ctl[C_THI] = nd;
-                    ctl[C_TTOP] = tstart[nd];
+                    ctl[C_TTOP] = stk.get(nd - 1).z;
                 }
                 node_full = true;
             }
@@ -1909,9 +1950,11 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(Sea
                 in_sel = 1;
                 out_sel = 2;
             }
-            lds_barrier();
-            for (int i = depth0 + tid; i < depth; i += W)
-                apply_decision(st, stack[i]);
+            full_barrier();  // stack levels in global memory are visible
+            for (int i = depth0 + tid; i < depth; i += W) {
+                const int4 e = stk.get(i);
+                apply_decision(st, make_int2(e.x, e.y));
+            }
             lds_barrier();
         }
         // ---- subtree done (or abandoned): publish counters
@@ -2195,7 +2238,7 @@ size_t search_lds_bytes(int max_vars, int max_depth, size_t max_desc, bool desc_
     const size_t Vp = (size_t)((max_vars + 3) & ~3);
     size_t b = sizeof(int32_t) * kCtlWords + Vp * sizeof(int2);
     if (root_lds) b += Vp * sizeof(int2);
-    b += align16(sizeof(int2) * (size_t)max_depth);
+    b += align16(sizeof(int4) * (size_t)kRing);
     if (feat_ndec > 0) b += align16(32 * (size_t)feat_ndec);
     if (list_items > 0) b += 3 * align16(sizeof(uint16_t) * (size_t)list_items);
     b += dep_bytes;
@@ -2203,10 +2246,9 @@ size_t search_lds_bytes(int max_vars, int max_depth, size_t max_desc, bool desc_
     return align16(b);
 }
 
-size_t dep_lds_bytes(int max_depth, bool tstart_lds, int vshift, int qw, const int wcap[4])
+size_t dep_lds_bytes(int vshift, int qw, const int wcap[4])
 {
-    return (tstart_lds ? align16(4 * (size_t)(max_depth + 1)) : 0) +
-           align16(12 * ((size_t)1 << vshift)) + align16(4 * (size_t)qw) +
+    return align16(12 * ((size_t)1 << vshift)) + align16(4 * (size_t)qw) +
            align16(2 * (size_t)(wcap[0] + wcap[1] + wcap[2] + wcap[3]));
 }
 

@@ -10,14 +10,14 @@ namespace pccp {
 size_t model_desc_bytes(int ndiff, int nreif, int nrows, int nterms, int ndec, int nbrows,
                         int nbslots);
 // list_items: sum over kinds of the largest table in the launch when the
-// search keeps item lists (three LDS buffers of 16-bit indices), else 0
+// search keeps item lists (three LDS buffers of 16-bit indices), else 0;
+// the decision stack takes a fixed LDS ring whatever max_depth is
 size_t search_lds_bytes(int max_vars, int max_depth, size_t max_desc, bool desc_lds, bool root_lds,
                         int feat_ndec, int list_items, size_t dep_bytes);
-// LDS of dependency-driven propagation: trail starts of max_depth + 1 path
-// levels (unless they are in global memory), three variable bitmaps of
+// LDS of dependency-driven propagation: three variable bitmaps of
 // 1 << vshift words, qw words of propagator marks and work lists of wcap[k]
 // 16-bit entries
-size_t dep_lds_bytes(int max_depth, bool tstart_lds, int vshift, int qw, const int wcap[4]);
+size_t dep_lds_bytes(int vshift, int qw, const int wcap[4]);
 size_t propagate_lds_bytes(int nvars, size_t desc, bool desc_lds);
 
 hipError_t launch_propagate_batch(const DevModel *m_dev, int nbox, const int32_t *lb_in,

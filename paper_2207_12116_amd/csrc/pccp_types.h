@@ -145,8 +145,7 @@ struct SearchParams {
     int4 *trail;                // [grid * tcap] {x, lb, ub, 0}
     int32_t tcap;
     int32_t pad2;
-    int32_t *tstart_g;          // trail start of each path level, [grid * (max_depth + 1)],
-                                // or null: in LDS
+    int4 *gstack;               // decision stacks, [grid * max_depth]
 };
 
 }  // namespace pccp

@@ -41,6 +41,24 @@ def test_120_tasks_prefix_parity(P):
         (ref["nodes"], ref["fails"], ref["solutions"], ref["best"], ref["max_depth"])
 
 
+@pytest.mark.parametrize("dep", [2, 1], ids=["tables", "dep"])
+def test_deep_paths_prefix_parity(P, dep):
+    """Input-order branching on 120 tasks dives about a thousand decisions
+    deep: a single-workgroup prefix whose path runs far past the decision
+    levels kept in LDS (the rest live in global memory) gives the oracle's
+    counters, depth included."""
+    model = I.rcpsp(120, 1)
+    ref = O.solve(model, branching=O.INPUT_ORDER, node_limit=1500)
+    s = P.Solver(model, num_wgs=1, max_depth=4096, dep=dep)
+    s.set_branching(P.BRANCH_INPUT_ORDER)
+    say("deep prefix", dep, ref["max_depth"])
+    assert s.solve(node_limit=1500, time_limit=120) == P.OUT_LIMIT
+    st = s.stats()
+    assert ref["max_depth"] > 600
+    assert (st["nodes"], st["fails"], st["solutions"], st["best"], st["max_depth"]) == \
+        (ref["nodes"], ref["fails"], ref["solutions"], ref["best"], ref["max_depth"])
+
+
 def test_120_tasks_whole_gpu_incumbent_feasible(P):
     """First-fail on 120 tasks thrashes deep in the tree (the oracle finds no
     schedule in its first 20k nodes either), so its run is only checked for
