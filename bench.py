@@ -51,8 +51,8 @@ PROFILED_TRAFFIC = [
     {"kernel_sha256": K, "block": blk, "desc_lds": dl, "root_lds": rl, "live": 0, "occupancy": oc,
      "dep": dep, "fetch_bytes_per_node": f, "write_bytes_per_node": w,
      "profile": "profiles/search_kernel_rcpsp30_traffic.md"}
-    for K in ["aac757300a5864bea7771c03728868fb0d48b81f640ef23bfcbcebbac58fca93"]
-    for blk, dl, rl, oc, dep, f, w in [(128, 0, 0, 2, 1, 5.30, 173.9)]
+    for K in ["c8213b376311dfd4aa9f887558499c96fa238db896f060c281ae7826480be56a"]
+    for blk, dl, rl, oc, dep, f, w in [(128, 0, 0, 2, 1, 5.18, 180.9)]
 ]
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
