@@ -144,7 +144,9 @@ typedef struct {
                              LDS, 2 = read from global memory                 */
     int32_t root_lds;     /* subtree-root store: 0 = choose, 1 = LDS,
                              2 = global memory                                */
-    int32_t max_depth;    /* decision-stack capacity per workgroup; 0 = 1024  */
+    int32_t max_depth;    /* decision-stack capacity per workgroup; 0 = 1024
+                             (levels live in device memory, the deepest 256
+                             also in LDS: capacity costs no LDS)          */
     int32_t queue_cap;    /* subtree queue slots; 0 = 4 x workgroups          */
     int64_t sol_cap;      /* ENUMERATE: solutions kept (all are counted)      */
     int32_t launch;       /* 0 = one hipGraph (initialisation + search
@@ -159,7 +161,8 @@ typedef struct {
                              LDS buffers of 2 bytes per propagator          */
     int32_t occupancy;    /* search kernel build: 0 = choose (high for
                              wg_size <= 256), 1 = high (at least 7 waves per
-                             SIMD, wg_size <= 256, leaner unrolling),
+                             SIMD, 6 with dep = 1; wg_size <= 256, leaner
+                             unrolling),
                              2 = normal (any wg_size)                       */
     int32_t dep;          /* dependency-driven propagation: 1 = on; 0
                              (default) or 2 = off.  On: after the first sweep

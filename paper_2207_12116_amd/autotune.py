@@ -57,12 +57,30 @@ def _store(path, data):
     os.replace(tmp, path)
 
 
-def _rate(models, mode, cfg, budget_s):
-    solvers = [pccp.Solver(m, config=cfg) for m in models]
-    pccp.batch_solve(solvers, mode, config=cfg, time_limit=budget_s)
+def _run(solvers, mode, cfg, t):
+    pccp.batch_solve(solvers, mode, config=cfg, time_limit=t)
     st = [s.stats() for s in solvers]
-    nodes = sum(x["nodes"] for x in st)
-    return nodes / max(st[0]["kernel_ms"] / 1e3, 1e-9), st[0]
+    return sum(x["nodes"] for x in st), st[0]["kernel_ms"] / 1e3, st[0]
+
+
+def _rate(models, mode, cfg, budget_s, steady=True):
+    """Node rate of a run of budget_s of device time; with `steady`, the
+    nodes and device time of a run of budget_s / 2 are subtracted (every run
+    starts the searches afresh, so the start-up while the queue fills, which
+    favours fewer workgroups in a short run, cancels out)."""
+    solvers = [pccp.Solver(m, config=cfg) for m in models]
+    # an untimed launch first: the first launch of a kernel variant in a
+    # process also loads its code object
+    pccp.batch_solve(solvers, mode, config=cfg, time_limit=min(0.05, budget_s / 4))
+    if not steady:
+        n2, k2, st = _run(solvers, mode, cfg, budget_s)
+        return n2 / max(k2, 1e-9), st
+    n1, k1, _ = _run(solvers, mode, cfg, budget_s / 2)
+    n2, k2, st = _run(solvers, mode, cfg, budget_s)
+    if k2 - k1 < 0.25 * k2 or n2 < n1:
+        # searches that finish early: the whole run's rate
+        return n2 / max(k2, 1e-9), st
+    return (n2 - n1) / (k2 - k1), st
 
 
 def _cfg(x, max_depth):
@@ -72,13 +90,15 @@ def _cfg(x, max_depth):
 
 def tune(models, mode=pccp.MINIMIZE, budget_s=0.4, cache_path=DEFAULT_CACHE, force=False,
          wg_sizes=WG_SIZES, placements=PLACEMENTS, modes=DEFAULT_MODES, log=None, finalists=3,
-         max_depth=0):
+         max_depth=0, steady=True):
     """Return (Config, report) for searching `models` together in one launch.
-    Every candidate is timed for `budget_s` of device time; the `finalists`
-    best are timed again for four times as long (a short run over-weights the
-    start-up while the queue fills) and the best of those is kept, rates
-    within 2 % counting as ties."""
-    key = f"{_device_name()}|{size_class(models, mode)}|d{max_depth}|{'+'.join(modes)}"
+    Every candidate's steady-state rate is taken from runs of budget_s / 2
+    and budget_s of device time (with steady=False: the rate of the whole
+    run of budget_s, start-up included, which is what short searches to a
+    proof see); the `finalists` best are timed again with runs four times as
+    long and the best of those is kept, rates within 2 % counting as ties."""
+    key = (f"{_device_name()}|{size_class(models, mode)}|d{max_depth}|{'+'.join(modes)}"
+           f"|{'steady' if steady else 'whole'}")
     cache = _load(cache_path) if cache_path else {}
     if not force and key in cache:
         c = cache[key]
@@ -89,7 +109,7 @@ def tune(models, mode=pccp.MINIMIZE, budget_s=0.4, cache_path=DEFAULT_CACHE, for
     for wg, (d, r), pm, oc in cands:
         x = {"wg_size": wg, "desc_lds": d, "root_lds": r, "prop": pm, "occupancy": oc}
         try:
-            rate, st = _rate(models, mode, _cfg(x, max_depth), budget_s)
+            rate, st = _rate(models, mode, _cfg(x, max_depth), budget_s, steady)
         except pccp.PccpError as e:
             # a layout that does not fit, or a path deeper than the stack
             if e.code in (pccp.E_LDS_CAPACITY, pccp.E_DEPTH):
@@ -104,7 +124,7 @@ def tune(models, mode=pccp.MINIMIZE, budget_s=0.4, cache_path=DEFAULT_CACHE, for
     results.sort(key=lambda x: -x["nodes_per_s"])
     for x in results[:finalists]:
         try:
-            x["nodes_per_s_long"], _ = _rate(models, mode, _cfg(x, max_depth), 4 * budget_s)
+            x["nodes_per_s_long"], _ = _rate(models, mode, _cfg(x, max_depth), 4 * budget_s, steady)
         except pccp.PccpError as e:
             if e.code != pccp.E_DEPTH:
                 raise

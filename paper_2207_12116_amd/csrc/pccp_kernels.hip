@@ -1509,10 +1509,12 @@ __device__ void flush_counters(Lane0 &z, InstState *is, int mode)
 // items the subtree root kept, A and B alternate down the current path; a
 // backtrack restarts from R, as the store restarts from the root's.
 // HI: workgroups of at most 256 threads and at least 7 wavefronts per SIMD
-// (at most 72 VGPRs): more resident subproblems per CU to hide the latency
-// of the dependent loads, with leaner unrolling.
+// (at most 72 VGPRs; 6 and 80 with dependency-driven sweeps, whose extra
+// state spills more at 72 and measured fastest at 6): more resident
+// subproblems per CU to hide the latency of the dependent loads, with
+// leaner unrolling.
 template <bool DL, bool RL, bool LEARN, int PM, bool HI>
-__global__ __launch_bounds__(HI ? 256 : 1024, HI ? 7 : 1) void search_kernel(SearchParams P)
+__global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? 6 : 7) : 1) void search_kernel(SearchParams P)
 {
     constexpr bool LIVE = PM == 1, DEP = PM == 2;
     extern __shared__ __align__(16) char smem[];
