@@ -46,3 +46,21 @@ def test_model_building_errors_without_device():
     n = ctypes.c_int32(0)
     assert L.pccp_model_info(h, ctypes.byref(n), None, None, None, None) == 0 and n.value == 2
     assert L.pccp_model_destroy(h) == 0
+
+
+def test_config_validation_without_device():
+    """Invalid launch configurations are refused before any device call:
+    item lists together with dependency-driven propagation, out-of-range
+    mode fields, a negative trail capacity, the high-occupancy build with
+    more than 256 threads."""
+    from paper_2207_12116_amd import instances as I
+    L = pccp.lib()
+    mh = pccp.ModelHandle(I.tiny_rcpsp(4, 0))
+    bad = [dict(live=1, dep=1), dict(dep=3), dict(live=-1), dict(trail_cap=-1),
+           dict(occupancy=1, wg_size=512), dict(wg_size=96)]
+    for kw in bad:
+        cfg = pccp.Config(**kw)
+        h = ctypes.c_void_p()
+        rc = L.pccp_solver_create(mh.h, ctypes.byref(cfg), None, ctypes.byref(h))
+        assert rc == pccp.E_INVALID_ARG, (kw, rc)
+        assert not h.value
