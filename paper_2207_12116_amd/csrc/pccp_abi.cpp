@@ -696,6 +696,7 @@ struct ShapeNeed {
 struct DepLayout {
     int vshift = 0, qw = 0;
     int wcap[4] = {0, 0, 0, 0};
+    int jcap = 0;       // two-phase expansion for workgroups of 8 or more wavefronts
 };
 
 static DepLayout dep_layout(int max_vars, const int items[4], int scale)
@@ -756,7 +757,8 @@ static int32_t choose_shape(const pccp_config &cfg, const ShapeNeed &nd, int num
             size_t depb = 0;
             if (pm == 2) {
                 dl = dep_layout(nd.max_vars, nd.max_items, 1 << li);
-                depb = dep_lds_bytes(dl.vshift, dl.qw, dl.wcap);
+                dl.jcap = sh.block >= 512 && !k.hi ? 512 : 0;
+                depb = dep_lds_bytes(dl.vshift, dl.qw, dl.wcap, dl.jcap);
             }
             const size_t lds = search_lds_bytes(nd.max_vars, cfg.max_depth, nd.max_desc, cd.d, cd.r,
                                                 nd.feat_ndec, list_items, depb);
@@ -881,6 +883,7 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
     P.dep_vshift = sh.dep.vshift;
     P.dep_qw = sh.dep.qw;
     for (int k = 0; k < 4; ++k) P.dep_wcap[k] = sh.dep.wcap[k];
+    P.dep_jcap = sh.dep.jcap;
     P.trail = sh.k.dep ? ws.trail.as<int4>() : nullptr;
     P.tcap = tcap;
     P.gstack = ws.gstack.as<int4>();

@@ -184,6 +184,7 @@ enum : int {
     C_TTOP = 24,                            // entries pushed on the trail
     C_THI = 25,                             // deepest path level without a whole trail
     C_MAXW = 26,                            // deepest decision-stack level written
+    C_JCNT = 28,                            // entries of the expansion's job list
 };
 
 // ------------------------------------------------------------ descriptors
@@ -368,6 +369,9 @@ struct Dep {
     uint16_t *wl;             // work lists: kind k at wl + woff[k], wcap[k] entries
     int4 *trail;              // this workgroup's trail (global), tcap entries
     int32_t *ttop;            // LDS word: entries pushed (may pass tcap)
+    uint32_t *jobs;           // two-phase expansion: changed variables, jcap entries
+    int32_t *jcnt;            // LDS word: entries in jobs (may pass jcap)
+    int jcap;                 // 0: one-phase expansion
     int vshift, vmask, vw, qw;
     int woff[4], wcap[4], qoff[4];
     int tcap;
@@ -940,6 +944,41 @@ __device__ int propagate_wg(const View<DL> &v, int2 *st, int32_t *ctl, const Nod
 // capacity means the next sweep runs that kind's whole table.
 // Bitmap word w is read by wavefront w % nw, so the variables of one
 // region of the store (the start times, say) spread over all wavefronts.
+// one chunk of adjacency entries (0 = none): queue the propagators that read
+// a bound in `reads`
+template <bool DL>
+__device__ __forceinline__ void dep_queue(const View<DL> &v, const Dep &dp, int32_t *cnt,
+                                          uint32_t e, uint32_t reads)
+{
+    const int lane = threadIdx.x & 63;
+    const int k = (int)((e >> 16) & 3u), idx = (int)(e & 0xffffu);
+    bool fire = (e & reads) != 0;
+    if (fire) {
+        const int p = idx + (k == 0 ? dp.qoff[0] : k == 1 ? dp.qoff[1] : k == 2 ? dp.qoff[2] : dp.qoff[3]);
+        const uint32_t qb = 1u << (p & 31);
+        fire = !(__hip_atomic_fetch_or(dp.qm + (p >> 5), qb, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP) & qb);
+    }
+#pragma unroll
+    for (int kk = 0; kk < kKindsDep; ++kk) {
+        const unsigned long long mk = __ballot(fire && k == kk);
+        if (mk == 0) continue;
+        int pos = 0;
+        if (lane == 0)
+            pos = __hip_atomic_fetch_add(cnt + kk, __popcll(mk), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+        pos = __builtin_amdgcn_readfirstlane(pos);
+        if (fire && k == kk) {
+            const int r = pos + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+            if (r < dp.wcap[kk]) dp.wl[dp.woff[kk] + r] = (uint16_t)idx;
+            if (kk >= 2)
+                __hip_atomic_fetch_add(cnt + 2 + kk, kk == 2 ? v.rows(idx).y : v.brows(idx).y,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+}
+
 template <bool DL>
 __device__ void dep_expand(const View<DL> &v, const Dep &dp, int32_t *cnt)
 {
@@ -969,40 +1008,85 @@ __device__ void dep_expand(const View<DL> &v, const Dep &dp, int32_t *cnt)
                 const int x = (b << dp.vshift) | wl;
                 const uint32_t reads = (((ml >> b) & 1u) ? kAdjLb : 0u) | (((mu >> b) & 1u) ? kAdjUb : 0u);
                 const int a0 = uni(v.adjp(x)), a1 = uni(v.adjp(x + 1));
-                for (int a = a0; a < a1; a += 64) {
-                    const int ai = a + lane;
-                    const uint32_t e = ai < a1 ? v.adj(ai) : 0u;
-                    const int k = (int)((e >> 16) & 3u), idx = (int)(e & 0xffffu);
-                    bool fire = (e & reads) != 0;
-                    if (fire) {
-                        const int p = idx + (k == 0 ? dp.qoff[0] : k == 1 ? dp.qoff[1]
-                                             : k == 2 ? dp.qoff[2] : dp.qoff[3]);
-                        const uint32_t qb = 1u << (p & 31);
-                        fire = !(__hip_atomic_fetch_or(dp.qm + (p >> 5), qb, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_WORKGROUP) & qb);
-                    }
-#pragma unroll
-                    for (int kk = 0; kk < kKindsDep; ++kk) {
-                        const unsigned long long mk = __ballot(fire && k == kk);
-                        if (mk == 0) continue;
-                        int pos = 0;
-                        if (lane == 0)
-                            pos = __hip_atomic_fetch_add(cnt + kk, __popcll(mk), __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
-                        pos = __builtin_amdgcn_readfirstlane(pos);
-                        if (fire && k == kk) {
-                            const int r = pos + (int)__builtin_amdgcn_mbcnt_hi(
-                                                    (uint32_t)(mk >> 32),
-                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
-                            if (r < dp.wcap[kk]) dp.wl[dp.woff[kk] + r] = (uint16_t)idx;
-                            if (kk >= 2)
-                                __hip_atomic_fetch_add(cnt + 2 + kk,
-                                                       kk == 2 ? v.rows(idx).y : v.brows(idx).y,
-                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        }
-                    }
-                }
+                for (int a = a0; a < a1; a += 64)
+                    dep_queue(v, dp, cnt, a + lane < a1 ? v.adj(a + lane) : 0u, reads);
             }
+        }
+    }
+}
+
+// Two-phase expansion for workgroups of many wavefronts, where one
+// wavefront's share of the changed variables (a start time of a large
+// instance is read by hundreds of propagators) would keep the others
+// waiting.  Phase 1 (before a barrier): each bitmap word's owner lane clears
+// it and appends its variables, with the bounds that changed, to the job
+// list.  Phase 2 (`dep_expand_jobs`, after the barrier): every wavefront
+// loads the adjacency ranges of 64 listed variables at a time, numbers
+// their chunks of 64 entries in list order and takes chunks wid, wid + nw,
+// ...  A list longer than jcap makes the next sweep run every table.
+__device__ void dep_expand_list(const Dep &dp)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int base = 0; base < dp.vw; base += 64 * nw) {
+        const int w = base + wid + nw * lane;
+        if (w >= dp.vw) continue;
+        const uint32_t bl = dp.lm[w], bu = dp.um[w];
+        uint32_t bits = bl | bu;
+        if (!bits) continue;
+        dp.lm[w] = 0;
+        dp.um[w] = 0;
+        int pos = __hip_atomic_fetch_add(dp.jcnt, __popc(bits), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+        while (bits) {
+            const int b = __builtin_ctz(bits);
+            bits &= bits - 1;
+            if (pos < dp.jcap)
+                dp.jobs[pos] = (uint32_t)((b << dp.vshift) | w) | (((bl >> b) & 1u) << 30) |
+                               (((bu >> b) & 1u) << 31);
+            ++pos;
+        }
+    }
+}
+
+template <bool DL>
+__device__ void dep_expand_jobs(const View<DL> &v, const Dep &dp, int32_t *cnt)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int n = uni(lds_ld(dp.jcnt));
+    if (n > dp.jcap) {
+        // too many changed variables: every table next sweep
+        if (threadIdx.x == 0)
+            for (int k = 0; k < 4; ++k) cnt[k] = dp.wcap[k] + 1;
+        return;
+    }
+    for (int r0 = 0; r0 < n; r0 += 64) {
+        const int i = r0 + lane;
+        uint32_t ent = 0;
+        int a0 = 0, a1 = 0;
+        if (i < n) {
+            ent = dp.jobs[i];
+            const int x = (int)(ent & 0x3fffffffu);
+            a0 = v.adjp(x);
+            a1 = v.adjp(x + 1);
+        }
+        const int nch = (a1 - a0 + 63) >> 6;
+        // inclusive scan of the chunk counts over the wavefront
+        int incl = nch;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int t = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += t;
+        }
+        const int first = incl - nch;
+        const int total = __shfl(incl, 63, 64);
+        for (int j = wid; j < total; j += nw) {
+            // the variable whose chunks contain j: the last lane starting at or before j
+            const int L = 63 - __builtin_clzll(__ballot(first <= j && nch > 0));
+            const int b0 = __shfl(a0, L, 64), b1 = __shfl(a1, L, 64);
+            const uint32_t e0 = (uint32_t)__shfl((int)ent, L, 64);
+            const uint32_t reads = ((e0 >> 30) & 1u ? kAdjLb : 0u) | ((e0 >> 31) & 1u ? kAdjUb : 0u);
+            const int a = b0 + 64 * (j - __shfl(first, L, 64));
+            dep_queue(v, dp, cnt, a + lane < b1 ? v.adj(a + lane) : 0u, reads);
         }
     }
 }
@@ -1013,7 +1097,9 @@ __device__ void dep_expand(const View<DL> &v, const Dep &dp, int32_t *cnt)
 // fixed point joined with the tells marked since (a decision, the objective
 // bound), and the first sweep runs what they make ready.  Returns as
 // propagate_wg; ex[] counts the items and row terms run.
-template <bool DL, bool LEAN>
+// TWO: the build may run the two-phase expansion (workgroups of 8 or more
+// wavefronts, dp.jcap > 0); the high-occupancy build never does.
+template <bool DL, bool LEAN, bool TWO>
 __device__ int propagate_dep(const View<DL> &v, int2 *st, int32_t *ctl, const Dep &dp, bool full,
                              uint32_t &nsweeps, unsigned long long (&ex)[4])
 {
@@ -1025,6 +1111,7 @@ __device__ int propagate_dep(const View<DL> &v, int2 *st, int32_t *ctl, const De
         ctl[C_POSTFAIL] = 0;
         *reinterpret_cast<unsigned long long *>(ctl + C_KEY) = ~0ull;
         for (int k = 0; k < 12; ++k) ctl[C_DCNT + k] = 0;
+        ctl[C_JCNT] = 0;
     }
     if (full)
         for (int w = tid; w < dp.vw; w += W) {
@@ -1034,10 +1121,18 @@ __device__ int propagate_dep(const View<DL> &v, int2 *st, int32_t *ctl, const De
         }
     lds_barrier();
     int set = 0;   // count set of the lists the next sweep runs
-    if (!full) {
-        dep_expand(v, dp, ctl + C_DCNT);
+    // one expansion into the count set cs, ending with a barrier
+    auto expand = [&](int32_t *cs) {
+        if (TWO && dp.jcap) {
+            dep_expand_list(dp);
+            lds_barrier();
+            dep_expand_jobs(v, dp, cs);
+        } else {
+            dep_expand(v, dp, cs);
+        }
         lds_barrier();
-    }
+    };
+    if (!full) expand(ctl + C_DCNT);
     const int tab[4] = {v.ndiff, v.nreif, v.nrows, v.nbrows};
     int slot = 0;
     bool all = full;
@@ -1054,8 +1149,10 @@ __device__ int propagate_dep(const View<DL> &v, int2 *st, int32_t *ctl, const De
         }
         const int terms = (whole[2] ? v.nterms : uni(lds_ld(&c[4]))) +
                           (whole[3] ? v.nbterms : uni(lds_ld(&c[5])));
-        if (tid == 0)
+        if (tid == 0) {
             for (int k = 0; k < 6; ++k) ctl[C_DCNT + 6 * (set ^ 1) + k] = 0;
+            ctl[C_JCNT] = 0;    // read by the last expansion before the barrier ending it
+        }
         // the queued bits of the lists run now are cleared for the next expansion
         for (int w = tid; w < dp.qw; w += W) dp.qm[w] = 0;
         bool chg = false, bad = false;
@@ -1089,8 +1186,7 @@ __device__ int propagate_dep(const View<DL> &v, int2 *st, int32_t *ctl, const De
         slot = next;
         set ^= 1;
         all = false;
-        dep_expand(v, dp, ctl + C_DCNT + 6 * set);
-        lds_barrier();
+        expand(ctl + C_DCNT + 6 * set);
     }
 }
 
@@ -1554,6 +1650,10 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? 6 : 7) : 1) void s
         p += align16(4 * (size_t)P.dep_qw);
         dp.wl = reinterpret_cast<uint16_t *>(p);
         p += align16(2 * (size_t)(P.dep_wcap[0] + P.dep_wcap[1] + P.dep_wcap[2] + P.dep_wcap[3]));
+        dp.jobs = reinterpret_cast<uint32_t *>(p);
+        p += align16(4 * (size_t)P.dep_jcap);
+        dp.jcap = P.dep_jcap;
+        dp.jcnt = ctl + C_JCNT;
         dp.vshift = P.dep_vshift;
         dp.vmask = vw - 1;
         dp.vw = vw;
@@ -1755,7 +1855,7 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? 6 : 7) : 1) void s
             if constexpr (DEP) {
                 dp.trail_on = !node_full;
                 // work lists are short: lean unrolling (fewer registers)
-                rc = propagate_dep<DL, true>(v, st, ctl, dp, node_full, nsw, ex);
+                rc = propagate_dep<DL, true, !HI>(v, st, ctl, dp, node_full, nsw, ex);
                 // the next node's trail marks start empty; a node whose
                 // changes did not all fit on the trail cannot be undone
                 for (int w = tid; w < dp.vw; w += W) dp.tm[w] = 0;
@@ -2248,10 +2348,10 @@ size_t search_lds_bytes(int max_vars, int max_depth, size_t max_desc, bool desc_
     return align16(b);
 }
 
-size_t dep_lds_bytes(int vshift, int qw, const int wcap[4])
+size_t dep_lds_bytes(int vshift, int qw, const int wcap[4], int jcap)
 {
     return align16(12 * ((size_t)1 << vshift)) + align16(4 * (size_t)qw) +
-           align16(2 * (size_t)(wcap[0] + wcap[1] + wcap[2] + wcap[3]));
+           align16(2 * (size_t)(wcap[0] + wcap[1] + wcap[2] + wcap[3])) + align16(4 * (size_t)jcap);
 }
 
 size_t propagate_lds_bytes(int nvars, size_t desc, bool desc_lds)

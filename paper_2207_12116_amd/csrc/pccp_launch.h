@@ -15,9 +15,9 @@ size_t model_desc_bytes(int ndiff, int nreif, int nrows, int nterms, int ndec, i
 size_t search_lds_bytes(int max_vars, int max_depth, size_t max_desc, bool desc_lds, bool root_lds,
                         int feat_ndec, int list_items, size_t dep_bytes);
 // LDS of dependency-driven propagation: three variable bitmaps of
-// 1 << vshift words, qw words of propagator marks and work lists of wcap[k]
-// 16-bit entries
-size_t dep_lds_bytes(int vshift, int qw, const int wcap[4]);
+// 1 << vshift words, qw words of propagator marks, work lists of wcap[k]
+// 16-bit entries and (two-phase expansion) a job list of jcap words
+size_t dep_lds_bytes(int vshift, int qw, const int wcap[4], int jcap);
 size_t propagate_lds_bytes(int nvars, size_t desc, bool desc_lds);
 
 hipError_t launch_propagate_batch(const DevModel *m_dev, int nbox, const int32_t *lb_in,

@@ -144,7 +144,7 @@ struct SearchParams {
     int32_t dep_wcap[4];
     int4 *trail;                // [grid * tcap] {x, lb, ub, 0}
     int32_t tcap;
-    int32_t pad2;
+    int32_t dep_jcap;           // job-list entries of the two-phase expansion (0: one phase)
     int4 *gstack;               // decision stacks, [grid * max_depth]
 };
 
