@@ -131,6 +131,23 @@ def single_instance_leg(n, seed, limit, cfg):
             "grid": st["grid"], "block": st["block"], "time_s": round(dt, 3)}
 
 
+def jobshop_leg(models, limit, cfg):
+    """Job shops compiled by the PCCP front-end (disjunctions on reified
+    differences), searched in one persistent launch."""
+    from paper_2207_12116_amd import pccp
+    solvers = [pccp.Solver(m, config=cfg) for m in models]
+    t0 = time.perf_counter()
+    outs = pccp.batch_solve(solvers, pccp.MINIMIZE, config=cfg, time_limit=limit)
+    dt = time.perf_counter() - t0
+    sts = [s.stats() for s in solvers]
+    nodes = sum(x["nodes"] for x in sts)
+    return {"instances": len(models), "jobs": 10, "machines": 10,
+            "nodes_per_s": round(nodes / dt, 1),
+            "proven": sum(o in (pccp.OUT_OPTIMAL, pccp.OUT_UNSAT) for o in outs),
+            "best": [x["best"] for x in sts], "grid": sts[0]["grid"], "block": sts[0]["block"],
+            "time_s": round(dt, 3)}
+
+
 def mixed_batch_leg(count, limit, cfg):
     """`count` instances of 30, 60 and 90 tasks (by seed mod 3) in one
     persistent launch."""
@@ -394,6 +411,14 @@ def main():
         c4cfg, c4rep = autotune.tune(c4m, pccp.MINIMIZE, budget_s=0.3, cache_path=None,
                                      wg_sizes=(256, 512, 1024), max_depth=4096, log=log)
         legs["c4_mixed256"] = mixed_batch_leg(256, 3.0, c4cfg)
+        log("job shops 10x10 from the PCCP front-end, 16 in one launch")
+        jsm = [I.jobshop(10, 10, s) for s in range(16)]
+        jscfg, jsrep = autotune.tune(jsm, pccp.MINIMIZE, budget_s=0.3, cache_path=None,
+                                     wg_sizes=(128, 256), max_depth=4096, log=log)
+        legs["jobshop_10x10_batch16"] = jobshop_leg(jsm, 3.0, jscfg)
+        legs["jobshop_10x10_batch16"]["config"] = {"wg_size": jscfg.wg_size, "prop": jsrep["prop"],
+                                                   "occupancy": jscfg.occupancy}
+        log(f"jobshop: {legs['jobshop_10x10_batch16']}")
         legs["c4_mixed256"]["config"] = {"wg_size": c4cfg.wg_size, "desc_lds": c4cfg.desc_lds,
                                          "root_lds": c4cfg.root_lds, "prop": c4rep["prop"],
                                          "max_depth": c4cfg.max_depth}

@@ -36,6 +36,7 @@ CFG_TINY_CSP = 1
 CFG_RCPSP = 2
 CFG_TINY_RCPSP = 3
 CFG_PREC_ONLY = 4
+CFG_JOBSHOP = 5
 
 
 class SplitMix64:
@@ -287,3 +288,44 @@ def precedence_only(n: int, seed: int) -> Model:
 def batch_sizes(seed: int) -> int:
     """Mixed-size batch: the task count of seed s is (30, 60, 90)[s mod 3]."""
     return (30, 60, 90)[seed % 3]
+
+
+def jobshop_data(n_jobs: int, n_mach: int, seed: int, dmax: int = 10):
+    """Synthetic job shop: every job visits every machine once, in a random
+    order, with durations uniform in 1..dmax.  Returns jobs[j] = list of
+    (machine, duration) in the job's order."""
+    rng = stream(CFG_JOBSHOP, seed)
+    jobs = []
+    for _ in range(n_jobs):
+        order = list(range(n_mach))
+        rng.shuffle(order)
+        jobs.append([(m, rng.uniform(1, dmax)) for m in order])
+    return jobs
+
+
+def jobshop(n_jobs: int, n_mach: int, seed: int) -> Model:
+    """The job shop as a PCCP program (front-end in `lang`): start times s,
+    makespan m; precedences along each job; for every pair of operations on
+    one machine, a disjunction of their two orders.  Variable layout: the
+    starts job by job, then m, then the auxiliaries of the disjunctions."""
+    from .lang import Program
+    jobs = jobshop_data(n_jobs, n_mach, seed)
+    h = sum(d for job in jobs for _, d in job)
+    p = Program()
+    s = [[p.var(0, h) for _ in job] for job in jobs]
+    m = p.var(0, h)
+    on = {k: [] for k in range(n_mach)}
+    for j, job in enumerate(jobs):
+        for k, (mach, d) in enumerate(job):
+            nxt = s[j][k + 1] if k + 1 < len(job) else m
+            p.tell([1, -1], [s[j][k], nxt], -d)            # s + d <= next
+            on[mach].append((s[j][k], d))
+    for ops in on.values():
+        for a in range(len(ops)):
+            for b in range(a + 1, len(ops)):
+                (x, dx), (y, dy) = ops[a], ops[b]
+                p.disj(x, y, -dx, y, x, -dy)               # x + dx <= y or y + dy <= x
+    dec = [v for row in s for v in row]
+    return p.compile(decision=dec, objective=m,
+                     meta=dict(kind="jobshop", jobs=jobs, n_jobs=n_jobs, n_mach=n_mach,
+                               horizon=h, seed=seed))

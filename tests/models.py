@@ -39,3 +39,46 @@ def random_subbox(model, rng, frac=0.3, tight=0.5):
             else:
                 ub[v] = b
     return lb, ub
+
+
+def jobshop_brute(jobs):
+    """Minimum makespan of a job shop by enumeration of every machine's
+    operation order (the disjunctive graph): for each combination of orders,
+    the earliest schedule is the longest path through the job and machine
+    arcs; a combination with a cycle is infeasible.  Independent of any
+    constraint model."""
+    import itertools
+    ops = [(j, k) for j, job in enumerate(jobs) for k in range(len(job))]
+    dur = {(j, k): jobs[j][k][1] for j, k in ops}
+    on = {}
+    for j, k in ops:
+        on.setdefault(jobs[j][k][0], []).append((j, k))
+    machines = sorted(on)
+    best = None
+    for orders in itertools.product(*[itertools.permutations(on[m]) for m in machines]):
+        succ = {o: [] for o in ops}
+        indeg = {o: 0 for o in ops}
+        for j, job in enumerate(jobs):
+            for k in range(len(job) - 1):
+                succ[(j, k)].append((j, k + 1))
+                indeg[(j, k + 1)] += 1
+        for order in orders:
+            for a, b in zip(order, order[1:]):
+                succ[a].append(b)
+                indeg[b] += 1
+        start = {o: 0 for o in ops}
+        ready = [o for o in ops if indeg[o] == 0]
+        seen = 0
+        while ready:
+            o = ready.pop()
+            seen += 1
+            for q in succ[o]:
+                start[q] = max(start[q], start[o] + dur[o])
+                indeg[q] -= 1
+                if indeg[q] == 0:
+                    ready.append(q)
+        if seen < len(ops):
+            continue            # a cycle: these orders admit no schedule
+        ms = max(start[o] + dur[o] for o in ops)
+        best = ms if best is None else min(best, ms)
+    return best
