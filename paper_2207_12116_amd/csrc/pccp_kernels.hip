@@ -937,8 +937,8 @@ __device__ int propagate_wg(const View<DL> &v, int2 *st, int32_t *ctl, const Nod
 }
 
 // Work lists of the next sweep from the change bitmaps of the last one:
-// every propagator that reads a tightened bound, once (the queued bit qm of
-// a propagator is set when it is listed).  Clears the bitmaps.  cnt: list
+// every propagator that reads a tightened bound (rows once: the queued bit
+// qm of a row is set when it is listed; see dep_queue).  Clears the bitmaps.  cnt: list
 // counts of the 4 kinds, then the terms of the listed rows of kinds 3 and
 // 4; zeroed by the caller before a barrier.  A count past its list's
 // capacity means the next sweep runs that kind's whole table.
@@ -953,8 +953,11 @@ __device__ __forceinline__ void dep_queue(const View<DL> &v, const Dep &dp, int3
     const int lane = threadIdx.x & 63;
     const int k = (int)((e >> 16) & 3u), idx = (int)(e & 0xffffu);
     bool fire = (e & reads) != 0;
-    if (fire) {
-        const int p = idx + (k == 0 ? dp.qoff[0] : k == 1 ? dp.qoff[1] : k == 2 ? dp.qoff[2] : dp.qoff[3]);
+    // difference rows and reified items may be listed twice (two of their
+    // variables changed): running one twice costs less than the queued
+    // bit's round trip; rows, which visit many terms, are listed once
+    if (fire && k >= 2) {
+        const int p = idx + (k == 2 ? dp.qoff[2] : dp.qoff[3]);
         const uint32_t qb = 1u << (p & 31);
         fire = !(__hip_atomic_fetch_or(dp.qm + (p >> 5), qb, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP) & qb);
