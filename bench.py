@@ -51,8 +51,8 @@ PROFILED_TRAFFIC = [
     {"kernel_sha256": K, "block": blk, "desc_lds": dl, "root_lds": rl, "live": 0, "occupancy": oc,
      "dep": dep, "fetch_bytes_per_node": f, "write_bytes_per_node": w,
      "profile": "profiles/search_kernel_rcpsp30_traffic.md"}
-    for K in ["626db88b30d6f00434242499a2af7387dc1a4af02f1f6df0f09cda22258a4c90"]
-    for blk, dl, rl, oc, dep, f, w in [(128, 0, 0, 1, 1, 6.18, 291.1)]
+    for K in ["b443c51ee41959df42d43192414e7c1dc54d61a554b1ba44484a4e7269b5b9fa"]
+    for blk, dl, rl, oc, dep, f, w in [(128, 0, 0, 1, 1, 6.21, 301.0)]
 ]
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
