@@ -5,7 +5,10 @@
   - a mixed batch of 30-, 60- and 90-task instances in one persistent launch:
     every incumbent is feasible (checked instant by instant on the raw data),
     proven optima agree with the same instances searched one per launch, and
-    the batch agrees with the same instances in a different order."""
+    the batch agrees with the same instances in a different order;
+  - the batch of sixteen 30-task instances in the launch shape the node-rate
+    measurement uses: the oracle's prefix on one workgroup, and sound
+    incumbents at full size over the whole GPU."""
 import sys
 
 import numpy as np
@@ -119,3 +122,58 @@ def test_mixed_batch_small_proven(P):
             assert s.best()[0] == r["best"]
         ok, ms = O.check_schedule(m.meta, s.best()[1])
         assert ok and ms == s.best()[0]
+
+
+# the batch of sixteen 30-task instances (seeds 0-15) in the launch shape
+# the node-rate measurement settles on: workgroups of 128 threads, tables
+# and subtree roots in HBM, the high-occupancy build, dependency-driven sweeps
+HEADLINE = dict(wg_size=128, desc_lds=2, root_lds=2, occupancy=1, dep=1)
+
+
+def test_headline_shape_single_wg_prefix(P):
+    """The same kernel variant on one workgroup: the oracle's depth-first
+    prefix, every counter equal."""
+    for seed, limit in ((0, 2500), (7, 2000), (15, 2000)):
+        m = I.rcpsp(30, seed)
+        ref = O.solve(m, node_limit=limit)
+        s = P.Solver(m, config=P.Config(num_wgs=1, **HEADLINE))
+        out = s.solve(node_limit=limit, time_limit=60)
+        st = s.stats()
+        say("headline shape 1wg", seed, st["nodes"], ref["nodes"])
+        assert out == P.OUT_LIMIT and ref["outcome"] == O.OUT_LIMIT
+        assert (st["block"], st["occupancy"], st["dep"]) == (128, 1, 1)
+        assert (st["nodes"], st["fails"], st["solutions"], st["best"], st["max_depth"]) == \
+            (ref["nodes"], ref["fails"], ref["solutions"], ref["best"], ref["max_depth"])
+
+
+def test_headline_batch_full_size_sound(P):
+    """The whole batch at its full size in that shape (a persistent launch
+    over the whole GPU): each incumbent is a feasible schedule on the raw
+    data, with the makespan the kernel reports, never below the oracle's root
+    bound; the counters are consistent; a second launch of the same solvers
+    starts afresh and is just as sound."""
+    models = [I.rcpsp(30, s) for s in range(16)]
+    roots = [O.propagate(m) for m in models]
+    cfg = P.Config(**HEADLINE)
+    solvers = [P.Solver(m, config=cfg) for m in models]
+    for rep in range(2):
+        outs = P.batch_solve(solvers, P.MINIMIZE, config=cfg, time_limit=2.0)
+        st0 = solvers[0].stats()
+        say("headline batch", rep, st0["grid"], st0["block"],
+            sum(s.stats()["nodes"] for s in solvers))
+        assert st0["block"] == 128 and st0["grid"] >= 256 and st0["dep"] == 1
+        found = 0
+        for m, s, o, r in zip(models, solvers, outs, roots):
+            st = s.stats()
+            assert o in (P.OUT_LIMIT, P.OUT_OPTIMAL)
+            assert 0 < st["nodes"] and st["fails"] <= st["nodes"]
+            # dependency-driven sweeps run a fraction of the tables per node
+            assert st["prop_linear2"] + st["prop_reified"] > 0
+            obj, vals = s.best()
+            if obj is None:
+                continue
+            found += 1
+            ok, ms = O.check_schedule(m.meta, vals)
+            assert ok and ms == obj == st["best"], m.meta["seed"]
+            assert obj >= r[1][m.objective]
+        assert found >= 8
