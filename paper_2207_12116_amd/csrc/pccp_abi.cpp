@@ -855,7 +855,9 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
     for (int i = 0; i < n; ++i) hm[i] = sv[i]->hmodel;
     HIPCHK(hipMemcpyAsync(ws.models.p, hm.data(), sizeof(DevModel) * n, hipMemcpyHostToDevice, s0->stream));
 
-    SearchParams P{};
+    // zeroed bytewise: the struct's bytes, padding included, key the graph cache
+    SearchParams P;
+    memset(&P, 0, sizeof(P));
     P.models = ws.models.as<DevModel>();
     P.inst = ws.inst.as<InstState>();
     P.ninst = n;
