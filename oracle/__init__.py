@@ -86,6 +86,8 @@ def lib():
         L.orc_trace.restype = C.c_int64
         L.orc_set_mlp_params.argtypes = [PD]
         L.orc_set_mlp_params.restype = None
+        L.orc_mlp_choice.argtypes = [MP, PD, _P32, _P32]
+        L.orc_mlp_choice.restype = C.c_int32
         L.orc_floor_div.argtypes = [C.c_int64, C.c_int64]
         L.orc_floor_div.restype = C.c_int64
         L.orc_ceil_div.argtypes = [C.c_int64, C.c_int64]
@@ -311,6 +313,16 @@ def trace(model, node_limit, mode=None, cap_nodes=100000, cap_cand=4000000):
     c = int(nc.value)
     return dict(feat=feat[:c].copy(), score=score[:c].copy(), cand=cand[:c].copy(),
                 off=off[:n + 1].copy(), label=lab[:n].copy())
+
+
+def mlp_choice(model, params, lb, ub):
+    """Decision-list position the network branches on at the store (lb, ub)
+    (the earliest of equal scores; fixed candidates skipped), or -1."""
+    om = _om(model)
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    assert p.shape == (NPARAM,)
+    lb, ub = _i32(lb), _i32(ub)
+    return int(lib().orc_mlp_choice(om.ref(), _pd(p), _ptr(lb), _ptr(ub)))
 
 
 _mlp_keep = None

@@ -158,6 +158,11 @@ int32_t orc_mlp_forward(const double *p, const double *x, int64_t ncand, double 
 int32_t orc_mlp_loss_grad(const double *p, const double *x, const int32_t *node_off,
                           const double *t, int32_t nnodes, double *loss, double *g);
 
+/* The network's branching choice at a propagated store: the decision-list
+ * position of the unfixed candidate with the largest score under p (ties to
+ * the earliest), or -1 if every decision variable is fixed. */
+int32_t orc_mlp_choice(const orc_model *m, const double *p, const int32_t *lb, const int32_t *ub);
+
 /* Search traces with expert labels (see learn.c). */
 int64_t orc_trace(const orc_model *m, int32_t mode, int64_t node_limit, float *feat,
                   double *score, int32_t *cand, int32_t *off, int32_t *label, int64_t cap_nodes,
