@@ -181,10 +181,10 @@ enum : int {
                                             // (R, A, B) = 4 kinds, row terms
     C_DCNT = 12,                            // or work-list counts: 6 words per set
                                             // (2 sets) = 4 kinds, terms of kinds 3, 4
-    C_TTOP = 24,                            // entries pushed on the trail
-    C_THI = 25,                             // deepest path level without a whole trail
-    C_MAXW = 26,                            // deepest decision-stack level written
+    C_TTOP = 24,                            // entries pushed on the trail (dependency-driven
+    C_THI = 25,                             // deepest path level without a whole trail  only)
     C_JCNT = 28,                            // entries of the expansion's job list
+    C_MAXW = 29,                            // deepest decision-stack level written (every mode)
 };
 
 // ------------------------------------------------------------ descriptors
@@ -862,7 +862,12 @@ __device__ __forceinline__ void sweep_brows(const View<DL> &v, int2 *st, const L
 constexpr int kKinds = 4;
 constexpr int kKindsDep = 4;
 constexpr int kListWords = kKinds + 1;
-static_assert(C_CNT + 3 * kListWords <= 32, "list counts must stay below the control lane's state");
+// Item lists (the live mode) and work lists (the dependency-driven mode) are
+// never used together; each must stay clear of the words every mode uses.
+static_assert(C_CNT + 3 * kListWords <= C_SKIP, "item-list counts overlap C_SKIP");
+static_assert(C_DCNT + 2 * 6 <= C_TTOP, "work-list counts overlap the trail words");
+static_assert(C_MAXW >= C_CNT + 3 * kListWords && C_MAXW != C_SKIP && C_MAXW != C_JCNT &&
+                  C_MAXW < 32, "the stack word must lie outside every count range");
 struct NodeLists {
     const uint16_t *in[kKinds];
     int nin[kKinds];

@@ -44,20 +44,28 @@ def test_120_tasks_prefix_parity(P):
         (ref["nodes"], ref["fails"], ref["solutions"], ref["best"], ref["max_depth"])
 
 
-@pytest.mark.parametrize("dep", [2, 1], ids=["tables", "dep"])
-def test_deep_paths_prefix_parity(P, dep):
-    """Input-order branching on 120 tasks dives about a thousand decisions
-    deep: a single-workgroup prefix whose path runs far past the decision
-    levels kept in LDS (the rest live in global memory) gives the oracle's
-    counters, depth included."""
-    model = I.rcpsp(120, 1)
+DEEP = [(120, 1, dict(dep=2)), (120, 1, dict(dep=1)), (60, 1, dict(live=1)), (60, 2, dict(live=1)),
+        (60, 1, dict(dep=1))]
+
+
+@pytest.mark.parametrize("n,seed,mode", DEEP, ids=["120-tables", "120-dep", "60-lists", "60b-lists",
+                                                   "60-dep"])
+def test_deep_paths_prefix_parity(P, n, seed, mode):
+    """Input-order branching dives hundreds of decisions deep (about a
+    thousand at 120 tasks, about 400 at 60): a single-workgroup prefix whose
+    path runs far past the decision levels kept in LDS (the rest live in
+    global memory) gives the oracle's counters, depth included.  The item
+    lists of the live mode share the control block with the stack's
+    deepest-level word, so that mode is covered here too."""
+    model = I.rcpsp(n, seed)
     ref = O.solve(model, branching=O.INPUT_ORDER, node_limit=1500)
-    s = P.Solver(model, num_wgs=1, max_depth=4096, dep=dep)
+    s = P.Solver(model, num_wgs=1, max_depth=4096, **mode)
     s.set_branching(P.BRANCH_INPUT_ORDER)
-    say("deep prefix", dep, ref["max_depth"])
+    say("deep prefix", n, seed, mode, ref["max_depth"])
     assert s.solve(node_limit=1500, time_limit=120) == P.OUT_LIMIT
     st = s.stats()
-    assert ref["max_depth"] > 600
+    assert st["live"] == (mode.get("live") == 1) and st["dep"] == (mode.get("dep") == 1)
+    assert ref["max_depth"] > 300
     assert (st["nodes"], st["fails"], st["solutions"], st["best"], st["max_depth"]) == \
         (ref["nodes"], ref["fails"], ref["solutions"], ref["best"], ref["max_depth"])
 
