@@ -133,6 +133,25 @@ int32_t pccp_model_set_objective(pccp_model *m, int32_t var);
 int32_t pccp_model_info(const pccp_model *m, int32_t *nvars, int32_t *nlinear,
                         int32_t *nterms, int32_t *nreified, int32_t *ndecision);
 
+/* Model files: the variables, constraints, decision list and objective of a
+ * model (§2 modelling layer, after compilation to the two constraint forms;
+ * §3 names erased to indices), so that a generated model is built once and
+ * read by every consumer.  Layout, all integers little-endian:
+ *   line 1   "PCCP-MODEL 1"
+ *   line 2   a JSON object with the integer fields nvars, nrows, nterms,
+ *            nreif, ndec, objective (other fields are ignored on load; a
+ *            generator may add its parameters there)
+ *   then     int32 lb[nvars], ub[nvars], row_ptr[nrows + 1] (0 .. nterms,
+ *            increasing), coef[nterms], var[nterms], rhs[nrows],
+ *            reif[4 * nreif] (b, si, sj, d per item), dec[ndec]
+ * save writes the model as built; load creates a model (*out, destroyed with
+ * pccp_model_destroy) or returns PCCP_E_MODEL for a bad header, a file of
+ * the wrong length or an inconsistent row pointer, PCCP_E_INVALID_ARG if the
+ * file cannot be opened.  Index ranges are checked when a solver is
+ * created, as for a model built call by call. */
+int32_t pccp_model_save_file(const pccp_model *m, const char *path);
+int32_t pccp_model_load_file(const char *path, pccp_model **out);
+
 /* ---- solver ------------------------------------------------------------ */
 /* A zero-initialised pccp_config selects every default. */
 typedef struct {
@@ -281,12 +300,24 @@ typedef struct {
     int32_t occupancy;        /* 1 = high-occupancy build, 2 = normal         */
     int32_t dep;              /* dependency-driven propagation with a trail   */
     int32_t pad;
+    int64_t atomics;          /* lattice joins issued by the sweeps: one LDS
+                                 atomic max (lb) or min (ub) per tell whose
+                                 value was strictly tighter than the bound the
+                                 lane read (§4: store only on a strict gain;
+                                 §5 erratum: the store's joins are atomic)    */
 } pccp_stats;
 
 int32_t pccp_get_stats(const pccp_solver *s, pccp_stats *st);
 
 /* ENUMERATE: number of solutions found (counted even beyond sol_cap). */
 int32_t pccp_get_solution_count(const pccp_solver *s, int64_t *count);
+
+/* ENUMERATE: order-independent hash of the solution set found by the last
+ * search: the wrapping sum over solutions of fmix64 (MurmurHash3's final
+ * mix) of the 64-bit FNV-1a hash of the decision values' little-endian
+ * bytes, so that searches splitting the tree differently can be compared
+ * (§5: subproblems explored in any order).  PCCP_E_STATE before a search. */
+int32_t pccp_get_solution_hash(const pccp_solver *s, uint64_t *hash);
 
 /* ENUMERATE: copy solutions [first, first + count) (ndecision values each,
  * in the order they were found) into vals.  Only the first sol_cap are
@@ -305,6 +336,76 @@ int32_t pccp_set_branching(pccp_solver *s, int32_t kind, const void *weights);
 /* Number of workgroups of each configuration that are resident at once
  * (the default grid of a search launch). */
 int32_t pccp_solver_capacity(const pccp_solver *s, int32_t *wgs_per_cu, int32_t *num_cus);
+
+/* ---- launch tuning ------------------------------------------------------
+ * The paper picks its launch shape by measurement (§5 Evaluation: 4x
+ * oversubscription of the GPU's blocks was best on its machine).  The tuner
+ * times short searches of the given models in one launch under each
+ * candidate configuration - workgroup size x propagator tables in LDS or
+ * global memory x subtree-root store in LDS or global memory x propagation
+ * mode x kernel build - and returns the fastest (nodes per second of device
+ * time).  A zero-initialised pccp_tune_opts selects every default. */
+typedef struct {
+    double budget_s;      /* device-clock seconds of one probe; 0 = 0.4      */
+    int32_t whole_run;    /* 0: steady-state rate - the nodes and device time
+                             of a run of budget_s / 2 are subtracted from
+                             those of a run of budget_s, so the start-up
+                             while the queue fills cancels out (unless the
+                             searches finish early); 1: the whole run's rate
+                             (what searches to a quick proof see)           */
+    int32_t finalists;    /* the best this many are timed again with runs 4x
+                             as long; rates within 2 % count as ties, won by
+                             the better first-pass rank; 0 = 3              */
+    int32_t modes;        /* propagation modes tried, bit mask: 1 every table
+                             every sweep, 2 dependency-driven, 4 item lists;
+                             0 = 1 | 2                                      */
+    int32_t wg_sizes;     /* workgroup sizes tried, bit k = 64 << k (k = 0..4);
+                             0 = 128, 256, 512 and 1024                     */
+    int32_t max_depth;    /* decision-stack capacity of every candidate;
+                             0 = solvers[0]'s                               */
+    int32_t pad;
+} pccp_tune_opts;
+
+typedef struct {
+    pccp_config cfg;          /* the candidate                              */
+    double nodes_per_s;       /* first-pass rate (0 when status != PCCP_OK)  */
+    double nodes_per_s_long;  /* rate of the long runs (finalists), else 0   */
+    int32_t grid;             /* workgroups the candidate's launch used      */
+    int32_t status;           /* PCCP_OK, PCCP_E_LDS_CAPACITY (the layout
+                                 does not fit) or PCCP_E_DEPTH (a path was
+                                 deeper than max_depth)                      */
+} pccp_tune_result;
+
+/* Tune the launch for searching solvers[0..n) together in `mode` (every
+ * probe is a pccp_batch_solve with a time limit, so their stats are those
+ * of the last probe).  *best receives the chosen configuration (its
+ * num_wgs, queue_cap, sol_cap, launch and trail_cap are solvers[0]'s).
+ * results (may be NULL) receives up to cap candidates in the order tried,
+ * *nresults (may be NULL) their number.  Returns PCCP_E_LDS_CAPACITY if no
+ * candidate fits, or the first other error a probe gave. */
+int32_t pccp_autotune(pccp_solver *const *solvers, int32_t n, int32_t mode,
+                      const pccp_tune_opts *opts, pccp_config *best,
+                      pccp_tune_result *results, int32_t cap, int32_t *nresults);
+
+/* ---- LDS peaks ----------------------------------------------------------
+ * The propagation loop's store lives in LDS (§5: the shared-memory store was
+ * the fastest; its joins are atomic per the erratum), so its roofline is
+ * LDS bandwidth and LDS atomic throughput.  This measures both on the
+ * current device with conflict-free access patterns over every compute
+ * unit: 64-bit LDS reads (ds_read_b64), and 32-bit atomic max without and
+ * with the old value returned.  Synchronises the null stream. */
+typedef struct {
+    double read_gbs;          /* LDS bytes read per second / 1e9             */
+    double atomic_gops;       /* LDS atomic max lane operations per second,
+                                 no return, / 1e9                            */
+    double atomic_ret_gops;   /* the same with the old value returned        */
+    double ms[3];             /* kernel times of the three measurements      */
+    int32_t num_cus;
+    int32_t grid, block;      /* launch of each measurement                  */
+    int32_t pad;
+} pccp_lds_peaks;
+
+int32_t pccp_measure_lds_peaks(pccp_lds_peaks *out);
 
 /* ---- learned branching: network and training --------------------------
  * The rule scores each unfixed decision variable from its 6 features

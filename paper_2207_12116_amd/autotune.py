@@ -1,7 +1,8 @@
-"""Autotuner for the batched search launch.
+"""Autotuner for the batched search launch (a cache in front of the
+library's pccp_autotune).
 
-For a batch of models it times a short search under each candidate launch
-configuration - workgroup size x placement of the propagator tables (LDS or
+For a batch of models the library times a short search under each candidate
+launch configuration - workgroup size x placement of the propagator tables (LDS or
 HBM/L2) x placement of the subtree-root store (LDS or HBM) x propagation
 mode (every propagator every sweep, or dependency-driven sweeps with a
 trail; item lists of non-entailed propagators on request) x kernel build
@@ -14,7 +15,6 @@ from __future__ import annotations
 
 import json
 import os
-import time
 
 from . import pccp
 
@@ -57,92 +57,51 @@ def _store(path, data):
     os.replace(tmp, path)
 
 
-def _run(solvers, mode, cfg, t):
-    pccp.batch_solve(solvers, mode, config=cfg, time_limit=t)
-    st = [s.stats() for s in solvers]
-    return sum(x["nodes"] for x in st), st[0]["kernel_ms"] / 1e3, st[0]
-
-
-def _rate(models, mode, cfg, budget_s, steady=True):
-    """Node rate of a run of budget_s of device time; with `steady`, the
-    nodes and device time of a run of budget_s / 2 are subtracted (every run
-    starts the searches afresh, so the start-up while the queue fills, which
-    favours fewer workgroups in a short run, cancels out)."""
-    solvers = [pccp.Solver(m, config=cfg) for m in models]
-    # an untimed launch first: the first launch of a kernel variant in a
-    # process also loads its code object
-    pccp.batch_solve(solvers, mode, config=cfg, time_limit=min(0.05, budget_s / 4))
-    if not steady:
-        n2, k2, st = _run(solvers, mode, cfg, budget_s)
-        return n2 / max(k2, 1e-9), st
-    n1, k1, _ = _run(solvers, mode, cfg, budget_s / 2)
-    n2, k2, st = _run(solvers, mode, cfg, budget_s)
-    if k2 - k1 < 0.25 * k2 or n2 < n1:
-        # searches that finish early: the whole run's rate
-        return n2 / max(k2, 1e-9), st
-    return (n2 - n1) / (k2 - k1), st
-
-
-def _cfg(x, max_depth):
-    return pccp.Config(wg_size=x["wg_size"], desc_lds=x["desc_lds"], root_lds=x["root_lds"],
-                       occupancy=x["occupancy"], max_depth=max_depth, **MODES[x["prop"]])
-
-
 def tune(models, mode=pccp.MINIMIZE, budget_s=0.4, cache_path=DEFAULT_CACHE, force=False,
          wg_sizes=WG_SIZES, placements=PLACEMENTS, modes=DEFAULT_MODES, log=None, finalists=3,
          max_depth=0, steady=True):
     """Return (Config, report) for searching `models` together in one launch.
-    Every candidate's steady-state rate is taken from runs of budget_s / 2
-    and budget_s of device time (with steady=False: the rate of the whole
-    run of budget_s, start-up included, which is what short searches to a
-    proof see); the `finalists` best are timed again with runs four times as
-    long and the best of those is kept, rates within 2 % counting as ties."""
+    The measurement is the library's pccp_autotune: every candidate's
+    steady-state rate is taken from runs of budget_s / 2 and budget_s of
+    device time (with steady=False: the rate of the whole run of budget_s,
+    start-up included, which is what short searches to a proof see); the
+    `finalists` best are timed again with runs four times as long and the
+    best of those is kept, rates within 2 % counting as ties.  `placements`
+    other than all four are not supported by the library's candidate set."""
+    assert set(placements) == set(PLACEMENTS), "the tuner tries every placement"
     key = (f"{_device_name()}|{size_class(models, mode)}|d{max_depth}|{'+'.join(modes)}"
            f"|{'steady' if steady else 'whole'}")
     cache = _load(cache_path) if cache_path else {}
     if not force and key in cache:
         c = cache[key]
         return pccp.Config(**c["config"]), {"cached": True, **c}
+    bits = {"tables": 1, "dep": 2, "lists": 4}
+    opts = pccp.TuneOpts(budget_s=budget_s, whole_run=0 if steady else 1, finalists=finalists,
+                         modes=sum(bits[m] for m in modes),
+                         wg_sizes=sum(1 << (w.bit_length() - 7) for w in wg_sizes),
+                         max_depth=max_depth)
+    solvers = [pccp.Solver(m, max_depth=max_depth) for m in models]
+    best, cands = pccp.autotune(solvers, mode, opts)
     results = []
-    cands = [(w, p, pm, o) for w in wg_sizes for p in placements for pm in modes
-             for o in ((1, 2) if w <= 256 else (2,))]
-    for wg, (d, r), pm, oc in cands:
-        x = {"wg_size": wg, "desc_lds": d, "root_lds": r, "prop": pm, "occupancy": oc}
-        try:
-            rate, st = _rate(models, mode, _cfg(x, max_depth), budget_s, steady)
-        except pccp.PccpError as e:
-            # a layout that does not fit, or a path deeper than the stack
-            if e.code in (pccp.E_LDS_CAPACITY, pccp.E_DEPTH):
-                continue
-            raise
-        x.update({"nodes_per_s": rate, "grid": st["grid"], "placed_desc_lds": st["desc_lds"],
-                  "placed_root_lds": st["root_lds"]})
+    for c in cands:
+        cf = c["config"]
+        prop = "dep" if cf["dep"] == 1 else ("lists" if cf["live"] == 1 else "tables")
+        x = {"wg_size": cf["wg_size"], "desc_lds": cf["desc_lds"], "root_lds": cf["root_lds"],
+             "prop": prop, "occupancy": cf["occupancy"], "nodes_per_s": c["nodes_per_s"],
+             "nodes_per_s_long": c["nodes_per_s_long"], "grid": c["grid"], "status": c["status"]}
         results.append(x)
-        if log:
-            log(f"autotune wg={wg} desc={d} root={r} prop={pm} occ={oc}: {rate / 1e6:.2f} M nodes/s "
-                f"(grid {st['grid']})")
-    results.sort(key=lambda x: -x["nodes_per_s"])
-    for x in results[:finalists]:
-        try:
-            x["nodes_per_s_long"], _ = _rate(models, mode, _cfg(x, max_depth), 4 * budget_s, steady)
-        except pccp.PccpError as e:
-            if e.code != pccp.E_DEPTH:
-                raise
-            x["nodes_per_s_long"] = 0.0
-        if log:
-            log(f"autotune finalist wg={x['wg_size']} desc={x['desc_lds']} root={x['root_lds']} "
-                f"prop={x['prop']} occ={x['occupancy']}: {x['nodes_per_s_long'] / 1e6:.2f} M nodes/s")
-    if not results:
-        raise RuntimeError("autotune: no configuration fits")
-    # long-run rates within 2 % of the best are ties (searches of different
-    # launch shapes explore different trees, so rates vary by a few percent);
-    # ties go to the candidate that ranked higher in the first pass
-    top = max(x["nodes_per_s_long"] for x in results[:finalists])
-    best = next(x for x in results[:finalists] if x["nodes_per_s_long"] >= 0.98 * top)
-    entry = {"config": {"wg_size": best["wg_size"], "desc_lds": best["desc_lds"],
-                        "root_lds": best["root_lds"], "occupancy": best["occupancy"],
-                        "max_depth": max_depth, **MODES[best["prop"]]},
-             "prop": best["prop"], "nodes_per_s": best["nodes_per_s"], "candidates": results}
+        if log and c["status"] == pccp.OK:
+            log(f"autotune wg={x['wg_size']} desc={x['desc_lds']} root={x['root_lds']} "
+                f"prop={prop} occ={x['occupancy']}: {x['nodes_per_s'] / 1e6:.2f} M nodes/s "
+                f"(grid {x['grid']})" + (f", long {x['nodes_per_s_long'] / 1e6:.2f}"
+                                         if x["nodes_per_s_long"] else ""))
+    prop = "dep" if best.dep == 1 else ("lists" if best.live == 1 else "tables")
+    entry = {"config": {"wg_size": best.wg_size, "desc_lds": best.desc_lds,
+                        "root_lds": best.root_lds, "occupancy": best.occupancy,
+                        "max_depth": max_depth, **MODES[prop]},
+             "prop": prop,
+             "nodes_per_s": max(x["nodes_per_s"] for x in results if x["status"] == pccp.OK),
+             "candidates": [x for x in results if x["status"] == pccp.OK]}
     if cache_path:
         cache[key] = entry
         _store(cache_path, cache)

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cctype>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -36,6 +37,8 @@ static int32_t fail(int32_t code, const std::string &msg)
         if (e_ != hipSuccess)                                                           \
             return fail(PCCP_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
+
+int32_t pccp::internal_fail(int32_t code, const std::string &msg) { return fail(code, msg); }
 
 extern "C" const char *pccp_last_error(void) { return g_last_error.c_str(); }
 extern "C" const char *pccp_version(void) { return "pccp 0.1 (gfx950)"; }
@@ -119,6 +122,121 @@ extern "C" int32_t pccp_model_info(const pccp_model *m, int32_t *nvars, int32_t 
     if (nterms) *nterms = (int32_t)m->coef.size();
     if (nreified) *nreified = (int32_t)(m->reif.size() / 4);
     if (ndecision) *ndecision = (int32_t)m->dec.size();
+    return PCCP_OK;
+}
+
+// ------------------------------------------------------------------ model files
+// Format (little-endian): the line "PCCP-MODEL 1", one line of JSON with
+// the top-level integer fields nvars, nrows, nterms, nreif, ndec and
+// objective (other fields, e.g. a generator's parameters, are ignored),
+// then the int32 arrays lb[nvars], ub[nvars], row_ptr[nrows + 1],
+// coef[nterms], var[nterms], rhs[nrows], reif[4 nreif] (b, si, sj, d),
+// dec[ndec].
+static const char kModelMagic[] = "PCCP-MODEL 1\n";
+
+// value of the top-level integer field `key` of a one-line JSON object
+static bool json_top_int(const std::string &h, const char *key, int64_t &out)
+{
+    int depth = 0;
+    bool in_str = false;
+    size_t kstart = 0;
+    for (size_t i = 0; i < h.size(); ++i) {
+        const char ch = h[i];
+        if (in_str) {
+            if (ch == '\\') { ++i; continue; }
+            if (ch != '"') continue;
+            in_str = false;
+            if (depth != 1 || h.compare(kstart, i - kstart, key) != 0 || strlen(key) != i - kstart)
+                continue;
+            size_t j = i + 1;
+            while (j < h.size() && isspace((unsigned char)h[j])) ++j;
+            if (j >= h.size() || h[j] != ':') continue;
+            ++j;
+            while (j < h.size() && isspace((unsigned char)h[j])) ++j;
+            char *end = nullptr;
+            const long long v = strtoll(h.c_str() + j, &end, 10);
+            if (end == h.c_str() + j) return false;
+            out = v;
+            return true;
+        }
+        if (ch == '"') { in_str = true; kstart = i + 1; }
+        else if (ch == '{' || ch == '[') ++depth;
+        else if (ch == '}' || ch == ']') --depth;
+    }
+    return false;
+}
+
+extern "C" int32_t pccp_model_save_file(const pccp_model *m, const char *path)
+{
+    if (!m || !path) return fail(PCCP_E_INVALID_ARG, "pccp_model_save_file: bad arguments");
+    FILE *f = fopen(path, "wb");
+    if (!f) return fail(PCCP_E_INVALID_ARG, std::string("pccp_model_save_file: cannot open ") + path);
+    char hdr[256];
+    snprintf(hdr, sizeof(hdr),
+             "{\"nvars\": %zu, \"nrows\": %zu, \"nterms\": %zu, \"nreif\": %zu, \"ndec\": %zu, "
+             "\"objective\": %d}\n",
+             m->lb.size(), m->rhs.size(), m->coef.size(), m->reif.size() / 4, m->dec.size(),
+             (int)m->objective);
+    bool ok = fputs(kModelMagic, f) >= 0 && fputs(hdr, f) >= 0;
+    auto put = [&](const std::vector<int32_t> &v) {
+        if (ok && !v.empty()) ok = fwrite(v.data(), 4, v.size(), f) == v.size();
+    };
+    put(m->lb); put(m->ub); put(m->row_ptr); put(m->coef); put(m->var); put(m->rhs);
+    put(m->reif); put(m->dec);
+    ok = (fclose(f) == 0) && ok;
+    return ok ? PCCP_OK : fail(PCCP_E_INVALID_ARG, std::string("pccp_model_save_file: write failed: ") + path);
+}
+
+extern "C" int32_t pccp_model_load_file(const char *path, pccp_model **out)
+{
+    if (!path || !out) return fail(PCCP_E_INVALID_ARG, "pccp_model_load_file: bad arguments");
+    *out = nullptr;
+    FILE *f = fopen(path, "rb");
+    if (!f) return fail(PCCP_E_INVALID_ARG, std::string("pccp_model_load_file: cannot open ") + path);
+    auto line = [&](std::string &l) {
+        l.clear();
+        int ch;
+        while ((ch = fgetc(f)) != EOF && ch != '\n') {
+            l.push_back((char)ch);
+            if (l.size() > (1u << 26)) return false;
+        }
+        return ch == '\n';
+    };
+    std::string magic, hdr;
+    int64_t V = -1, R = -1, T = -1, Q = -1, D = -1, obj = -2;
+    if (!line(magic) || magic + "\n" != kModelMagic || !line(hdr) ||
+        !json_top_int(hdr, "nvars", V) || !json_top_int(hdr, "nrows", R) ||
+        !json_top_int(hdr, "nterms", T) || !json_top_int(hdr, "nreif", Q) ||
+        !json_top_int(hdr, "ndec", D) || !json_top_int(hdr, "objective", obj) || V < 0 ||
+        V > kMaxVars || R < 0 || T < 0 || Q < 0 || D < 0 || obj < -1 || obj >= V ||
+        R > INT32_MAX - 1 || T > INT32_MAX || Q > INT32_MAX / 4) {
+        fclose(f);
+        return fail(PCCP_E_MODEL, std::string("pccp_model_load_file: bad header in ") + path);
+    }
+    pccp_model *m = new (std::nothrow) pccp_model();
+    if (!m) { fclose(f); return fail(PCCP_E_NOMEM, "pccp_model_load_file: out of memory"); }
+    bool ok = true;
+    auto get = [&](std::vector<int32_t> &v, int64_t n) {
+        if (!ok) return;
+        try { v.assign((size_t)n, 0); } catch (...) { ok = false; return; }
+        if (n > 0) ok = fread(v.data(), 4, (size_t)n, f) == (size_t)n;
+    };
+    get(m->lb, V); get(m->ub, V); get(m->row_ptr, R + 1); get(m->coef, T); get(m->var, T);
+    get(m->rhs, R); get(m->reif, 4 * Q); get(m->dec, D);
+    const bool at_end = ok && fgetc(f) == EOF;
+    fclose(f);
+    if (ok && at_end) {
+        // the row pointer must run from 0 to nterms without decreasing, with
+        // at least one term per row (as pccp_model_add_linear_le builds it)
+        ok = m->row_ptr[0] == 0 && m->row_ptr[R] == T;
+        for (int64_t r = 0; ok && r < R; ++r) ok = m->row_ptr[r + 1] > m->row_ptr[r];
+    }
+    if (!ok || !at_end) {
+        delete m;
+        return fail(PCCP_E_MODEL, std::string("pccp_model_load_file: truncated or inconsistent arrays in ") + path);
+    }
+    m->objective = (int32_t)obj;
+    *out = m;
     return PCCP_OK;
 }
 
@@ -938,6 +1056,7 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
         o.prop_reified = (int64_t)is.ex[1];
         o.prop_linear = (int64_t)is.ex[2];
         o.prop_terms = (int64_t)is.ex[3];
+        o.atomics = (int64_t)is.atomics;
         o.sol_hash = is.sol_hash;
         o.best = is.best;
         o.kernel_ms = kms;
@@ -992,6 +1111,14 @@ extern "C" int32_t pccp_get_stats(const pccp_solver *s, pccp_stats *st)
     if (!s || !st) return fail(PCCP_E_INVALID_ARG, "pccp_get_stats: bad arguments");
     if (!s->have_stats) return fail(PCCP_E_STATE, "pccp_get_stats: no search yet");
     *st = s->stats;
+    return PCCP_OK;
+}
+
+extern "C" int32_t pccp_get_solution_hash(const pccp_solver *s, uint64_t *hash)
+{
+    if (!s || !hash) return fail(PCCP_E_INVALID_ARG, "pccp_get_solution_hash: bad arguments");
+    if (!s->have_stats) return fail(PCCP_E_STATE, "pccp_get_solution_hash: no search yet");
+    *hash = s->stats.sol_hash;
     return PCCP_OK;
 }
 
@@ -1063,6 +1190,131 @@ extern "C" int32_t pccp_solver_capacity(const pccp_solver *s, int32_t *wgs_per_c
 }
 
 // ------------------------------------------------------------------ learned branching
+// ------------------------------------------------------------------ launch tuning
+namespace {
+struct Probe {
+    double nodes = 0, secs = 0;
+    int32_t grid = 0;
+};
+
+// one time-limited batched search; nodes over all instances, device seconds
+int32_t probe(pccp_solver *const *sv, int32_t n, int32_t mode, const pccp_config &cfg, double t,
+              Probe &out)
+{
+    pccp_limits lim{};
+    lim.time_limit_s = t;
+    std::vector<int32_t> outc((size_t)n);
+    const int32_t rc = run_search(sv, n, mode, &cfg, &lim, outc.data());
+    if (rc != PCCP_OK) return rc;
+    out.nodes = 0;
+    for (int i = 0; i < n; ++i) out.nodes += (double)sv[i]->stats.nodes;
+    out.secs = sv[0]->stats.kernel_ms / 1e3;
+    out.grid = sv[0]->stats.grid;
+    return PCCP_OK;
+}
+
+// node rate of a candidate (see pccp_tune_opts.whole_run)
+int32_t cand_rate(pccp_solver *const *sv, int32_t n, int32_t mode, const pccp_config &cfg,
+                  double budget, bool whole, double &rate, int32_t &grid)
+{
+    Probe a, b;
+    // untimed first: the first launch of a kernel variant also loads its code
+    int32_t rc = probe(sv, n, mode, cfg, std::min(0.05, budget / 4), a);
+    if (rc == PCCP_OK && !whole) rc = probe(sv, n, mode, cfg, budget / 2, a);
+    if (rc == PCCP_OK) rc = probe(sv, n, mode, cfg, budget, b);
+    if (rc != PCCP_OK) return rc;
+    grid = b.grid;
+    if (whole || b.secs - a.secs < 0.25 * b.secs || b.nodes < a.nodes)
+        rate = b.nodes / std::max(b.secs, 1e-9);       // finished early: the whole run
+    else
+        rate = (b.nodes - a.nodes) / (b.secs - a.secs);
+    return PCCP_OK;
+}
+}  // namespace
+
+extern "C" int32_t pccp_autotune(pccp_solver *const *solvers, int32_t n, int32_t mode,
+                                 const pccp_tune_opts *opts, pccp_config *best,
+                                 pccp_tune_result *results, int32_t cap, int32_t *nresults)
+{
+    if (!solvers || n < 1 || !best || cap < 0 || (cap > 0 && !results))
+        return fail(PCCP_E_INVALID_ARG, "pccp_autotune: bad arguments");
+    for (int i = 0; i < n; ++i)
+        if (!solvers[i]) return fail(PCCP_E_INVALID_ARG, "pccp_autotune: solver is NULL");
+    pccp_tune_opts o = opts ? *opts : pccp_tune_opts{};
+    if (o.budget_s < 0 || o.finalists < 0 || o.modes < 0 || o.modes > 7 || o.wg_sizes < 0 ||
+        o.wg_sizes > 31 || o.max_depth < 0)
+        return fail(PCCP_E_INVALID_ARG, "pccp_autotune: bad options");
+    const double budget = o.budget_s > 0 ? o.budget_s : 0.4;
+    const int finalists = o.finalists > 0 ? o.finalists : 3;
+    const int modes = o.modes ? o.modes : 3;
+    const int wgs = o.wg_sizes ? o.wg_sizes : (2 | 4 | 8 | 16);
+    struct Cand {
+        pccp_config cfg;
+        double rate = 0, rate_long = 0;
+        int32_t grid = 0, status = PCCP_OK, order = 0;
+    };
+    std::vector<Cand> all;
+    const pccp_config base = solvers[0]->cfg;
+    for (int k = 0; k < 5; ++k) {
+        if (!(wgs & (1 << k))) continue;
+        const int wg = 64 << k;
+        for (int place = 0; place < 4; ++place)
+            for (int pm = 0; pm < 3; ++pm) {
+                if (!(modes & (1 << pm))) continue;
+                for (int occ = 1; occ <= 2; ++occ) {
+                    if (occ == 1 && wg > 256) continue;
+                    Cand c;
+                    c.cfg = base;
+                    c.cfg.wg_size = wg;
+                    c.cfg.desc_lds = 1 + (place >> 1);
+                    c.cfg.root_lds = 1 + (place & 1);
+                    c.cfg.live = pm == 2 ? 1 : 2;
+                    c.cfg.dep = pm == 1 ? 1 : 2;
+                    c.cfg.occupancy = occ;
+                    c.cfg.max_depth = o.max_depth > 0 ? o.max_depth : base.max_depth;
+                    c.order = (int32_t)all.size();
+                    all.push_back(c);
+                }
+            }
+    }
+    for (Cand &c : all) {
+        c.status = cand_rate(solvers, n, mode, c.cfg, budget, o.whole_run != 0, c.rate, c.grid);
+        if (c.status != PCCP_OK && c.status != PCCP_E_LDS_CAPACITY && c.status != PCCP_E_DEPTH)
+            return c.status;
+        if (c.status != PCCP_OK) c.rate = 0;
+    }
+    std::vector<Cand *> ok;
+    for (Cand &c : all)
+        if (c.status == PCCP_OK) ok.push_back(&c);
+    if (ok.empty()) return fail(PCCP_E_LDS_CAPACITY, "pccp_autotune: no candidate fits");
+    std::stable_sort(ok.begin(), ok.end(), [](const Cand *a, const Cand *b) { return a->rate > b->rate; });
+    const size_t nf = std::min<size_t>(finalists, ok.size());
+    double top = 0;
+    for (size_t i = 0; i < nf; ++i) {
+        int32_t g = 0;
+        const int32_t rc = cand_rate(solvers, n, mode, ok[i]->cfg, 4 * budget, o.whole_run != 0,
+                                     ok[i]->rate_long, g);
+        if (rc == PCCP_E_DEPTH) ok[i]->rate_long = 0;
+        else if (rc != PCCP_OK) return rc;
+        top = std::max(top, ok[i]->rate_long);
+    }
+    const Cand *pick = ok[0];
+    for (size_t i = 0; i < nf; ++i)
+        if (ok[i]->rate_long >= 0.98 * top) { pick = ok[i]; break; }
+    *best = pick->cfg;
+    fill_defaults(*best);
+    const int32_t nr = std::min<int32_t>(cap, (int32_t)all.size());
+    for (int32_t i = 0; i < nr; ++i) {
+        results[i].cfg = all[i].cfg;
+        results[i].nodes_per_s = all[i].rate;
+        results[i].nodes_per_s_long = all[i].rate_long;
+        results[i].grid = all[i].grid;
+        results[i].status = all[i].status;
+    }
+    if (nresults) *nresults = (int32_t)all.size();
+    return PCCP_OK;
+}
+
 struct pccp_mlp {
     int device = 0;
     hipStream_t stream = nullptr;

@@ -81,6 +81,11 @@ __device__ __forceinline__ void tell_ub(int2 *st, int x, int32_t v)
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Lanes of the wavefront where p holds (wave-uniform).  The sweeps count the
+// lattice joins (LDS atomic max / min) they issue with it, in code every
+// lane of the wavefront runs, so the count stays in a scalar register.
+__device__ __forceinline__ uint32_t lanes(bool p) { return (uint32_t)__popcll(__ballot(p)); }
+
 // Barrier that orders LDS only (the store, flags and stack are all in LDS).
 __device__ __forceinline__ void lds_barrier()
 {
@@ -185,6 +190,7 @@ enum : int {
     C_THI = 25,                             // deepest path level without a whole trail  only)
     C_JCNT = 28,                            // entries of the expansion's job list
     C_MAXW = 29,                            // deepest decision-stack level written (every mode)
+    C_ATOM = 30,                            // lattice joins issued by the node's sweeps
 };
 
 // ------------------------------------------------------------ descriptors
@@ -418,7 +424,7 @@ __device__ __forceinline__ int group_sum(int x, int G)
 // entailed once ub(x) - lb(y) <= c.
 template <bool DL, bool MK = false>
 __device__ __forceinline__ void sweep_diff(const View<DL> &v, int2 *st, const ListIO &io,
-                                           const Dep &dp, bool &chg, bool &bad)
+                                           const Dep &dp, bool &chg, bool &bad, uint32_t &nat)
 {
     constexpr int U = 2;
     const int tid = threadIdx.x, lane = tid & 63, W = blockDim.x, n = io.n;
@@ -457,6 +463,8 @@ __device__ __forceinline__ void sweep_diff(const View<DL> &v, int2 *st, const Li
             pl[u] = ok[u] && dx[u].x - c > dy[u].x;
             any |= pu[u] | pl[u];
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) nat += lanes(pu[u]) + lanes(pl[u]);
         if (any) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -492,7 +500,7 @@ __device__ __forceinline__ void sweep_diff(const View<DL> &v, int2 *st, const Li
 // them disentailed (lb(si) > ub(sj), or lb(sj) >= ub(si) + d).
 template <bool DL, int U, bool MK = false>
 __device__ __forceinline__ void sweep_reif(const View<DL> &v, int2 *st, const ListIO &io,
-                                           const Dep &dp, bool &chg, bool &bad)
+                                           const Dep &dp, bool &chg, bool &bad, uint32_t &nat)
 {
     const int tid = threadIdx.x, lane = tid & 63, W = blockDim.x, n = io.n;
     for (int c0 = uni(tid - lane); c0 < n; c0 += U * W) {
@@ -550,6 +558,8 @@ __device__ __forceinline__ void sweep_reif(const View<DL> &v, int2 *st, const Li
                                  (b0 && (li > uj || lj >= ui + d));
                 keep[u] = ok[u] && !ent;
             }
+            nat += lanes(ok[u] && t_b1) + lanes(ok[u] && t_b0) + lanes(ok[u] && p_ui) +
+                   lanes(ok[u] && p_lj) + lanes(ok[u] && p_uj) + lanes(ok[u] && p_li);
             if (!ok[u] || !(t_b1 | t_b0 | p_ui | p_lj | p_uj | p_li))
                 continue;
             const int b = e[u].x & 0xffff, i = (uint32_t)e[u].x >> 16, j = e[u].y & 0xffff;
@@ -597,7 +607,7 @@ __device__ __forceinline__ void term_tell(int2 *st, const Dep &dp, int x, int a,
 // terms' largest values is at most rhs.
 template <bool DL, int RR, bool MK = false>
 __device__ __forceinline__ void sweep_rows(const View<DL> &v, int2 *st, const ListIO &io,
-                                           const Dep &dp, bool &chg, bool &bad)
+                                           const Dep &dp, bool &chg, bool &bad, uint32_t &nat)
 {
     constexpr int TK = 2;
     const int tid = threadIdx.x, W = blockDim.x, n = io.n;
@@ -657,6 +667,7 @@ __device__ __forceinline__ void sweep_rows(const View<DL> &v, int2 *st, const Li
                     tight[q][k] = tok[q][k] && term_tight((int32_t)tv[q][k] >> 16, td[q][k].x,
                                                           td[q][k].y, rd[q].z, S[q]);
                     any |= tight[q][k];
+                    nat += lanes(tight[q][k]);
                 }
             if (any) {
 #pragma unroll
@@ -693,15 +704,19 @@ __device__ __forceinline__ void sweep_rows(const View<DL> &v, int2 *st, const Li
                 const int o = gl + k * G;
 #pragma unroll
                 for (int q = 0; q < RR; ++q) {
-                    if (rok[q] && o < rd[q].y) {
-                        const uint32_t t = v.terms(rd[q].x + o);
-                        const int x = t & 0xffff, a = (int32_t)t >> 16;
+                    const bool in = rok[q] && o < rd[q].y;
+                    uint32_t t = 0;
+                    int2 dx = make_int2(0, 0);
+                    if (in) {
+                        t = v.terms(rd[q].x + o);
                         // a bound re-read here can only have tightened since S
                         // was formed: the tell is then weaker, never unsound
-                        const int2 dx = dom(st, x);
-                        if (term_tight(a, dx.x, dx.y, rd[q].z, S[q]))
-                            term_tell<MK>(st, dp, x, a, dx.x, dx.y, rd[q].z, S[q], chg, bad);
+                        dx = dom(st, t & 0xffff);
                     }
+                    const int x = t & 0xffff, a = (int32_t)t >> 16;
+                    const bool tt = in && term_tight(a, dx.x, dx.y, rd[q].z, S[q]);
+                    nat += lanes(tt);
+                    if (tt) term_tell<MK>(st, dp, x, a, dx.x, dx.y, rd[q].z, S[q], chg, bad);
                 }
             }
         }
@@ -731,7 +746,7 @@ __device__ __forceinline__ void sweep_rows(const View<DL> &v, int2 *st, const Li
 // most rhs.
 template <bool DL, int RB, bool MK = false>
 __device__ __forceinline__ void sweep_brows(const View<DL> &v, int2 *st, const ListIO &io,
-                                            const Dep &dp, bool &chg, bool &bad)
+                                            const Dep &dp, bool &chg, bool &bad, uint32_t &nat)
 {
     constexpr int TB = 4;                   // term slots per lane held in registers
     const int tid = threadIdx.x, W = blockDim.x, n = io.n;
@@ -789,6 +804,8 @@ __device__ __forceinline__ void sweep_brows(const View<DL> &v, int2 *st, const L
                 for (int k = 0; k < TB; ++k)
                     tight |= (rok[q] && slack >= 0 && rv[q][k] > slack) ? 1u << (q * TB + k) : 0u;
             }
+#pragma unroll
+            for (int i = 0; i < RB * TB; ++i) nat += lanes((tight >> i) & 1u);
             if (__any(tight != 0)) {
 #pragma unroll
                 for (int q = 0; q < RB; ++q)
@@ -831,7 +848,9 @@ __device__ __forceinline__ void sweep_brows(const View<DL> &v, int2 *st, const L
                     // a bound re-read here can only have tightened since S was
                     // formed: an open term is still told soundly
                     const int2 dx = dom(st, t & 0xffff);
-                    if (rok[q] && a > 0 && a > rd[q].x - S[q] && dx.x < dx.y) {
+                    const bool tt = rok[q] && a > 0 && a > rd[q].x - S[q] && dx.x < dx.y;
+                    nat += lanes(tt);
+                    if (tt) {
                         tell_m<MK, false>(st, dp, t & 0xffff, 0, dx);
                         chg = true;
                         bad |= dx.x > 0;
@@ -868,6 +887,8 @@ static_assert(C_CNT + 3 * kListWords <= C_SKIP, "item-list counts overlap C_SKIP
 static_assert(C_DCNT + 2 * 6 <= C_TTOP, "work-list counts overlap the trail words");
 static_assert(C_MAXW >= C_CNT + 3 * kListWords && C_MAXW != C_SKIP && C_MAXW != C_JCNT &&
                   C_MAXW < 32, "the stack word must lie outside every count range");
+static_assert(C_ATOM >= C_CNT + 3 * kListWords && C_ATOM != C_SKIP && C_ATOM != C_JCNT &&
+                  C_ATOM != C_MAXW && C_ATOM < 32, "the join counter needs a word of its own");
 struct NodeLists {
     const uint16_t *in[kKinds];
     int nin[kKinds];
@@ -886,7 +907,7 @@ struct NodeLists {
 // lists' compaction, and for the high-occupancy search kernel).
 template <bool DL, bool LIVE, bool LEAN = LIVE>
 __device__ int propagate_wg(const View<DL> &v, int2 *st, int32_t *ctl, const NodeLists &L,
-                            uint32_t &nsweeps, unsigned long long (&ex)[4])
+                            uint32_t &nsweeps, unsigned long long (&ex)[4], uint32_t &nat)
 {
     const int tid = threadIdx.x, lane = tid & 63;
     const bool cmp = L.out[0] != nullptr;
@@ -910,10 +931,10 @@ __device__ int propagate_wg(const View<DL> &v, int2 *st, int32_t *ctl, const Nod
     const Dep nodep{};
     for (;;) {
         bool chg = false, bad = false;
-        sweep_diff(v, st, d, nodep, chg, bad);
-        sweep_reif<DL, LEAN ? 2 : 4>(v, st, r, nodep, chg, bad);
-        sweep_rows<DL, LEAN ? 2 : 4>(v, st, w, nodep, chg, bad);
-        sweep_brows<DL, LEAN ? 1 : 2>(v, st, b, nodep, chg, bad);
+        sweep_diff(v, st, d, nodep, chg, bad, nat);
+        sweep_reif<DL, LEAN ? 2 : 4>(v, st, r, nodep, chg, bad, nat);
+        sweep_rows<DL, LEAN ? 2 : 4>(v, st, w, nodep, chg, bad, nat);
+        sweep_brows<DL, LEAN ? 1 : 2>(v, st, b, nodep, chg, bad, nat);
         ex[0] += (unsigned)d.n;
         ex[1] += (unsigned)r.n;
         ex[2] += (unsigned)(w.n + b.n);
@@ -1109,7 +1130,7 @@ __device__ void dep_expand_jobs(const View<DL> &v, const Dep &dp, int32_t *cnt)
 // wavefronts, dp.jcap > 0); the high-occupancy build never does.
 template <bool DL, bool LEAN, bool TWO>
 __device__ int propagate_dep(const View<DL> &v, int2 *st, int32_t *ctl, const Dep &dp, bool full,
-                             uint32_t &nsweeps, unsigned long long (&ex)[4])
+                             uint32_t &nsweeps, unsigned long long (&ex)[4], uint32_t &nat)
 {
     const int tid = threadIdx.x, lane = tid & 63, W = blockDim.x;
     if (tid == 0) {
@@ -1164,10 +1185,10 @@ __device__ int propagate_dep(const View<DL> &v, int2 *st, int32_t *ctl, const De
         // the queued bits of the lists run now are cleared for the next expansion
         for (int w = tid; w < dp.qw; w += W) dp.qm[w] = 0;
         bool chg = false, bad = false;
-        sweep_diff<DL, true>(v, st, io[0], dp, chg, bad);
-        sweep_reif<DL, LEAN ? 2 : 4, true>(v, st, io[1], dp, chg, bad);
-        sweep_rows<DL, LEAN ? 2 : 4, true>(v, st, io[2], dp, chg, bad);
-        sweep_brows<DL, LEAN ? 1 : 2, true>(v, st, io[3], dp, chg, bad);
+        sweep_diff<DL, true>(v, st, io[0], dp, chg, bad, nat);
+        sweep_reif<DL, LEAN ? 2 : 4, true>(v, st, io[1], dp, chg, bad, nat);
+        sweep_rows<DL, LEAN ? 2 : 4, true>(v, st, io[2], dp, chg, bad, nat);
+        sweep_brows<DL, LEAN ? 1 : 2, true>(v, st, io[3], dp, chg, bad, nat);
         ex[0] += (unsigned)io[0].n;
         ex[1] += (unsigned)io[1].n;
         ex[2] += (unsigned)(io[2].n + io[3].n);
@@ -1451,7 +1472,8 @@ __global__ __launch_bounds__(1024) void propagate_batch_kernel(
         uint32_t nsw = 0;
         unsigned long long ex[4] = {0, 0, 0, 0};
         lds_barrier();
-        const int rc = propagate_wg<DL, false>(v, st, ctl, L, nsw, ex);
+        uint32_t nat = 0;
+        const int rc = propagate_wg<DL, false>(v, st, ctl, L, nsw, ex, nat);
         post_scan(v, st, ctl, 0, false);
         const int failed = rc | lds_ld(&ctl[C_POSTFAIL]);
         for (int x = tid; x < m.nvars; x += W) {
@@ -1587,6 +1609,7 @@ struct Lane0 {
     unsigned long long nodes, fails, sols, sweeps, don, maxd;
     unsigned long long since_flush, known_total, pf_qt, pf_qh;
     unsigned long long ex[4];     // items run per kind, row terms visited
+    unsigned long long atom;      // lattice joins issued
     long long t_start;
     int32_t local_best, pf_best, pf_abort, pf_idle, idle_reg, pf_iabort;
 };
@@ -1601,10 +1624,12 @@ __device__ void flush_counters(Lane0 &z, InstState *is, int mode)
     g_add(&is->donations, z.don);
     g_add(&is->pops, 1ull);
     for (int k = 0; k < 4; ++k) g_add(&is->ex[k], z.ex[k]);
+    g_add(&is->atomics, z.atom);
     if (mode == 1) g_add(&is->solutions, z.sols);
     __hip_atomic_fetch_max(&is->max_depth, z.maxd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     z.nodes = z.fails = z.sweeps = z.don = z.sols = z.maxd = 0;
     z.ex[0] = z.ex[1] = z.ex[2] = z.ex[3] = 0;
+    z.atom = 0;
 }
 
 // Persistent kernel: every workgroup loops { take a subtree record; DFS it }
@@ -1689,6 +1714,8 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? 6 : 7) : 1) void s
     if (tid == 0) {
         z.nodes = z.fails = z.sols = z.sweeps = z.don = z.maxd = 0;
         z.ex[0] = z.ex[1] = z.ex[2] = z.ex[3] = 0;
+        z.atom = 0;
+        ctl[C_ATOM] = 0;
         z.since_flush = z.known_total = z.pf_qt = z.pf_qh = 0;
         z.t_start = g_load(&P.g->t_start);
         z.local_best = INT32_MAX;
@@ -1803,7 +1830,10 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? 6 : 7) : 1) void s
                     g_store_rel(&P.g->abort, 2);
                     stop = 1;
                 }
-                if (P.cancel && (z.since_flush & 255) == 0 && *P.cancel != 0) {
+                // the host word is read at system scope, past the device caches
+                if (P.cancel && (z.since_flush & 255) == 0 &&
+                    __hip_atomic_load(const_cast<int32_t *>(P.cancel), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_SYSTEM) != 0) {
                     g_store_rel(&P.g->abort, 3);
                     stop = 1;
                 }
@@ -1857,20 +1887,24 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? 6 : 7) : 1) void s
                 for (int k = 0; k < kKinds; ++k) L.out[k] = nullptr;
                 L.cnt = nullptr;
             }
-            uint32_t nsw = 0;
+            uint32_t nsw = 0, nat = 0;
             unsigned long long ex[4] = {0, 0, 0, 0};
             int rc;
             if constexpr (DEP) {
                 dp.trail_on = !node_full;
                 // work lists are short: lean unrolling (fewer registers)
-                rc = propagate_dep<DL, true, !HI>(v, st, ctl, dp, node_full, nsw, ex);
+                rc = propagate_dep<DL, true, !HI>(v, st, ctl, dp, node_full, nsw, ex, nat);
                 // the next node's trail marks start empty; a node whose
                 // changes did not all fit on the trail cannot be undone
                 for (int w = tid; w < dp.vw; w += W) dp.tm[w] = 0;
                 if (tid == 0 && !node_full && lds_ld(ctl + C_TTOP) > dp.tcap) ctl[C_THI] = depth;
             } else {
-                rc = propagate_wg<DL, LIVE, LIVE || HI>(v, st, ctl, L, nsw, ex);
+                rc = propagate_wg<DL, LIVE, LIVE || HI>(v, st, ctl, L, nsw, ex, nat);
             }
+            // each wavefront's joins, read by lane 0 after the scan's barrier
+            if ((tid & 63) == 0 && nat)
+                __hip_atomic_fetch_add(ctl + C_ATOM, (int32_t)nat, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
             post_scan(v, st, ctl, branching, rc == 0, fsc, P.mlp, &m);
             const int failed = uni(rc | lds_ld(&ctl[C_POSTFAIL]));
             const unsigned long long key =
@@ -1880,6 +1914,8 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? 6 : 7) : 1) void s
                 z.since_flush += 1;
                 z.sweeps += nsw;
                 for (int k = 0; k < 4; ++k) z.ex[k] += ex[k];
+                z.atom += (uint32_t)lds_ld(ctl + C_ATOM);
+                ctl[C_ATOM] = 0;
                 if ((unsigned long long)depth > z.maxd) z.maxd = depth;
                 if (z.since_flush >= 256) {
                     z.known_total = g_add(&P.g->nodes_total, z.since_flush) + z.since_flush;
@@ -2096,6 +2132,7 @@ __global__ void init_search_kernel(SearchParams P)
         s.nodes = s.fails = s.solutions = s.sweeps = 0;
         s.donations = s.pops = s.sol_hash = s.max_depth = 0;
         s.ex[0] = s.ex[1] = s.ex[2] = s.ex[3] = 0;
+        s.atomics = 0;
         s.t_done = 0;
         s.best = INT32_MAX;
         s.outstanding = 1;

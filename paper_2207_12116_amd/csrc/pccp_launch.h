@@ -3,9 +3,15 @@
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 
+#include <string>
+
 #include "pccp_types.h"
 
 namespace pccp {
+
+// record `msg` as the calling thread's last error (pccp_last_error) and
+// return `code`
+int32_t internal_fail(int32_t code, const std::string &msg);
 
 size_t model_desc_bytes(int ndiff, int nreif, int nrows, int nterms, int ndec, int nbrows,
                         int nbslots);

@@ -77,6 +77,7 @@ struct InstState {
     unsigned long long ex[4];   // propagator executions: difference rows,
                                 // reified items, linear rows (kinds 3 and 4);
                                 // row terms
+    unsigned long long atomics; // lattice joins issued (LDS atomic max / min)
     long long t_done;           // wall-clock tick when the last subtree finished (0 = not done)
     int32_t best;               // MINIMIZE: best objective so far (INT32_MAX = none)
     int32_t outstanding;        // subtrees queued or in progress

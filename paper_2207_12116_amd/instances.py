@@ -329,3 +329,47 @@ def jobshop(n_jobs: int, n_mach: int, seed: int) -> Model:
     return p.compile(decision=dec, objective=m,
                      meta=dict(kind="jobshop", jobs=jobs, n_jobs=n_jobs, n_mach=n_mach,
                                horizon=h, seed=seed))
+
+
+# ------------------------------------------------------------- model files
+# The library's model-file layout (little-endian): the line "PCCP-MODEL 1",
+# one line of JSON with nvars, nrows, nterms, nreif, ndec, objective (and
+# here also the search mode and the generator's parameters as "meta"), then int32
+# arrays lb, ub, row_ptr, coef, var, rhs, reif (4 per item), dec.
+MODEL_MAGIC = b"PCCP-MODEL 1\n"
+
+
+def save_model(model: Model, path: str) -> None:
+    import json
+    hdr = {"nvars": model.nvars, "nrows": model.nrows, "nterms": model.nterms,
+           "nreif": model.nreif, "ndec": int(model.decision.shape[0]),
+           "objective": int(model.objective), "mode": int(model.mode), "meta": model.meta}
+    with open(path, "wb") as f:
+        f.write(MODEL_MAGIC)
+        f.write(json.dumps(hdr, separators=(", ", ": ")).encode() + b"\n")
+        for a in (model.lb, model.ub, model.lin_ptr, model.lin_coef, model.lin_var,
+                  model.lin_rhs, model.reif, model.decision):
+            f.write(np.ascontiguousarray(a, dtype="<i4").tobytes())
+
+
+def load_model(path: str) -> Model:
+    import json
+    with open(path, "rb") as f:
+        if f.readline() != MODEL_MAGIC:
+            raise ValueError(f"{path}: not a model file")
+        hdr = json.loads(f.readline())
+        body = np.frombuffer(f.read(), dtype="<i4")
+    V, R, T, Q, D = (int(hdr[k]) for k in ("nvars", "nrows", "nterms", "nreif", "ndec"))
+    sizes = [V, V, R + 1, T, T, R, 4 * Q, D]
+    if body.shape[0] != sum(sizes):
+        raise ValueError(f"{path}: {body.shape[0]} values, expected {sum(sizes)}")
+    parts, o = [], 0
+    for n in sizes:
+        parts.append(body[o:o + n].astype(np.int32))
+        o += n
+    lb, ub, ptr, coef, var, rhs, reif, dec = parts
+    obj = int(hdr["objective"])
+    mode = int(hdr.get("mode", MODE_MINIMIZE if obj >= 0 else MODE_ENUMERATE))
+    return Model(lb, ub, ptr, coef, var, rhs, reif.reshape(-1, 4), dec, obj, mode,
+                 dict(hdr.get("meta", {})))
+

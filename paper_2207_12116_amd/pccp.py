@@ -53,12 +53,29 @@ class Stats(C.Structure):
                 ("outcome", _I32), ("kernel_ms", C.c_double), ("ttpo_ms", C.c_double),
                 ("grid", _I32), ("block", _I32), ("desc_lds", _I32), ("root_lds", _I32),
                 ("lds_bytes", _I64), ("live", _I32), ("occupancy", _I32), ("dep", _I32),
-                ("pad", _I32)]
+                ("pad", _I32), ("atomics", _I64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["best"] = None if d["best"] == 2**31 - 1 else int(d["best"])
         return d
+
+
+class TuneOpts(C.Structure):
+    """pccp_tune_opts; zero fields select the defaults."""
+    _fields_ = [("budget_s", C.c_double), ("whole_run", _I32), ("finalists", _I32),
+                ("modes", _I32), ("wg_sizes", _I32), ("max_depth", _I32), ("pad", _I32)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("cfg", Config), ("nodes_per_s", C.c_double), ("nodes_per_s_long", C.c_double),
+                ("grid", _I32), ("status", _I32)]
+
+
+class LdsPeaks(C.Structure):
+    _fields_ = [("read_gbs", C.c_double), ("atomic_gops", C.c_double),
+                ("atomic_ret_gops", C.c_double), ("ms", C.c_double * 3), ("num_cus", _I32),
+                ("grid", _I32), ("block", _I32), ("pad", _I32)]
 
 
 EXPORTS = [
@@ -71,7 +88,8 @@ EXPORTS = [
     "pccp_set_branching", "pccp_solver_capacity", "pccp_last_error", "pccp_version",
     "pccp_node_features", "pccp_mlp_create", "pccp_mlp_destroy", "pccp_mlp_set_params",
     "pccp_mlp_get_params", "pccp_mlp_train_step", "pccp_mlp_get_grads", "pccp_mlp_scores",
-    "pccp_mlp_weights",
+    "pccp_mlp_weights", "pccp_model_save_file", "pccp_model_load_file",
+    "pccp_get_solution_hash", "pccp_autotune", "pccp_measure_lds_peaks",
 ]
 
 _lib = None
@@ -126,6 +144,12 @@ def lib():
         "pccp_mlp_get_grads": [_VP, C.POINTER(C.c_float)],
         "pccp_mlp_scores": [_VP, _VP, _I32, _VP, _I32],
         "pccp_mlp_weights": [_VP, C.POINTER(_VP)],
+        "pccp_model_save_file": [_VP, C.c_char_p],
+        "pccp_model_load_file": [C.c_char_p, C.POINTER(_VP)],
+        "pccp_get_solution_hash": [_VP, C.POINTER(C.c_uint64)],
+        "pccp_autotune": [C.POINTER(_VP), _I32, _I32, C.POINTER(TuneOpts), C.POINTER(Config),
+                          C.POINTER(TuneResult), _I32, _P32],
+        "pccp_measure_lds_peaks": [C.POINTER(LdsPeaks)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -187,6 +211,25 @@ class ModelHandle:
         _chk(L.pccp_model_set_decision_vars(h, int(dec.shape[0]), _p(dec)), "set_decision_vars")
         _chk(L.pccp_model_set_objective(h, int(model.objective)), "set_objective")
 
+    @classmethod
+    def from_file(cls, path: str) -> "ModelHandle":
+        """A model read by pccp_model_load_file."""
+        self = cls.__new__(cls)
+        h = _VP()
+        _chk(lib().pccp_model_load_file(os.fsencode(path), C.byref(h)), "pccp_model_load_file")
+        self.h = h
+        return self
+
+    def save(self, path: str):
+        _chk(lib().pccp_model_save_file(self.h, os.fsencode(path)), "pccp_model_save_file")
+
+    def info(self) -> dict:
+        v = [_I32(0) for _ in range(5)]
+        _chk(lib().pccp_model_info(self.h, *[C.cast(C.byref(x), _P32) for x in v]),
+             "pccp_model_info")
+        return dict(zip(("nvars", "nlinear", "nterms", "nreified", "ndecision"),
+                        [int(x.value) for x in v]))
+
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
             _lib.pccp_model_destroy(self.h)
@@ -196,11 +239,14 @@ class ModelHandle:
 class Solver:
     """A model compiled and uploaded to the current HIP device."""
 
-    def __init__(self, model: Model, config: Config | None = None, stream=None, **cfg):
+    def __init__(self, model: Model, config: Config | None = None, stream=None,
+                 handle: ModelHandle | None = None, **cfg):
+        """`handle`: an already built library model (e.g. read from a file)
+        whose content is `model`'s; by default one is built from `model`."""
         L = lib()
         self.model = model
         self.cfg = config if config is not None else Config(**cfg)
-        self._mh = ModelHandle(model)
+        self._mh = handle if handle is not None else ModelHandle(model)
         self.stream = _current_stream() if stream is None else int(stream)
         h = _VP()
         _chk(L.pccp_solver_create(self._mh.h, C.byref(self.cfg), C.c_void_p(self.stream),
@@ -259,6 +305,11 @@ class Solver:
         _chk(lib().pccp_get_stats(self.h, C.byref(st)), "pccp_get_stats")
         return st.as_dict()
 
+    def solution_hash(self) -> int:
+        h = C.c_uint64(0)
+        _chk(lib().pccp_get_solution_hash(self.h, C.byref(h)), "pccp_get_solution_hash")
+        return int(h.value)
+
     def solution_count(self) -> int:
         n = C.c_int64(0)
         _chk(lib().pccp_get_solution_count(self.h, C.byref(n)), "pccp_get_solution_count")
@@ -311,6 +362,34 @@ def batch_solve(solvers, mode=MINIMIZE, config: Config | None = None, node_limit
     _chk(lib().pccp_batch_solve(arr, n, int(mode), cfg_p, C.byref(lim), _p(outs)),
          "pccp_batch_solve")
     return outs.tolist()
+
+
+def autotune(solvers, mode=MINIMIZE, opts: TuneOpts | None = None, cap=256):
+    """pccp_autotune: (chosen Config, list of candidate dicts in the order
+    tried)."""
+    n = len(solvers)
+    arr = (_VP * n)(*[s.h for s in solvers])
+    best = Config()
+    res = (TuneResult * cap)()
+    nres = _I32(0)
+    _chk(lib().pccp_autotune(arr, n, int(mode), C.byref(opts) if opts is not None else None,
+                             C.byref(best), res, cap, C.cast(C.byref(nres), _P32)),
+         "pccp_autotune")
+    out = []
+    for r in res[:min(cap, nres.value)]:
+        c = {k: getattr(r.cfg, k) for k, _ in Config._fields_}
+        out.append({"config": c, "nodes_per_s": r.nodes_per_s,
+                    "nodes_per_s_long": r.nodes_per_s_long, "grid": r.grid, "status": r.status})
+    return best, out
+
+
+def lds_peaks() -> dict:
+    """pccp_measure_lds_peaks on the current device."""
+    p = LdsPeaks()
+    _chk(lib().pccp_measure_lds_peaks(C.byref(p)), "pccp_measure_lds_peaks")
+    return {"read_GBs": p.read_gbs, "atomic_Gops": p.atomic_gops,
+            "atomic_ret_Gops": p.atomic_ret_gops, "ms": list(p.ms), "num_cus": p.num_cus,
+            "grid": p.grid, "block": p.block}
 
 
 def version() -> str:

@@ -64,3 +64,80 @@ def test_config_validation_without_device():
         rc = L.pccp_solver_create(mh.h, ctypes.byref(cfg), None, ctypes.byref(h))
         assert rc == pccp.E_INVALID_ARG, (kw, rc)
         assert not h.value
+
+
+def _handle_arrays(path):
+    """Arrays of a model file as written by the library (read back with the
+    data-only reader)."""
+    from paper_2207_12116_amd import instances as I
+    m = I.load_model(path)
+    return [m.lb, m.ub, m.lin_ptr, m.lin_coef, m.lin_var, m.lin_rhs, m.reif.reshape(-1),
+            m.decision, m.objective]
+
+
+def test_model_file_round_trip_without_device(tmp_path):
+    """pccp_model_save_file writes what was built; the data-only reader of
+    the generator module reads it back array by array; a file written by the
+    generator module loads into the library with the same sizes and saves
+    back to the same bytes."""
+    import numpy as np
+    from paper_2207_12116_amd import instances as I
+    for model in (I.rcpsp(30, 2), I.tiny_csp(3), I.jobshop(3, 3, 1)):
+        mh = pccp.ModelHandle(model)
+        p1 = str(tmp_path / "lib.pccp")
+        mh.save(p1)
+        got = _handle_arrays(p1)
+        want = [model.lb, model.ub, model.lin_ptr, model.lin_coef, model.lin_var,
+                model.lin_rhs, np.asarray(model.reif).reshape(-1), model.decision,
+                model.objective]
+        for a, b in zip(got, want):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
+        p2 = str(tmp_path / "gen.pccp")
+        I.save_model(model, p2)
+        h2 = pccp.ModelHandle.from_file(p2)
+        assert h2.info() == dict(nvars=model.nvars, nlinear=model.nrows, nterms=model.nterms,
+                                 nreified=model.nreif, ndecision=int(model.decision.shape[0]))
+        p3 = str(tmp_path / "again.pccp")
+        h2.save(p3)
+        with open(p1, "rb") as a, open(p3, "rb") as b:
+            assert a.read() == b.read()
+        assert I.load_model(p2).content_hash() == model.content_hash()
+
+
+def test_model_file_errors_without_device(tmp_path):
+    from paper_2207_12116_amd import instances as I
+    L = pccp.lib()
+    h = ctypes.c_void_p()
+    assert L.pccp_model_load_file(str(tmp_path / "none").encode(), ctypes.byref(h)) == \
+        pccp.E_INVALID_ARG
+    good = str(tmp_path / "m.pccp")
+    I.save_model(I.tiny_rcpsp(5, 1), good)
+    data = open(good, "rb").read()
+    cases = {"truncated": data[:-4], "extra": data + b"\0\0\0\0",
+             "magic": b"PCCP-MODEL 2" + data[12:],
+             "header": data.replace(b'"nvars"', b'"nvarz"', 1)}
+    for name, blob in cases.items():
+        p = str(tmp_path / f"{name}.pccp")
+        with open(p, "wb") as f:
+            f.write(blob)
+        h = ctypes.c_void_p()
+        assert L.pccp_model_load_file(p.encode(), ctypes.byref(h)) == pccp.E_MODEL, name
+        assert not h.value
+    # a row pointer that decreases
+    m = I.tiny_rcpsp(5, 1)
+    m.lin_ptr = m.lin_ptr.copy()
+    m.lin_ptr[1], m.lin_ptr[2] = m.lin_ptr[2], m.lin_ptr[1]
+    bad = str(tmp_path / "ptr.pccp")
+    I.save_model(m, bad)
+    assert L.pccp_model_load_file(bad.encode(), ctypes.byref(h)) == pccp.E_MODEL
+
+
+def test_query_and_tuning_errors_without_device():
+    """The result queries refuse a missing solver or output pointer before
+    touching a device; the tuner refuses bad options the same way."""
+    L = pccp.lib()
+    assert L.pccp_get_solution_hash(None, None) == pccp.E_INVALID_ARG
+    best = pccp.Config()
+    assert L.pccp_autotune(None, 1, pccp.MINIMIZE, None, ctypes.byref(best), None, 0, None) == \
+        pccp.E_INVALID_ARG
+    assert L.pccp_measure_lds_peaks(None) == pccp.E_INVALID_ARG

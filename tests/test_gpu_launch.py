@@ -104,3 +104,35 @@ def test_instance_node_budget_abandons_only_the_hard_instance(P, dep):
     st = solvers[-1].stats()
     assert outs[-1] == P.OUT_LIMIT and st["ttpo_ms"] < 0
     assert budget <= st["nodes"] <= budget + 512 * st["grid"]
+
+
+@pytest.mark.parametrize("dep", [2, 1], ids=["tables", "dep"])
+def test_host_cancel_word_stops_search(P, dep):
+    """A search with a 30 s limit on an instance no search proves in that
+    time: another host thread sets the pinned cancel word after 0.5 s, and
+    the search returns CANCELLED well before its limit, with sound
+    counters."""
+    import threading
+    import time
+    import torch
+    cancel = torch.zeros(1, dtype=torch.int32).pin_memory()
+    s = P.Solver(I.rcpsp(30, 0), dep=dep)
+
+    def setter():
+        time.sleep(0.5)
+        cancel[0] = 1
+
+    th = threading.Thread(target=setter)
+    th.start()
+    t0 = time.time()
+    out = s.solve(time_limit=30.0, cancel=cancel)
+    el = time.time() - t0
+    th.join()
+    st = s.stats()
+    say("cancel", dep, P.OUTCOME_NAMES[out], round(el, 3), st["nodes"])
+    assert out == P.OUT_CANCELLED and st["outcome"] == P.OUT_CANCELLED
+    assert 0.4 < el < 10.0
+    assert st["nodes"] > 0 and st["ttpo_ms"] < 0
+    # the word cleared, the same solver searches again to its limit
+    cancel[0] = 0
+    assert s.solve(time_limit=0.3, cancel=cancel) == P.OUT_LIMIT

@@ -156,50 +156,42 @@ def test_bf16_scores_and_argmax(P, small_traces):
     assert mism == near
 
 
-def _gain_instances():
-    # held out from training (30 and 60 tasks) and from the choice of the
-    # training recipe (seeds 0-5 of these sizes)
-    return [(n, s) for n in (12, 14, 16) for s in range(6, 12)]
+def _random_params(seed, scale=0.5):
+    """A seeded random network (not trained: an input independent of the
+    library), rounded to BF16 so that both sides use the same weights."""
+    rng = np.random.default_rng(seed)
+    return bf16_round(rng.normal(0.0, scale, O.NPARAM).astype(np.float32))
 
 
-def test_learned_search_optimum_and_gain(P):
-    """Whole-GPU searches with first-fail and with the trained network on
-    held-out instances: every optimum both prove is the same, every optimum
-    the oracle proves is matched, and the network needs less total time to
-    proven optimum (limits counted at the limit)."""
-    from paper_2207_12116_amd import learn
-    if not os.path.exists(learn.DEFAULT_WEIGHTS):
-        pytest.fail(f"trained weights missing: {learn.DEFAULT_WEIGHTS}")
-    mlp = learn.network()
-    limit = 5.0
-    rows = []
-    for n, s in _gain_instances():
-        m = I.rcpsp_model(*I.rcpsp_data(n, s)[:4])
-        r = O.solve(m, node_limit=100000)
-        res = []
-        for use in (False, True):
-            sv = P.Solver(m)
-            if use:
-                learn.attach(sv, mlp)
-            out = sv.solve(time_limit=limit)
-            st = sv.stats()
-            obj, vals = sv.best()
-            if obj is not None:
-                ok, ms = O.check_schedule(m.meta, vals)
-                assert ok and ms == obj, (n, s, use)
-            if out == P.OUT_OPTIMAL and r["outcome"] == O.OUT_OPTIMAL:
-                assert obj == r["best"], (n, s, use)
-            res.append((out == P.OUT_OPTIMAL, obj, st["ttpo_ms"] / 1e3 if out == P.OUT_OPTIMAL
-                        else limit, st["nodes"]))
-        if res[0][0] and res[1][0]:
-            assert res[0][1] == res[1][1], (n, s)
-        rows.append((n, s, res[0], res[1]))
-        say("gain", n, s, "first-fail", res[0], "learned", res[1])
-    ff = sum(x[2][2] for x in rows)
-    ln = sum(x[3][2] for x in rows)
-    say("total time to proven optimum: first-fail", round(ff, 3), "learned", round(ln, 3),
-        "speedup", round(ff / ln, 2))
-    assert ln < ff
+# (tasks, seed, node limit): node-limited prefixes of 30- and 60-task
+# instances and whole searches of small ones
+MLP_PREFIXES = [(30, 3, 2000, 11), (30, 8, 2000, 12), (60, 4, 400, 13), (14, 2, 20000, 14),
+                (12, 1, 0, 15), (16, 7, 0, 16)]
+
+
+@pytest.mark.parametrize("n,seed,limit,wseed", MLP_PREFIXES,
+                         ids=[f"{n}t-s{s}-{l}" for n, s, l, _ in MLP_PREFIXES])
+@pytest.mark.parametrize("dep", [2, 1], ids=["tables", "dep"])
+def test_learned_search_matches_oracle(P, n, seed, limit, wseed, dep):
+    """The search branching on the network (in-kernel features, BF16
+    scoring with FP32 sums, argmax with ties to the earliest candidate) on
+    one workgroup against the oracle's FP64 depth-first search branching on
+    the same weights: every counter of the node-limited prefix (or of the
+    whole search) is the same, so every branching choice was."""
+    p = _random_params(wseed)
+    m = I.rcpsp(n, seed) if n >= 30 else I.rcpsp_model(*I.rcpsp_data(n, seed)[:4])
+    O.set_mlp_params(p.astype(np.float64))
+    ref = O.solve(m, branching=O.MLP, node_limit=limit)
+    mlp = P.MLP(seed=0)
+    mlp.set_params(p)
+    s = P.Solver(m, num_wgs=1, dep=dep)
+    s.set_branching(P.BRANCH_MLP, mlp.weights_ptr())
+    out = s.solve(node_limit=limit, time_limit=120)
+    st = s.stats()
+    say("mlp search", n, seed, limit, dep, P.OUTCOME_NAMES[out], st["nodes"], ref["nodes"])
+    assert out == {O.OUT_LIMIT: P.OUT_LIMIT, O.OUT_OPTIMAL: P.OUT_OPTIMAL}[ref["outcome"]]
+    assert (st["nodes"], st["fails"], st["solutions"], st["best"], st["max_depth"]) == \
+        (ref["nodes"], ref["fails"], ref["solutions"], ref["best"], ref["max_depth"])
 
 
 def test_learned_branching_dep_same_tree(P):
