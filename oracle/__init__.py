@@ -31,7 +31,9 @@ class _Model(C.Structure):
                 ("nrows", C.c_int32), ("row_ptr", _P32), ("coef", _P32),
                 ("var", _P32), ("rhs", _P32), ("nreif", C.c_int32),
                 ("reif", _P32), ("ndec", C.c_int32), ("dec", _P32),
-                ("objective", C.c_int32)]
+                ("objective", C.c_int32), ("ncmd", C.c_int32), ("cmd", _P32),
+                ("cmd_gptr", _P32), ("guard", _P32), ("cmd_tptr", _P32),
+                ("cterm", _P32)]
 
 
 class _Stats(C.Structure):
@@ -44,56 +46,71 @@ class _Stats(C.Structure):
 _lib = None
 
 
+def use_library(path):
+    """Load the oracle from `path` instead of LIB_PATH (the benchmark's
+    CPU baseline times a copy built with -march=native on its host)."""
+    global _lib
+    _lib = _load(path)
+    return _lib
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"oracle library not built: {LIB_PATH} "
                                "(run `python -m oracle.build`)")
-        L = C.CDLL(LIB_PATH)
-        MP = C.POINTER(_Model)
-        L.orc_validate.argtypes = [MP]
-        L.orc_validate.restype = C.c_int32
-        L.orc_propagate.argtypes = [MP, _P32, _P32, C.c_int32, C.c_uint64,
-                                    C.POINTER(C.c_int64)]
-        L.orc_propagate.restype = C.c_int32
-        L.orc_jacobi_step.argtypes = [MP, _P32, _P32]
-        L.orc_jacobi_step.restype = C.c_int32
-        L.orc_gs_step.argtypes = [MP, _P32, _P32]
-        L.orc_gs_step.restype = C.c_int32
-        L.orc_solve.argtypes = [MP, C.c_int32, C.c_int32, C.c_int64, _P32,
-                                C.c_int64, _P32, C.POINTER(_Stats)]
-        L.orc_solve.restype = C.c_int32
-        L.orc_solution_hash.argtypes = [_P32, C.c_int32]
-        L.orc_solution_hash.restype = C.c_uint64
-        L.orc_brute_points.argtypes = [MP, _P32, C.c_int64, C.POINTER(C.c_uint64)]
-        L.orc_brute_points.restype = C.c_int64
-        L.orc_brute_rcpsp.argtypes = [C.c_int32, _P32, C.c_int32, _P32, C.c_int32,
-                                      _P32, _P32, C.c_int32, _P32]
-        L.orc_brute_rcpsp.restype = C.c_int32
-        L.orc_check_schedule.argtypes = [C.c_int32, _P32, C.c_int32, _P32,
-                                         C.c_int32, _P32, _P32, _P32, _P32]
-        L.orc_check_schedule.restype = C.c_int32
-        PD = C.POINTER(C.c_double)
-        L.orc_features.argtypes = [MP, _P32, _P32, PD]
-        L.orc_features.restype = C.c_int32
-        L.orc_mlp_forward.argtypes = [PD, PD, C.c_int64, PD]
-        L.orc_mlp_forward.restype = C.c_int32
-        L.orc_mlp_loss_grad.argtypes = [PD, PD, _P32, PD, C.c_int32, PD, PD]
-        L.orc_mlp_loss_grad.restype = C.c_int32
-        L.orc_trace.argtypes = [MP, C.c_int32, C.c_int64, C.POINTER(C.c_float), PD, _P32,
-                                _P32, _P32, C.c_int64, C.c_int64, C.POINTER(C.c_int64)]
-        L.orc_trace.restype = C.c_int64
-        L.orc_set_mlp_params.argtypes = [PD]
-        L.orc_set_mlp_params.restype = None
-        L.orc_mlp_choice.argtypes = [MP, PD, _P32, _P32]
-        L.orc_mlp_choice.restype = C.c_int32
-        L.orc_floor_div.argtypes = [C.c_int64, C.c_int64]
-        L.orc_floor_div.restype = C.c_int64
-        L.orc_ceil_div.argtypes = [C.c_int64, C.c_int64]
-        L.orc_ceil_div.restype = C.c_int64
-        _lib = L
+        _lib = _load(LIB_PATH)
     return _lib
+
+
+def _load(path):
+    L = C.CDLL(path)
+    MP = C.POINTER(_Model)
+    L.orc_validate.argtypes = [MP]
+    L.orc_validate.restype = C.c_int32
+    L.orc_propagate.argtypes = [MP, _P32, _P32, C.c_int32, C.c_uint64,
+                                C.POINTER(C.c_int64)]
+    L.orc_propagate.restype = C.c_int32
+    L.orc_jacobi_step.argtypes = [MP, _P32, _P32]
+    L.orc_jacobi_step.restype = C.c_int32
+    L.orc_gs_step.argtypes = [MP, _P32, _P32]
+    L.orc_gs_step.restype = C.c_int32
+    L.orc_solve.argtypes = [MP, C.c_int32, C.c_int32, C.c_int64, _P32,
+                            C.c_int64, _P32, C.POINTER(_Stats)]
+    L.orc_solve.restype = C.c_int32
+    L.orc_solution_hash.argtypes = [_P32, C.c_int32]
+    L.orc_solution_hash.restype = C.c_uint64
+    L.orc_brute_points.argtypes = [MP, _P32, C.c_int64, C.POINTER(C.c_uint64)]
+    L.orc_brute_points.restype = C.c_int64
+    L.orc_brute_rcpsp.argtypes = [C.c_int32, _P32, C.c_int32, _P32, C.c_int32,
+                                  _P32, _P32, C.c_int32, _P32]
+    L.orc_brute_rcpsp.restype = C.c_int32
+    L.orc_check_schedule.argtypes = [C.c_int32, _P32, C.c_int32, _P32,
+                                     C.c_int32, _P32, _P32, _P32, _P32]
+    L.orc_check_schedule.restype = C.c_int32
+    PD = C.POINTER(C.c_double)
+    L.orc_features.argtypes = [MP, _P32, _P32, PD]
+    L.orc_features.restype = C.c_int32
+    L.orc_mlp_forward.argtypes = [PD, PD, C.c_int64, PD]
+    L.orc_mlp_forward.restype = C.c_int32
+    L.orc_mlp_loss_grad.argtypes = [PD, PD, _P32, PD, C.c_int32, PD, PD]
+    L.orc_mlp_loss_grad.restype = C.c_int32
+    L.orc_trace.argtypes = [MP, C.c_int32, C.c_int64, C.POINTER(C.c_float), PD, _P32,
+                            _P32, _P32, C.c_int64, C.c_int64, C.POINTER(C.c_int64)]
+    L.orc_trace.restype = C.c_int64
+    L.orc_set_mlp_params.argtypes = [PD]
+    L.orc_set_mlp_params.restype = None
+    L.orc_mlp_choice.argtypes = [MP, PD, _P32, _P32]
+    L.orc_mlp_choice.restype = C.c_int32
+    L.orc_floor_div.argtypes = [C.c_int64, C.c_int64]
+    L.orc_floor_div.restype = C.c_int64
+    L.orc_ceil_div.argtypes = [C.c_int64, C.c_int64]
+    L.orc_ceil_div.restype = C.c_int64
+    L.orc_solve_timed.argtypes = [C.POINTER(MP), C.c_int32, C.c_int32, C.c_int32, C.c_int64,
+                                  C.c_int32, C.POINTER(C.c_int64), PD, _P32, _P32, PD]
+    L.orc_solve_timed.restype = C.c_int32
+    return L
 
 
 def _i32(a) -> np.ndarray:
@@ -111,11 +128,16 @@ class OracleModel:
         self.model = model
         self._keep = [_i32(model.lb), _i32(model.ub), _i32(model.lin_ptr),
                       _i32(model.lin_coef), _i32(model.lin_var), _i32(model.lin_rhs),
-                      _i32(model.reif).reshape(-1), _i32(model.decision)]
-        lb, ub, ptr, coef, var, rhs, reif, dec = self._keep
+                      _i32(model.reif).reshape(-1), _i32(model.decision),
+                      _i32(model.cmd).reshape(-1), _i32(model.cmd_gptr),
+                      _i32(model.cmd_guard).reshape(-1), _i32(model.cmd_tptr),
+                      _i32(model.cmd_term).reshape(-1)]
+        lb, ub, ptr, coef, var, rhs, reif, dec, cmd, gptr, guard, tptr, cterm = self._keep
         self.s = _Model(model.nvars, _ptr(lb), _ptr(ub), model.nrows, _ptr(ptr),
                         _ptr(coef), _ptr(var), _ptr(rhs), model.nreif, _ptr(reif),
-                        int(dec.shape[0]), _ptr(dec), int(model.objective))
+                        int(dec.shape[0]), _ptr(dec), int(model.objective),
+                        model.ncmd, _ptr(cmd), _ptr(gptr), _ptr(guard), _ptr(tptr),
+                        _ptr(cterm))
 
     def ref(self):
         return C.byref(self.s)
@@ -186,6 +208,28 @@ def solve(model, mode=None, branching=FIRST_FAIL, node_limit=0, sol_cap=0):
                 outcome=int(st.outcome), sol_hash=int(st.sol_hash),
                 solutions_list=buf[:nsol, :nd].copy(),
                 best_assign=best[:nd].copy() if st.best != 2**31 - 1 else None)
+
+
+def solve_timed(models, threads, mode=MINIMIZE, branching=FIRST_FAIL, node_limit=0):
+    """orc_solve on independent instances, `threads` POSIX threads, timed in
+    C (CLOCK_MONOTONIC).  Returns dict(nodes, secs, outcome, best per
+    instance; wall_s for the set)."""
+    oms = [_om(m) for m in models]
+    n = len(oms)
+    arr = (C.POINTER(_Model) * max(n, 1))(*[C.pointer(o.s) for o in oms])
+    nodes = np.zeros(max(n, 1), dtype=np.int64)
+    secs = np.zeros(max(n, 1), dtype=np.float64)
+    out = np.zeros(max(n, 1), dtype=np.int32)
+    best = np.zeros(max(n, 1), dtype=np.int32)
+    wall = C.c_double(0.0)
+    rc = lib().orc_solve_timed(arr, n, int(mode), int(branching), int(node_limit), int(threads),
+                               nodes.ctypes.data_as(C.POINTER(C.c_int64)), _pd(secs), _ptr(out),
+                               _ptr(best), C.byref(wall))
+    if rc < 0:
+        raise ValueError(f"orc_solve_timed error {rc}")
+    return dict(nodes=nodes[:n].copy(), secs=secs[:n].copy(), outcome=out[:n].copy(),
+                best=[None if b == 2**31 - 1 else int(b) for b in best[:n]],
+                wall_s=float(wall.value))
 
 
 def solution_hash(vals) -> int:

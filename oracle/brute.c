@@ -11,7 +11,10 @@
  *    ((b >= 1) <=> (si <= sj and sj < si + d)).  Variables are assigned in
  *    index order; a partial assignment is abandoned only when a row cannot
  *    be satisfied whatever values the unassigned variables take in their
- *    boxes, so no solution is skipped.
+ *    boxes, so no solution is skipped.  Guarded commands are checked on
+ *    complete points only, as the constraint they state: when every guard
+ *    holds (y >= c, or y <= c), div * x >= k + sum a_t y_t for an lb tell,
+ *    div * x <= k + sum a_t y_t for an ub tell.
  *  - orc_brute_rcpsp: the RCPSP of §2 stated on raw data (durations,
  *    precedences, demands, capacities), independent of the Boolean
  *    decomposition: s_i + d_i <= s_j for each precedence, and at every
@@ -65,10 +68,29 @@ static int reif_holds(const int32_t *x, const int32_t *it)
     return (b >= 1) == psi;
 }
 
+static int cmd_holds(const orc_model *m, const int32_t *x, int32_t q)
+{
+    for (int32_t g = m->cmd_gptr[q]; g < m->cmd_gptr[q + 1]; ++g) {
+        const int32_t *gd = m->guard + 3 * (int64_t)g;
+        const int holds = gd[1] == 0 ? x[gd[0]] >= gd[2] : x[gd[0]] <= gd[2];
+        if (!holds)
+            return 1;          /* a guard is false: the command states nothing */
+    }
+    const int32_t *cm = m->cmd + 4 * (int64_t)q;
+    int64_t f = cm[2];
+    for (int32_t t = m->cmd_tptr[q]; t < m->cmd_tptr[q + 1]; ++t)
+        f += (int64_t)m->cterm[2 * (int64_t)t] * x[m->cterm[2 * (int64_t)t + 1]];
+    const int64_t lhs = (int64_t)cm[3] * x[cm[0]];
+    return cm[1] == 0 ? lhs >= f : lhs <= f;
+}
+
 static void brute_rec(bctx *c, int32_t k)
 {
     const orc_model *m = c->m;
     if (k == m->nvars) {
+        for (int32_t q = 0; q < m->ncmd; ++q)
+            if (!cmd_holds(m, c->x, q))
+                return;
         for (int32_t q = 0; q < m->ndec; ++q)
             c->vals[q] = c->x[m->dec[q]];
         if (c->out && c->count < c->cap)

@@ -1,4 +1,10 @@
-"""Compile the CPU oracle into oracle/liboracle.so (plain C, gcc)."""
+"""Compile the CPU oracle into oracle/liboracle.so (plain C, gcc).
+
+The library the tests load is built for the generic x86-64 target, so the
+copy that travels with the repository runs on any host.  The CPU baseline of
+the benchmark times a second copy built with -march=native on the host that
+runs it (build(native=True, out=...)); the sources are the same.
+"""
 from __future__ import annotations
 
 import os
@@ -6,14 +12,15 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["propagate.c", "search.c", "brute.c", "learn.c"]
+SOURCES = ["propagate.c", "search.c", "brute.c", "learn.c", "timing.c"]
 
 
-def build(verbose: bool = False) -> str:
-    out = os.path.join(HERE, "liboracle.so")
+def build(verbose: bool = False, native: bool = False, out: str | None = None) -> str:
+    out = out or os.path.join(HERE, "liboracle.so")
     tmp = out + ".tmp"
-    cmd = ["gcc", "-O3", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
-           "-o", tmp] + [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
+    cmd = ["gcc", "-O3"] + (["-march=native"] if native else []) + [
+        "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-pthread",
+        "-o", tmp] + [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

@@ -23,6 +23,11 @@
  *     of §2 extended to conjunction and negation, and disjunction propagated
  *     by the usual "one disjunct disentailed" rule (the paper gives no
  *     compilation of a disjunction or of negated entailment).
+ *   - Guarded command  {g_1..g_n} => x <- f(y_1..y_m) (§3, guarded normal
+ *     form; §2, ask and tell statements): when every guard is entailed,
+ *     join f into one bound of x.  Guards are entailment tests of a bound
+ *     against a constant; f is an affine form over the bounds that make it
+ *     monotone, divided and rounded toward the side that keeps it sound.
  *   - propagate: the least fixed point above a store (§3, Theorem 2), computed
  *     by the sequential composition of all guarded commands repeated until
  *     nothing changes (§3, Proposition 3: seq P has the same fixed point).
@@ -59,6 +64,20 @@ typedef struct {
     int32_t ndec;
     const int32_t *dec;                /* decision variables, tie-break order*/
     int32_t objective;                 /* -1 if none                          */
+    /* guarded commands (§3, guarded normal form):
+     *   {g_1, ..., g_n} => x <- f,  f = k + sum_t a_t * y_t,
+     * cmd: 4 per command: x, side (0: lb(x) >= ceil(f / div), 1: ub(x) <=
+     * floor(f / div)), k, div (> 0);  guards of command q:
+     * guard[3*g .. 3*g+2] for g in [cmd_gptr[q], cmd_gptr[q+1]): var, side
+     * (0: entailed(var >= c) = lb(var) >= c, 1: entailed(var <= c) =
+     * ub(var) <= c), c;  terms of command q: cterm[2*t], cterm[2*t+1] =
+     * a_t, y_t for t in [cmd_tptr[q], cmd_tptr[q+1]).                      */
+    int32_t ncmd;
+    const int32_t *cmd;
+    const int32_t *cmd_gptr;
+    const int32_t *guard;
+    const int32_t *cmd_tptr;
+    const int32_t *cterm;
 } orc_model;
 
 enum { ORC_FIXPOINT = 0, ORC_FAILED = 1 };
@@ -120,6 +139,16 @@ int32_t orc_solve(const orc_model *m, int32_t mode, int32_t branching,
 /* Hash of one solution (FNV-1a 64 over the little-endian bytes, finalised
  * by MurmurHash3's fmix64); the solution-set hash is the wrapping sum. */
 uint64_t orc_solution_hash(const int32_t *vals, int32_t n);
+
+/* Timing harness (timing.c): orc_solve on n independent instances, one
+ * POSIX thread per host core (threads), each taking the next instance.
+ * Per instance: nodes, seconds (CLOCK_MONOTONIC), outcome and best; wall_s
+ * is the whole set's time.  Returns 0, or the first negative error of
+ * orc_solve (the other instances still run). */
+int32_t orc_solve_timed(const orc_model *const *models, int32_t n, int32_t mode,
+                        int32_t branching, int64_t node_limit, int32_t threads,
+                        int64_t *nodes, double *secs, int32_t *outcome, int32_t *best,
+                        double *wall_s);
 
 /* ---- brute force (independent of the propagation code) ---------------- */
 

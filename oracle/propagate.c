@@ -3,8 +3,9 @@
  * ONLY (see oracle.h); never linked into the product.
  *
  * Every guarded command of the model is one of:
- *   - a term of a linear row  sum_t a_t x_t <= c  (the tell on x_t), or
- *   - one of the ten tells of a reified overlap item.
+ *   - a term of a linear row  sum_t a_t x_t <= c  (the tell on x_t),
+ *   - one of the ten tells of a reified overlap item, or
+ *   - a general guarded command of the model (its own propagator).
  * A propagator is one row or one reified item (§2, the function [[.]] maps a
  * constraint to a process).  The guarded normal form of §3 (gnf) flattens a
  * propagator into its commands; the commands are listed below in the order
@@ -175,6 +176,50 @@ static void run_reif(const orc_model *m, store_t *s, int32_t q)
 }
 
 /* ---------------------------------------------------------------------- */
+/* General guarded command  {g_1, ..., g_n} => x <- f  (§3: a command of the
+ * guarded normal form; §2: "if b then P" runs P once b is true, and the
+ * sugar "if e then P" first tells b <- e).  A guard is the entailment of a
+ * bound constraint: entailed(y >= c) = lb(y) >= c, entailed(y <= c) =
+ * ub(y) <= c (monotone by the lemma of §2 on partial orders as functions).
+ * The tell is the join of f = k + sum_t a_t * y_t into one bound of x, where
+ * every y_t is read through the bound that makes f move in the direction of
+ * the join as the store grows (§2: tells must be monotone):
+ *   lb tell: a_t > 0 reads lb(y_t), a_t < 0 reads ub(y_t); value ceil(f/div)
+ *   ub tell: a_t > 0 reads ub(y_t), a_t < 0 reads lb(y_t); value floor(f/div)
+ * Read as a constraint on points, the command says "if every guard holds,
+ * div * x >= k + sum a_t y_t" (lb tell) or "<=" (ub tell); the bound read
+ * through is the least (resp. greatest) value of the sum over the box, so
+ * the tell removes no point that satisfies it.                             */
+static int cmd_guards_hold(const orc_model *m, const store_t *s, int32_t q)
+{
+    for (int32_t g = m->cmd_gptr[q]; g < m->cmd_gptr[q + 1]; ++g) {
+        const int32_t *gd = m->guard + 3 * (int64_t)g;
+        if (gd[1] == 0 ? !(s->lb[gd[0]] >= gd[2]) : !(s->ub[gd[0]] <= gd[2]))
+            return 0;
+    }
+    return 1;
+}
+
+static void run_cmd(const orc_model *m, store_t *s, int32_t q)
+{
+    if (!cmd_guards_hold(m, s, q))
+        return;
+    const int32_t *c = m->cmd + 4 * (int64_t)q;
+    const int32_t x = c[0], side = c[1];
+    int64_t f = c[2];
+    for (int32_t t = m->cmd_tptr[q]; t < m->cmd_tptr[q + 1]; ++t) {
+        const int64_t a = m->cterm[2 * (int64_t)t];
+        const int32_t y = m->cterm[2 * (int64_t)t + 1];
+        const int use_lb = side == 0 ? a > 0 : a < 0;
+        f += a * (use_lb ? s->lb[y] : s->ub[y]);
+    }
+    if (side == 0)
+        tell_lb(s, x, ceil_div(f, c[3]));
+    else
+        tell_ub(s, x, floor_div(f, c[3]));
+}
+
+/* ---------------------------------------------------------------------- */
 int32_t orc_validate(const orc_model *m)
 {
     if (!m || m->nvars < 0 || m->nrows < 0 || m->nreif < 0 || m->ndec < 0)
@@ -186,6 +231,8 @@ int32_t orc_validate(const orc_model *m)
     if (m->nreif > 0 && !m->reif)
         return -1;
     if (m->ndec > 0 && !m->dec)
+        return -1;
+    if (m->ncmd < 0 || (m->ncmd > 0 && (!m->cmd || !m->cmd_gptr || !m->cmd_tptr)))
         return -1;
     if (m->objective < -1 || m->objective >= m->nvars)
         return -2;
@@ -232,6 +279,32 @@ int32_t orc_validate(const orc_model *m)
         if (2 * maxabs_all + llabs((int64_t)it[3]) + 1 >= LIM)
             return -3;
     }
+    if (m->ncmd > 0 && (m->cmd_gptr[0] != 0 || m->cmd_tptr[0] != 0))
+        return -2;
+    for (int32_t q = 0; q < m->ncmd; ++q) {
+        const int32_t *c = m->cmd + 4 * (int64_t)q;
+        if (c[0] < 0 || c[0] >= m->nvars || (c[1] != 0 && c[1] != 1) || c[3] <= 0)
+            return -2;
+        const int32_t g0 = m->cmd_gptr[q], g1 = m->cmd_gptr[q + 1];
+        const int32_t t0 = m->cmd_tptr[q], t1 = m->cmd_tptr[q + 1];
+        if (g1 < g0 || t1 < t0 || (g1 > g0 && !m->guard) || (t1 > t0 && !m->cterm))
+            return -2;
+        for (int32_t g = g0; g < g1; ++g) {
+            const int32_t *gd = m->guard + 3 * (int64_t)g;
+            if (gd[0] < 0 || gd[0] >= m->nvars || (gd[1] != 0 && gd[1] != 1))
+                return -2;
+        }
+        int64_t tot = llabs((int64_t)c[2]);
+        for (int32_t t = t0; t < t1; ++t) {
+            const int32_t a = m->cterm[2 * (int64_t)t], y = m->cterm[2 * (int64_t)t + 1];
+            if (a == 0 || y < 0 || y >= m->nvars)
+                return -2;
+            int64_t p = llabs((int64_t)m->lb0[y]), u = llabs((int64_t)m->ub0[y]);
+            tot += llabs((int64_t)a) * (p > u ? p : u);
+            if (tot >= LIM)
+                return -3;
+        }
+    }
     return 0;
 }
 
@@ -256,8 +329,10 @@ static void run_propagator(const orc_model *m, store_t *s, int64_t p)
 {
     if (p < m->nrows)
         run_row(m, s, (int32_t)p);
-    else
+    else if (p < (int64_t)m->nrows + m->nreif)
         run_reif(m, s, (int32_t)(p - m->nrows));
+    else
+        run_cmd(m, s, (int32_t)(p - m->nrows - m->nreif));
 }
 
 /* Jacobi step: every command reads the snapshot (lb0s, ub0s) and joins its
@@ -298,6 +373,14 @@ static void jacobi_sweep(const orc_model *m, const int32_t *slb, const int32_t *
                 tub[x] = sub[x];
             }
         }
+    }
+    for (int32_t q = 0; q < m->ncmd; ++q) {
+        const int32_t x = m->cmd[4 * (int64_t)q];
+        run_cmd(m, &t, q);
+        if (tlb[x] > out->lb[x]) out->lb[x] = tlb[x];
+        if (tub[x] < out->ub[x]) out->ub[x] = tub[x];
+        tlb[x] = slb[x];
+        tub[x] = sub[x];
     }
     free(tlb);
     free(tub);
@@ -346,7 +429,7 @@ int32_t orc_gs_step(const orc_model *m, int32_t *lb, int32_t *ub)
     store_t s = {lb, ub, 0, 0};
     if (store_is_failed(m, &s))
         return ORC_FAILED;
-    const int64_t P = (int64_t)m->nrows + m->nreif;
+    const int64_t P = (int64_t)m->nrows + m->nreif + m->ncmd;
     for (int64_t p = 0; p < P && !s.failed; ++p)
         run_propagator(m, &s, p);
     if (s.failed)
@@ -379,7 +462,7 @@ int32_t orc_propagate_validated(const orc_model *m, int32_t *lb, int32_t *ub,
         if (sweeps) *sweeps = 0;
         return ORC_FAILED;
     }
-    const int64_t P = (int64_t)m->nrows + m->nreif;
+    const int64_t P = (int64_t)m->nrows + m->nreif + m->ncmd;
     uint64_t rng = seed;
 
     if (sched == ORC_SCHED_GS || sched == ORC_SCHED_REVERSE || sched == ORC_SCHED_PERM) {
@@ -406,9 +489,11 @@ int32_t orc_propagate_validated(const orc_model *m, int32_t *lb, int32_t *ub,
             if (st == ORC_FIXPOINT) break;
         }
     } else if (sched == ORC_SCHED_SELECT) {
-        /* commands: one per row term, REIF_NCMD per reified item */
+        /* commands: one per row term, REIF_NCMD per reified item, then the
+         * model's guarded commands */
         const int64_t T = m->nrows > 0 ? m->row_ptr[m->nrows] : 0;
-        const int64_t C = T + (int64_t)REIF_NCMD * m->nreif;
+        const int64_t CR = T + (int64_t)REIF_NCMD * m->nreif;
+        const int64_t C = CR + m->ncmd;
         int32_t *term_row = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T > 0 ? T : 1));
         for (int32_t r = 0; r < m->nrows; ++r)
             for (int32_t t = m->row_ptr[r]; t < m->row_ptr[r + 1]; ++t)
@@ -420,9 +505,11 @@ int32_t orc_propagate_validated(const orc_model *m, int32_t *lb, int32_t *ub,
                 if (C == 0) break;
                 if (c < T)
                     run_row_term(m, &s, term_row[c], (int32_t)c);
-                else
+                else if (c < CR)
                     run_reif_cmd(&s, m->reif + 4 * ((c - T) / REIF_NCMD),
                                  (int)((c - T) % REIF_NCMD));
+                else
+                    run_cmd(m, &s, (int32_t)(c - CR));
             }
             if (s.failed) break;
             /* ... then every command once, so that each is selected at least
@@ -432,9 +519,11 @@ int32_t orc_propagate_validated(const orc_model *m, int32_t *lb, int32_t *ub,
             for (int64_t c = 0; c < C && !s.failed; ++c) {
                 if (c < T)
                     run_row_term(m, &s, term_row[c], (int32_t)c);
-                else
+                else if (c < CR)
                     run_reif_cmd(&s, m->reif + 4 * ((c - T) / REIF_NCMD),
                                  (int)((c - T) % REIF_NCMD));
+                else
+                    run_cmd(m, &s, (int32_t)(c - CR));
             }
             if (s.failed || !s.changed) break;
         }

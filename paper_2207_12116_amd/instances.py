@@ -95,6 +95,15 @@ class Model:
     objective      int           variable to minimise, or -1
     mode           int           MODE_ENUMERATE or MODE_MINIMIZE
     meta           dict          generator parameters (durations, demands, ...)
+    cmd            int32[C, 4]   guarded commands {guards} => x <- f (§3):
+                                 (x, side, k, div); side 0 tells lb(x) >=
+                                 ceil(f / div), side 1 tells ub(x) <=
+                                 floor(f / div), f = k + sum a_t * y_t
+    cmd_gptr       int32[C+1]    CSR pointer of the guards
+    cmd_guard      int32[G, 3]   (y, side, c): side 0 is entailed(y >= c),
+                                 side 1 is entailed(y <= c)
+    cmd_tptr       int32[C+1]    CSR pointer of the terms of f
+    cmd_term       int32[U, 2]   (a, y), a nonzero
     """
 
     lb: np.ndarray
@@ -108,6 +117,11 @@ class Model:
     objective: int
     mode: int
     meta: dict = field(default_factory=dict)
+    cmd: np.ndarray = field(default_factory=lambda: np.zeros((0, 4), dtype=np.int32))
+    cmd_gptr: np.ndarray = field(default_factory=lambda: np.zeros(1, dtype=np.int32))
+    cmd_guard: np.ndarray = field(default_factory=lambda: np.zeros((0, 3), dtype=np.int32))
+    cmd_tptr: np.ndarray = field(default_factory=lambda: np.zeros(1, dtype=np.int32))
+    cmd_term: np.ndarray = field(default_factory=lambda: np.zeros((0, 2), dtype=np.int32))
 
     @property
     def nvars(self) -> int:
@@ -125,6 +139,10 @@ class Model:
     def nreif(self) -> int:
         return int(self.reif.shape[0])
 
+    @property
+    def ncmd(self) -> int:
+        return int(self.cmd.shape[0])
+
     def rows(self):
         """Yield (coef array, var array, rhs) per linear row."""
         for r in range(self.nrows):
@@ -138,6 +156,9 @@ class Model:
             h.update(np.ascontiguousarray(arr, dtype=np.int32).tobytes())
         h.update(np.int64(self.objective).tobytes())
         h.update(np.int64(self.mode).tobytes())
+        if self.ncmd:
+            for arr in (self.cmd, self.cmd_gptr, self.cmd_guard, self.cmd_tptr, self.cmd_term):
+                h.update(np.ascontiguousarray(arr, dtype=np.int32).tobytes())
         return h.hexdigest()[:16]
 
 
@@ -150,6 +171,11 @@ class _Builder:
         self.var: list[int] = []
         self.rhs: list[int] = []
         self.reif: list[tuple[int, int, int, int]] = []
+        self.cmd: list[tuple[int, int, int, int]] = []
+        self.gptr = [0]
+        self.guard: list[tuple[int, int, int]] = []
+        self.tptr = [0]
+        self.cterm: list[tuple[int, int]] = []
 
     def add_vars(self, n: int, lo: int, hi: int) -> int:
         first = len(self.lb)
@@ -170,12 +196,26 @@ class _Builder:
     def add_reif(self, b: int, si: int, sj: int, d: int) -> None:
         self.reif.append((b, si, sj, d))
 
+    def add_cmd(self, guards, x: int, side: int, k: int, div: int, terms) -> None:
+        """{guards} => x <- f: guards (y, side, c), terms (a, y) of f."""
+        for y, gs, c in guards:
+            self.guard.append((int(y), int(gs), int(c)))
+        self.gptr.append(len(self.guard))
+        for a, y in terms:
+            if int(a) != 0:
+                self.cterm.append((int(a), int(y)))
+        self.tptr.append(len(self.cterm))
+        self.cmd.append((int(x), int(side), int(k), int(div)))
+
     def finish(self, decision, objective, mode, meta) -> Model:
         i32 = lambda xs: np.asarray(xs, dtype=np.int32)
         reif = np.asarray(self.reif, dtype=np.int32).reshape(-1, 4)
         return Model(i32(self.lb), i32(self.ub), i32(self.ptr), i32(self.coef),
                      i32(self.var), i32(self.rhs), reif, i32(decision),
-                     int(objective), int(mode), meta)
+                     int(objective), int(mode), meta,
+                     i32(self.cmd).reshape(-1, 4), i32(self.gptr),
+                     i32(self.guard).reshape(-1, 3), i32(self.tptr),
+                     i32(self.cterm).reshape(-1, 2))
 
 
 def tiny_csp(seed: int, nvars: int = 8, dom: int = 20, nprec: int = 12) -> Model:
@@ -303,11 +343,14 @@ def jobshop_data(n_jobs: int, n_mach: int, seed: int, dmax: int = 10):
     return jobs
 
 
-def jobshop(n_jobs: int, n_mach: int, seed: int) -> Model:
+def jobshop(n_jobs: int, n_mach: int, seed: int, guarded: bool = False) -> Model:
     """The job shop as a PCCP program (front-end in `lang`): start times s,
     makespan m; precedences along each job; for every pair of operations on
     one machine, a disjunction of their two orders.  Variable layout: the
-    starts job by job, then m, then the auxiliaries of the disjunctions."""
+    starts job by job, then m, then the auxiliaries of the disjunctions.
+    guarded=True states each disjunction with guarded commands (disj_rows:
+    once one order is impossible the other is told) instead of a reified
+    difference with an implication."""
     from .lang import Program
     jobs = jobshop_data(n_jobs, n_mach, seed)
     h = sum(d for job in jobs for _, d in job)
@@ -324,11 +367,14 @@ def jobshop(n_jobs: int, n_mach: int, seed: int) -> Model:
         for a in range(len(ops)):
             for b in range(a + 1, len(ops)):
                 (x, dx), (y, dy) = ops[a], ops[b]
-                p.disj(x, y, -dx, y, x, -dy)               # x + dx <= y or y + dy <= x
+                if guarded:
+                    p.disj_rows([1, -1], [x, y], -dx, [1, -1], [y, x], -dy)
+                else:
+                    p.disj(x, y, -dx, y, x, -dy)           # x + dx <= y or y + dy <= x
     dec = [v for row in s for v in row]
     return p.compile(decision=dec, objective=m,
                      meta=dict(kind="jobshop", jobs=jobs, n_jobs=n_jobs, n_mach=n_mach,
-                               horizon=h, seed=seed))
+                               horizon=h, seed=seed, guarded=bool(guarded)))
 
 
 # ------------------------------------------------------------- model files

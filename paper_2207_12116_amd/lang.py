@@ -23,6 +23,29 @@ constraint forms, the linear row and the reified overlap item):
                               guard is entailed (§2 ask; interval entailment
                               decides b)
 
+Constructs on the library's guarded-command kind (§3 guarded normal form:
+a set of commands {g_1..g_n} => x <- f run in parallel; the gnf function of
+§3 lifts nested asks by duplicating their guards):
+
+  when(guards, sum a x <= c)  {guards} => one command per term: the term's
+                              bound told from the other terms' bounds
+                              (guards are bound tests (y, ">=", c) or
+                              (y, "<=", c), i.e. entailed(y >= c) etc.)
+  view(sum a x)               an auxiliary t with t <- sum a x on both
+                              bounds (two unguarded commands): lb(t) and
+                              ub(t) are the least and greatest value of the
+                              sum over the box, so entailed(sum a x <= c) is
+                              ub(t) <= c and entailed(not sum a x <= c) is
+                              lb(t) >= c + 1 (§2 entailment of a linear sum)
+  ask_row(guard row, body row)
+                              if entailed(guard) then tell(body)
+  iff_row(b, row)             b <=> row, §2's four processes for phi <=> psi:
+                              entailed(row) -> b; entailed(b) -> row;
+                              entailed(not row) -> not b; entailed(not b) ->
+                              not row
+  disj_rows(row1, row2)       entailed(not row1) -> row2 and entailed(not
+                              row2) -> row1
+
 The program keeps its own variables first (in creation order) and appends
 the auxiliary ones; `decision` defaults to the program's own variables.
 """
@@ -39,6 +62,7 @@ class Program:
         self._hi: list[int] = []
         self._rows: list[tuple[list[int], list[int], int]] = []
         self._reif: list[tuple[int, int, int, int]] = []
+        self._cmds: list[tuple] = []
         self._own: list[int] = []
         self._aux_from = None
 
@@ -124,6 +148,72 @@ class Program:
         self.implies(b, coefs, vars_, rhs)
         return b
 
+    # ---- guarded commands
+    @staticmethod
+    def _guards(guards):
+        out = []
+        for y, op, c in guards:
+            if op not in (">=", "<="):
+                raise ValueError("a guard is (var, '>=' or '<=', constant)")
+            out.append((int(y), 0 if op == ">=" else 1, int(c)))
+        return out
+
+    def _check_row(self, coefs, vars_):
+        coefs, vars_ = [int(a) for a in coefs], [int(v) for v in vars_]
+        if len(coefs) != len(vars_) or len(set(vars_)) != len(vars_) or 0 in coefs:
+            raise ValueError("a row needs one nonzero coefficient per distinct variable")
+        return coefs, vars_
+
+    def when(self, guards, coefs, vars_, c: int):
+        """{guards} => tell(sum coefs * vars_ <= c), one command per term:
+        a_i > 0: ub(x_i) <= floor((c - sum_{j != i} a_j x_j) / a_i);
+        a_i < 0: lb(x_i) >= ceil((sum_{j != i} a_j x_j - c) / -a_i)."""
+        g = self._guards(guards)
+        coefs, vars_ = self._check_row(coefs, vars_)
+        for i, (a, x) in enumerate(zip(coefs, vars_)):
+            rest = [(aj, xj) for j, (aj, xj) in enumerate(zip(coefs, vars_)) if j != i]
+            if a > 0:
+                self._cmds.append((g, x, 1, int(c), a, [(-aj, xj) for aj, xj in rest]))
+            else:
+                self._cmds.append((g, x, 0, -int(c), -a, rest))
+
+    def view(self, coefs, vars_) -> int:
+        """An auxiliary t whose bounds are the least and greatest value of
+        sum coefs * vars_ over the box (two unguarded commands)."""
+        coefs, vars_ = self._check_row(coefs, vars_)
+        lo = sum(a * (self._lo[v] if a > 0 else self._hi[v]) for a, v in zip(coefs, vars_))
+        hi = sum(a * (self._hi[v] if a > 0 else self._lo[v]) for a, v in zip(coefs, vars_))
+        t = self._aux(lo, hi)
+        terms = list(zip(coefs, vars_))
+        self._cmds.append(([], t, 0, 0, 1, terms))      # lb(t) >= sum of least terms
+        self._cmds.append(([], t, 1, 0, 1, terms))      # ub(t) <= sum of greatest terms
+        return t
+
+    def ask_row(self, gcoefs, gvars, gc: int, coefs, vars_, c: int, guards=()):
+        """if entailed(sum gcoefs * gvars <= gc) then tell(sum coefs * vars_ <= c)."""
+        t = self.view(gcoefs, gvars)
+        self.when(list(guards) + [(t, "<=", int(gc))], coefs, vars_, c)
+        return t
+
+    def iff_row(self, b: int, coefs, vars_, c: int):
+        """b <=> (sum coefs * vars_ <= c)."""
+        self._bool(b)
+        coefs, vars_ = self._check_row(coefs, vars_)
+        t = self.view(coefs, vars_)
+        self._cmds.append(([(t, 1, int(c))], b, 0, 1, 1, []))     # entailed(row) -> lb(b) >= 1
+        self._cmds.append(([(t, 0, int(c) + 1)], b, 1, 0, 1, []))  # entailed(not row) -> ub(b) <= 0
+        self.when([(b, ">=", 1)], coefs, vars_, c)                # entailed(b) -> row
+        self.when([(b, "<=", 0)], [-a for a in coefs], vars_, -int(c) - 1)  # entailed(not b) -> not row
+        return t
+
+    def disj_rows(self, c1, v1, r1: int, c2, v2, r2: int):
+        """(sum c1 * v1 <= r1) or (sum c2 * v2 <= r2)."""
+        t1 = self.view(c1, v1)
+        t2 = self.view(c2, v2)
+        self.when([(t1, ">=", int(r1) + 1)], c2, v2, r2)
+        self.when([(t2, ">=", int(r2) + 1)], c1, v1, r1)
+        return t1, t2
+
     # ---- compile
     def compile(self, decision=None, objective: int = -1, meta: dict | None = None) -> Model:
         bld = _Builder()
@@ -133,6 +223,8 @@ class Program:
             bld.add_row(coefs, vars_, c)
         for it in self._reif:
             bld.add_reif(*it)
+        for g, x, side, k, div, terms in self._cmds:
+            bld.add_cmd(g, x, side, k, div, terms)
         dec = list(self._own) if decision is None else [int(v) for v in decision]
         mode = MODE_MINIMIZE if objective >= 0 else MODE_ENUMERATE
         return bld.finish(dec, objective, mode, dict(meta or {}, kind="pccp_program"))

@@ -24,7 +24,11 @@ def _row(coefs, vars_, c, pt):
     return sum(a * pt[v] for a, v in zip(coefs, vars_)) <= c
 
 
-def _random_program(rng):
+def _guard_holds(guards, pt):
+    return all((pt[y] >= c) if op == ">=" else (pt[y] <= c) for y, op, c in guards)
+
+
+def _random_program(rng, guarded=False):
     nx, nb = rng.randint(2, 3), rng.randint(1, 2)
     p = Program()
     xs = [p.var(rng.randint(-2, 0), rng.randint(1, 3)) for _ in range(nx)]
@@ -36,8 +40,11 @@ def _random_program(rng):
         vs = rng.sample(xs, k)
         return [rng.choice([-2, -1, 1, 2]) for _ in vs], vs, rng.randint(-2, 4)
 
+    kinds = ["tell", "iff", "implies", "implies_not", "disj", "ask"]
+    if guarded:
+        kinds = ["tell", "when", "ask_row", "iff_row", "disj_rows"]
     for _ in range(rng.randint(2, 4)):
-        kind = rng.choice(["tell", "iff", "implies", "implies_not", "disj", "ask"])
+        kind = rng.choice(kinds)
         if kind == "tell":
             a, v, c = rrow()
             p.tell(a, v, c)
@@ -57,6 +64,29 @@ def _random_program(rng):
             else:
                 p.implies(p.neg(b), a, v, c)
                 cons.append(lambda pt, b=b, a=a, v=v, c=c: pt[b] == 1 or _row(a, v, c, pt))
+        elif kind == "when":
+            g = [(rng.choice(xs + bs), rng.choice([">=", "<="]), rng.randint(-1, 2))
+                 for _ in range(rng.randint(1, 2))]
+            a, v, c = rrow()
+            p.when(g, a, v, c)
+            cons.append(lambda pt, g=g, a=a, v=v, c=c: not _guard_holds(g, pt) or _row(a, v, c, pt))
+        elif kind == "ask_row":
+            ga, gv, gc = rrow()
+            a, v, c = rrow()
+            p.ask_row(ga, gv, gc, a, v, c)
+            cons.append(lambda pt, ga=ga, gv=gv, gc=gc, a=a, v=v, c=c:
+                        not _row(ga, gv, gc, pt) or _row(a, v, c, pt))
+        elif kind == "iff_row":
+            b = rng.choice(bs)
+            a, v, c = rrow()
+            p.iff_row(b, a, v, c)
+            cons.append(lambda pt, b=b, a=a, v=v, c=c: pt[b] == int(_row(a, v, c, pt)))
+        elif kind == "disj_rows":
+            a1, v1, c1 = rrow()
+            a2, v2, c2 = rrow()
+            p.disj_rows(a1, v1, c1, a2, v2, c2)
+            cons.append(lambda pt, a1=a1, v1=v1, c1=c1, a2=a2, v2=v2, c2=c2:
+                        _row(a1, v1, c1, pt) or _row(a2, v2, c2, pt))
         elif kind == "disj":
             x, y = rng.sample(xs, 2)
             u, w = rng.sample(xs, 2)
@@ -74,10 +104,14 @@ def _random_program(rng):
     return p, xs + bs, cons
 
 
+@pytest.mark.parametrize("guarded", [False, True], ids=["rows_reified", "guarded_commands"])
 @pytest.mark.parametrize("seed", range(60))
-def test_random_programs_solution_sets(seed):
-    rng = random.Random(seed)
-    p, own, cons = _random_program(rng)
+def test_random_programs_solution_sets(seed, guarded):
+    """Guarded commands (§3 guarded normal form) are pinned here by their
+    meaning: the points the oracle's search keeps are exactly those where
+    every construct holds, evaluated directly on the point."""
+    rng = random.Random(seed + (1000 if guarded else 0))
+    p, own, cons = _random_program(rng, guarded)
     model = p.compile()
     boxes = [range(model.lb[v], model.ub[v] + 1) for v in own]
     want = set()
@@ -91,10 +125,11 @@ def test_random_programs_solution_sets(seed):
     assert got == want, (seed, sorted(want - got)[:5], sorted(got - want)[:5])
 
 
+@pytest.mark.parametrize("guarded", [False, True], ids=["reified", "guarded"])
 @pytest.mark.parametrize("nj,nm", [(2, 2), (3, 2), (3, 3), (4, 2), (4, 3)])
 @pytest.mark.parametrize("seed", range(3))
-def test_jobshop_optimum_equals_disjunctive_graph_brute_force(nj, nm, seed):
-    m = I.jobshop(nj, nm, seed)
+def test_jobshop_optimum_equals_disjunctive_graph_brute_force(nj, nm, seed, guarded):
+    m = I.jobshop(nj, nm, seed, guarded=guarded)
     r = O.solve(m)
     assert r["outcome"] == O.OUT_OPTIMAL
     assert r["best"] == jobshop_brute(m.meta["jobs"])
@@ -115,3 +150,32 @@ def test_front_end_rejects_bad_programs():
     u, w, bb = q.var(0, 40000), q.var(0, 40000), q.boolean()
     with pytest.raises(ValueError):
         q.iff(bb, u, w, 0)                 # span past the reified item's int16 d
+
+
+def test_guarded_program_brute_points():
+    """The oracle's independent point checker (orc_brute_points states each
+    guarded command as a constraint on complete points) agrees with the
+    direct evaluation on random guarded programs."""
+    for seed in range(25):
+        rng = random.Random(5000 + seed)
+        p, own, cons = _random_program(rng, guarded=True)
+        model = p.compile()
+        # brute force runs over every variable: keep the auxiliaries'
+        # boxes (views) as they are, they are determined by the own ones
+        n, h, pts = O.brute_points(model, cap=100000)
+        boxes = [range(model.lb[v], model.ub[v] + 1) for v in own]
+        want = {vals for vals in itertools.product(*boxes)
+                if all(f(dict(zip(own, vals))) for f in cons)}
+        got = {tuple(int(x) for x in row) for row in pts}
+        assert got == want, seed
+
+
+def test_front_end_guarded_errors():
+    p = Program()
+    x, y = p.var(0, 5), p.var(0, 5)
+    with pytest.raises(ValueError):
+        p.when([(x, ">", 1)], [1], [y], 3)        # guards are >= or <=
+    with pytest.raises(ValueError):
+        p.when([], [1, 0], [x, y], 3)             # zero coefficient
+    with pytest.raises(ValueError):
+        p.iff_row(x, [1], [y], 2)                 # x is not Boolean
