@@ -36,6 +36,14 @@ class _Model(C.Structure):
                 ("cterm", _P32)]
 
 
+_PF = C.POINTER(C.c_float)
+
+
+class _FModel(C.Structure):
+    _fields_ = [("nvars", C.c_int32), ("lb0", _PF), ("ub0", _PF), ("nrows", C.c_int32),
+                ("row_ptr", _P32), ("coef", _PF), ("var", _P32), ("rhs", _PF)]
+
+
 class _Stats(C.Structure):
     _fields_ = [("nodes", C.c_int64), ("fails", C.c_int64),
                 ("solutions", C.c_int64), ("max_depth", C.c_int64),
@@ -110,6 +118,15 @@ def _load(path):
     L.orc_solve_timed.argtypes = [C.POINTER(MP), C.c_int32, C.c_int32, C.c_int32, C.c_int64,
                                   C.c_int32, C.POINTER(C.c_int64), PD, _P32, _P32, PD]
     L.orc_solve_timed.restype = C.c_int32
+    FP = C.POINTER(_FModel)
+    L.orc_fvalidate.argtypes = [FP]
+    L.orc_fvalidate.restype = C.c_int32
+    L.orc_fpropagate.argtypes = [FP, _PF, _PF, C.c_int32, C.c_uint64, C.POINTER(C.c_int64)]
+    L.orc_fpropagate.restype = C.c_int32
+    L.orc_fjacobi_step.argtypes = [FP, _PF, _PF]
+    L.orc_fjacobi_step.restype = C.c_int32
+    L.orc_fsame.argtypes = [C.c_int32, _PF, _PF]
+    L.orc_fsame.restype = C.c_int32
     return L
 
 
@@ -377,3 +394,60 @@ def set_mlp_params(params):
     global _mlp_keep
     _mlp_keep = np.ascontiguousarray(params, dtype=np.float64)
     lib().orc_set_mlp_params(_pd(_mlp_keep))
+
+
+# ---------------------------------------------------------------- float stores
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _pf(a: np.ndarray):
+    return a.ctypes.data_as(_PF)
+
+
+class OracleFModel:
+    """float32 / int32 copies of an `FModel`'s arrays and the C struct."""
+
+    def __init__(self, model):
+        self.model = model
+        self._keep = [_f32(model.lb), _f32(model.ub), _i32(model.row_ptr), _f32(model.coef),
+                      _i32(model.var), _f32(model.rhs)]
+        lb, ub, ptr, coef, var, rhs = self._keep
+        self.s = _FModel(model.nvars, _pf(lb), _pf(ub), model.nrows, _ptr(ptr), _pf(coef),
+                         _ptr(var), _pf(rhs))
+
+    def ref(self):
+        return C.byref(self.s)
+
+
+def _ofm(model) -> OracleFModel:
+    return model if isinstance(model, OracleFModel) else OracleFModel(model)
+
+
+def fvalidate(model) -> int:
+    return int(lib().orc_fvalidate(_ofm(model).ref()))
+
+
+def fpropagate(model, lb=None, ub=None, sched=SCHED_GS, seed=0):
+    """Fixed point of a float interval store above (lb, ub) (default: the
+    model's box).  Returns (status, lb, ub, sweeps) with float32 arrays."""
+    om = _ofm(model)
+    m = om.model
+    lb = np.array(m.lb if lb is None else lb, dtype=np.float32, copy=True)
+    ub = np.array(m.ub if ub is None else ub, dtype=np.float32, copy=True)
+    sw = C.c_int64(0)
+    st = lib().orc_fpropagate(om.ref(), _pf(lb), _pf(ub), int(sched),
+                              C.c_uint64(seed & (2**64 - 1)), C.byref(sw))
+    if st < 0:
+        raise ValueError(f"orc_fpropagate error {st}")
+    return int(st), lb, ub, int(sw.value)
+
+
+def fjacobi_step(model, lb, ub):
+    om = _ofm(model)
+    lb = np.array(lb, dtype=np.float32, copy=True)
+    ub = np.array(ub, dtype=np.float32, copy=True)
+    st = lib().orc_fjacobi_step(om.ref(), _pf(lb), _pf(ub))
+    if st < 0:
+        raise ValueError(f"orc_fjacobi_step error {st}")
+    return int(st), lb, ub

@@ -12,7 +12,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["propagate.c", "search.c", "brute.c", "learn.c", "timing.c"]
+SOURCES = ["propagate.c", "search.c", "brute.c", "learn.c", "timing.c", "fprop.c"]
 
 
 def build(verbose: bool = False, native: bool = False, out: str | None = None) -> str:
@@ -20,6 +20,8 @@ def build(verbose: bool = False, native: bool = False, out: str | None = None) -
     tmp = out + ".tmp"
     cmd = ["gcc", "-O3"] + (["-march=native"] if native else []) + [
         "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-pthread",
+        # fprop.c changes the rounding mode between operations
+        "-frounding-math", "-ffp-contract=off",
         "-o", tmp] + [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
     if verbose:
         print(" ".join(cmd))

@@ -197,6 +197,38 @@ int64_t orc_trace(const orc_model *m, int32_t mode, int64_t node_limit, float *f
                   double *score, int32_t *cand, int32_t *off, int32_t *label, int64_t cap_nodes,
                   int64_t cap_cand, int64_t *ncand);
 
+/* ---- floating-point interval stores (fprop.c) ----------------------- */
+
+/* A model over float32 interval variables (§2: FInc x FDec, IEEE total
+ * order) with linear rows sum_t coef[t] * x_var[t] <= rhs over the reals;
+ * propagation rounds outward (fprop.c).  Initial bounds must be finite. */
+typedef struct {
+    int32_t nvars;
+    const float *lb0, *ub0;
+    int32_t nrows;
+    const int32_t *row_ptr;            /* nrows + 1                          */
+    const float *coef;                 /* row_ptr[nrows]                     */
+    const int32_t *var;
+    const float *rhs;                  /* nrows                              */
+} orc_fmodel;
+
+/* 0, or -1 (bad arguments) / -2 (non-finite bound or coefficient, zero
+ * coefficient, index out of range, variable repeated in a row). */
+int32_t orc_fvalidate(const orc_fmodel *m);
+
+/* Least fixed point above (lb, ub), in place (zeros made canonical first:
+ * -0 for lower bounds, +0 for upper bounds).  Schedules: ORC_SCHED_GS,
+ * _JACOBI, _PERM (seeded), _REVERSE.  ORC_FIXPOINT or ORC_FAILED. */
+int32_t orc_fpropagate(const orc_fmodel *m, float *lb, float *ub, int32_t sched, uint64_t seed,
+                       int64_t *sweeps);
+
+/* One Jacobi step: ORC_FIXPOINT if nothing changed, 2 if the store changed
+ * and is not failed, ORC_FAILED. */
+int32_t orc_fjacobi_step(const orc_fmodel *m, float *lb, float *ub);
+
+/* 1 if a and b (n floats) are bit-identical. */
+int32_t orc_fsame(int32_t n, const float *a, const float *b);
+
 #ifdef __cplusplus
 }
 #endif

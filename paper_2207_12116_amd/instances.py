@@ -37,6 +37,8 @@ CFG_RCPSP = 2
 CFG_TINY_RCPSP = 3
 CFG_PREC_ONLY = 4
 CFG_JOBSHOP = 5
+CFG_FLOAT_CSP = 6
+CFG_FLOAT_NET = 7
 
 
 class SplitMix64:
@@ -379,9 +381,11 @@ def jobshop(n_jobs: int, n_mach: int, seed: int, guarded: bool = False) -> Model
 
 # ------------------------------------------------------------- model files
 # The library's model-file layout (little-endian): the line "PCCP-MODEL 1",
-# one line of JSON with nvars, nrows, nterms, nreif, ndec, objective (and
-# here also the search mode and the generator's parameters as "meta"), then int32
-# arrays lb, ub, row_ptr, coef, var, rhs, reif (4 per item), dec.
+# one line of JSON with nvars, nrows, nterms, nreif, ndec, objective,
+# ncmd, nguards, ncterms (and here also the search mode and the generator's
+# parameters as "meta"), then int32 arrays lb, ub, row_ptr, coef, var, rhs,
+# reif (4 per item), dec, and when ncmd > 0 the guarded commands: cmd (4 per
+# command), cmd_gptr, guards (3 per guard), cmd_tptr, terms (2 per term).
 MODEL_MAGIC = b"PCCP-MODEL 1\n"
 
 
@@ -389,12 +393,18 @@ def save_model(model: Model, path: str) -> None:
     import json
     hdr = {"nvars": model.nvars, "nrows": model.nrows, "nterms": model.nterms,
            "nreif": model.nreif, "ndec": int(model.decision.shape[0]),
-           "objective": int(model.objective), "mode": int(model.mode), "meta": model.meta}
+           "objective": int(model.objective), "ncmd": model.ncmd,
+           "nguards": int(np.asarray(model.cmd_guard).reshape(-1, 3).shape[0]),
+           "ncterms": int(np.asarray(model.cmd_term).reshape(-1, 2).shape[0]),
+           "mode": int(model.mode), "meta": model.meta}
+    arrays = [model.lb, model.ub, model.lin_ptr, model.lin_coef, model.lin_var,
+              model.lin_rhs, model.reif, model.decision]
+    if model.ncmd:
+        arrays += [model.cmd, model.cmd_gptr, model.cmd_guard, model.cmd_tptr, model.cmd_term]
     with open(path, "wb") as f:
         f.write(MODEL_MAGIC)
         f.write(json.dumps(hdr, separators=(", ", ": ")).encode() + b"\n")
-        for a in (model.lb, model.ub, model.lin_ptr, model.lin_coef, model.lin_var,
-                  model.lin_rhs, model.reif, model.decision):
+        for a in arrays:
             f.write(np.ascontiguousarray(a, dtype="<i4").tobytes())
 
 
@@ -406,16 +416,125 @@ def load_model(path: str) -> Model:
         hdr = json.loads(f.readline())
         body = np.frombuffer(f.read(), dtype="<i4")
     V, R, T, Q, D = (int(hdr[k]) for k in ("nvars", "nrows", "nterms", "nreif", "ndec"))
+    NC, NG, NT = (int(hdr.get(k, 0)) for k in ("ncmd", "nguards", "ncterms"))
     sizes = [V, V, R + 1, T, T, R, 4 * Q, D]
+    if NC:
+        sizes += [4 * NC, NC + 1, 3 * NG, NC + 1, 2 * NT]
     if body.shape[0] != sum(sizes):
         raise ValueError(f"{path}: {body.shape[0]} values, expected {sum(sizes)}")
     parts, o = [], 0
     for n in sizes:
         parts.append(body[o:o + n].astype(np.int32))
         o += n
-    lb, ub, ptr, coef, var, rhs, reif, dec = parts
+    lb, ub, ptr, coef, var, rhs, reif, dec = parts[:8]
     obj = int(hdr["objective"])
     mode = int(hdr.get("mode", MODE_MINIMIZE if obj >= 0 else MODE_ENUMERATE))
-    return Model(lb, ub, ptr, coef, var, rhs, reif.reshape(-1, 4), dec, obj, mode,
-                 dict(hdr.get("meta", {})))
+    m = Model(lb, ub, ptr, coef, var, rhs, reif.reshape(-1, 4), dec, obj, mode,
+              dict(hdr.get("meta", {})))
+    if NC:
+        m.cmd = parts[8].reshape(-1, 4)
+        m.cmd_gptr = parts[9]
+        m.cmd_guard = parts[10].reshape(-1, 3)
+        m.cmd_tptr = parts[11]
+        m.cmd_term = parts[12].reshape(-1, 2)
+    return m
 
+# ---------------------------------------------------------------- float models
+@dataclass
+class FModel:
+    """A model over float32 interval variables with linear rows over the
+    reals (data only):
+
+    lb, ub     float32[V]   initial box (finite)
+    row_ptr    int32[R+1]   CSR pointer of the rows
+    coef       float32[T]   nonzero coefficients
+    var        int32[T]     variables (distinct within a row)
+    rhs        float32[R]   sum_t coef[t] * x_var[t] <= rhs
+    """
+
+    lb: np.ndarray
+    ub: np.ndarray
+    row_ptr: np.ndarray
+    coef: np.ndarray
+    var: np.ndarray
+    rhs: np.ndarray
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nvars(self) -> int:
+        return int(self.lb.shape[0])
+
+    @property
+    def nrows(self) -> int:
+        return int(self.rhs.shape[0])
+
+    @property
+    def nterms(self) -> int:
+        return int(self.coef.shape[0])
+
+
+def _f32(v) -> float:
+    return float(np.float32(v))
+
+
+def _fmodel(lb, ub, rows, meta) -> FModel:
+    ptr, coef, var, rhs = [0], [], [], []
+    for a, x, c in rows:
+        coef.extend(a)
+        var.extend(x)
+        rhs.append(c)
+        ptr.append(len(coef))
+    f32 = lambda v: np.asarray(v, dtype=np.float32)
+    return FModel(f32(lb), f32(ub), np.asarray(ptr, dtype=np.int32), f32(coef),
+                  np.asarray(var, dtype=np.int32), f32(rhs), meta)
+
+
+def _unit(rng: SplitMix64) -> float:
+    """Uniform in [0, 1) with 24 random bits (exactly a float32)."""
+    return (rng.next_u64() >> 40) / float(1 << 24)
+
+
+def float_csp(seed: int, nvars: int = 8, dom: float = 20.0, nprec: int = 12) -> FModel:
+    """The tiny CSP over the reals: `nvars` variables in [0, dom],
+    `nprec` precedences x_u + d <= x_v (d uniform in [1, 5]) along a random
+    topological order, and one row sum_i a_i x_i <= c with a_i uniform in
+    [1, 4] and c = 60% of the largest possible sum."""
+    rng = stream(CFG_FLOAT_CSP, seed)
+    perm = list(range(nvars))
+    rng.shuffle(perm)
+    pairs = [(p, q) for p in range(nvars) for q in range(p + 1, nvars)]
+    rng.shuffle(pairs)
+    rows = []
+    for (p, q) in pairs[:nprec]:
+        d = _f32(1.0 + 4.0 * _unit(rng))
+        rows.append(([1.0, -1.0], [perm[p], perm[q]], -d))
+    a = [_f32(1.0 + 3.0 * _unit(rng)) for _ in range(nvars)]
+    c = _f32(0.6 * dom * sum(a))
+    rows.append((a, list(range(nvars)), c))
+    return _fmodel([0.0] * nvars, [dom] * nvars, rows,
+                   dict(kind="float_csp", seed=seed, dom=dom))
+
+
+def float_network(n: int, seed: int, rows_per_var: int = 2, kmax: int = 6,
+                  dom: float = 100.0) -> FModel:
+    """A sparse system over the reals: n variables in [-dom, dom] and
+    rows_per_var * n rows of 2..kmax distinct variables with coefficients
+    uniform in +-[0.25, 4] and a right-hand side that a random point of the
+    box satisfies with a slack uniform in [0, dom / 4] (so the root is not
+    failed, and propagation tightens the box)."""
+    rng = stream(CFG_FLOAT_NET, seed)
+    pt = [_f32(dom * (2.0 * _unit(rng) - 1.0) * 0.5) for _ in range(n)]
+    rows = []
+    for _ in range(rows_per_var * n):
+        k = rng.uniform(2, kmax)
+        xs = set()
+        while len(xs) < k:
+            xs.add(rng.below(n))
+        xs = sorted(xs)
+        a = []
+        for _x in xs:
+            mag = 0.25 + 3.75 * _unit(rng)
+            a.append(_f32(mag if rng.below(2) else -mag))
+        val = sum(ai * pt[x] for ai, x in zip(a, xs))
+        rows.append((a, xs, _f32(val + dom / 4.0 * _unit(rng))))
+    return _fmodel([-dom] * n, [dom] * n, rows, dict(kind="float_network", n=n, seed=seed))
