@@ -90,6 +90,8 @@ extern "C" {
 
 typedef struct pccp_model pccp_model;
 typedef struct pccp_solver pccp_solver;
+typedef struct pccp_fmodel pccp_fmodel;
+typedef struct pccp_fsolver pccp_fsolver;
 
 /* ---- model building (host) -------------------------------------------- */
 /* §2 (modelling layer): a model declares interval variables and constraints;
@@ -123,6 +125,27 @@ int32_t pccp_model_add_linear_le(pccp_model *m, int32_t nterms, const int32_t *c
 int32_t pccp_model_add_reified_overlap(pccp_model *m, int32_t b, int32_t si, int32_t sj,
                                        int32_t d);
 
+/* Append the guarded command {g_1, ..., g_n} => x <- f of the guarded
+ * normal form (§3: a program is a set of commands whose guards are
+ * entailment tests and whose bodies are tells; §2: ask and tell), with
+ *   f = k + sum_{t < nterms} coef[t] * y_{var[t]},
+ *   side 0: lb(x) >= ceil(f / div),  side 1: ub(x) <= floor(f / div),
+ * div >= 1.  Guard g tests one bound: gside[g] = 0 is entailed(y >= gc[g])
+ * = lb(y) >= gc[g], gside[g] = 1 is entailed(y <= gc[g]) = ub(y) <= gc[g]
+ * (y = gvar[g]).  The tell runs when every guard holds (nguards = 0: always)
+ * and each term is read through the bound that keeps f monotone as the
+ * store grows (§2: tells are monotone): for a lower-bound tell lb(y) when
+ * coef > 0 and ub(y) when coef < 0, the opposite for an upper-bound tell.
+ * Read on points, the command says: if every guard holds then div * x >= f
+ * (side 0) or div * x <= f (side 1).  Checked when a solver is created:
+ * indices in range, side in {0, 1}, div >= 1, nonzero coefficients,
+ * |k| + sum |coef| * max |bound| < 2^30 (PCCP_E_OVERFLOW), at most 65535
+ * guards and 65535 terms per command. */
+int32_t pccp_model_add_guarded(pccp_model *m, int32_t x, int32_t side, int32_t k, int32_t div,
+                               int32_t nguards, const int32_t *gvar, const int32_t *gside,
+                               const int32_t *gc, int32_t nterms, const int32_t *coef,
+                               const int32_t *var);
+
 /* Branching candidates, in tie-break order (§1: the search splits on them). */
 int32_t pccp_model_set_decision_vars(pccp_model *m, int32_t n, const int32_t *vars);
 
@@ -139,11 +162,16 @@ int32_t pccp_model_info(const pccp_model *m, int32_t *nvars, int32_t *nlinear,
  * read by every consumer.  Layout, all integers little-endian:
  *   line 1   "PCCP-MODEL 1"
  *   line 2   a JSON object with the integer fields nvars, nrows, nterms,
- *            nreif, ndec, objective (other fields are ignored on load; a
- *            generator may add its parameters there)
+ *            nreif, ndec, objective, and optionally ncmd, nguards, ncterms
+ *            (absent = 0); other fields are ignored on load (a generator
+ *            may add its parameters there)
  *   then     int32 lb[nvars], ub[nvars], row_ptr[nrows + 1] (0 .. nterms,
  *            increasing), coef[nterms], var[nterms], rhs[nrows],
  *            reif[4 * nreif] (b, si, sj, d per item), dec[ndec]
+ *   and, when ncmd > 0, the guarded commands: cmd[4 * ncmd] (x, side, k,
+ *            div), cmd_gptr[ncmd + 1] (0 .. nguards, not decreasing),
+ *            guard[3 * nguards] (y, side, c), cmd_tptr[ncmd + 1] (0 ..
+ *            ncterms, not decreasing), cterm[2 * ncterms] (coef, y)
  * save writes the model as built; load creates a model (*out, destroyed with
  * pccp_model_destroy) or returns PCCP_E_MODEL for a bad header, a file of
  * the wrong length or an inconsistent row pointer, PCCP_E_INVALID_ARG if the
@@ -226,6 +254,29 @@ int32_t pccp_propagate_batch(pccp_solver *s, int32_t nbox, const int32_t *lb_in,
                              const int32_t *ub_in, int32_t *lb_out, int32_t *ub_out,
                              int32_t *status, int32_t *sweeps);
 
+/* Incremental fixed points by dependency-driven propagation (§3, Theorem 2:
+ * any fair schedule - here, running a propagator only after a bound it
+ * reads was tightened - reaches the same least fixed point).  Box k is the
+ * store (lb_in, ub_in) row k joined with one decision,
+ *   lb(dvar[k]) >= dlo[k]  and  ub(dvar[k]) <= dhi[k]
+ * (a join: a bound already tighter is kept).  Precondition: every input
+ * store is a fixed point of the model, e.g. an output of
+ * pccp_propagate_batch; then lb_out/ub_out row k is the fixed point of
+ * the joined box, the one pccp_propagate_batch computes from it.  Only the
+ * propagators that read a bound the decision tightened run in the first
+ * sweep, and each later sweep runs those reading a bound the one before
+ * tightened.  All pointers are device memory: lb_in/ub_in/lb_out/ub_out are
+ * [nbox][nvars] int32, dvar/dlo/dhi/status/sweeps [nbox] (sweeps may be
+ * NULL).  status[k] = PCCP_FIXPOINT, PCCP_FAILED (lb_out/ub_out row k
+ * unspecified), or -1 when dvar[k] is outside [0, nvars) (the row is copied
+ * unchanged).  PCCP_E_UNSUPPORTED if a kind has more than 65536
+ * propagators.  Enqueued on the solver's stream; returns without
+ * waiting. */
+int32_t pccp_propagate_batch_incr(pccp_solver *s, int32_t nbox, const int32_t *lb_in,
+                                  const int32_t *ub_in, const int32_t *dvar, const int32_t *dlo,
+                                  const int32_t *dhi, int32_t *lb_out, int32_t *ub_out,
+                                  int32_t *status, int32_t *sweeps);
+
 /* Branching features (6 floats per decision variable, in decision-list
  * order) of nbox stores; all pointers are device memory: lb/ub are
  * [nbox][nvars] int32, feat is [nbox][ndecision][6] float.  For decision
@@ -285,7 +336,8 @@ typedef struct {
     int64_t max_depth;
     int64_t prop_linear2;     /* propagator executions: difference rows       */
     int64_t prop_reified;     /*                         reified overlaps     */
-    int64_t prop_linear;      /*                         other linear rows    */
+    int64_t prop_linear;      /*                         other linear rows and
+                                                         guarded commands     */
     int64_t prop_terms;       /* terms visited by other linear rows           */
     uint64_t sol_hash;        /* ENUMERATE: wrapping sum over solutions of
                                  fmix64(FNV-1a-64(decision values, LE bytes)) */
@@ -386,6 +438,59 @@ typedef struct {
 int32_t pccp_autotune(pccp_solver *const *solvers, int32_t n, int32_t mode,
                       const pccp_tune_opts *opts, pccp_config *best,
                       pccp_tune_result *results, int32_t cap, int32_t *nresults);
+
+/* ---- floating-point interval stores -----------------------------------
+ * §2 defines the lattices FInc and FDec of increasing and decreasing
+ * floating-point numbers, ordered by the IEEE 754 total order (footnote);
+ * §6 notes that intervals of reals are approximated by intervals of floats.
+ * A float model has float32 interval variables (lb in FInc, ub in FDec) and
+ * linear rows over the reals, sum_t coef[t] * x_var[t] <= rhs.  Each term's
+ * tell is the linear tell of §2 with outward rounding, so that no real
+ * solution is removed: the other terms' least values a_u * (lb or ub)(x_u)
+ * rounded down and summed in term order from +0 with each addition rounded
+ * down (S), then ub(x_t) <- (rhs - S, rounded up) / a_t rounded up when
+ * a_t > 0, lb(x_t) <- (rhs - S, rounded up) / a_t rounded down when a_t < 0.
+ * Zero bounds are canonical: a lower bound of zero is -0 and an upper bound
+ * of zero is +0 (so the total order and the numeric one agree).  A box is
+ * failed when some lb > ub. */
+
+/* Empty float model / destroy. */
+int32_t pccp_fmodel_create(pccp_fmodel **out);
+int32_t pccp_fmodel_destroy(pccp_fmodel *m);
+
+/* Append n variables with initial intervals [lb[i], ub[i]] (finite;
+ * checked at pccp_fsolver_create).  *first_id (may be NULL) receives the
+ * index of the first. */
+int32_t pccp_fmodel_add_vars(pccp_fmodel *m, int32_t n, const float *lb, const float *ub,
+                             int32_t *first_id);
+
+/* Append sum_{t<nterms} coef[t] * x_{var[t]} <= rhs (nterms >= 1; nonzero
+ * finite coefficients, distinct variables, finite rhs; checked at
+ * pccp_fsolver_create). */
+int32_t pccp_fmodel_add_linear_le(pccp_fmodel *m, int32_t nterms, const float *coef,
+                                  const int32_t *var, float rhs);
+
+/* Validate the float model and upload its tables to the current device.
+ * wg_size: threads per workgroup (multiple of 64, <= 1024; 0 = 256).
+ * PCCP_E_MODEL for a non-finite bound or coefficient, a zero coefficient,
+ * an index out of range or a variable repeated in a row;
+ * PCCP_E_LDS_CAPACITY if 8 bytes per variable do not fit in LDS. */
+int32_t pccp_fsolver_create(const pccp_fmodel *m, int32_t wg_size, void *stream,
+                            pccp_fsolver **out);
+int32_t pccp_fsolver_destroy(pccp_fsolver *s);
+
+/* Fixed points of nbox float boxes, one workgroup per box, every term's
+ * tell running concurrently with LDS atomic max / min on the bounds' total-
+ * order keys (§5 fixed point loop on the float lattices).  The tells are
+ * monotone, so the result is the least fixed point (§3, Theorem 2): the
+ * same store, bit for bit, as a sequential loop.  All pointers are device
+ * memory: lb_in/ub_in/lb_out/ub_out are [nbox][nvars] float32 (zeros of the
+ * inputs are made canonical), status [nbox] receives PCCP_FIXPOINT or
+ * PCCP_FAILED (on FAILED the output row is unspecified), sweeps [nbox] (may
+ * be NULL) the loop's iterations.  Enqueued on the solver's stream. */
+int32_t pccp_fpropagate_batch(pccp_fsolver *s, int32_t nbox, const float *lb_in,
+                              const float *ub_in, float *lb_out, float *ub_out,
+                              int32_t *status, int32_t *sweeps);
 
 /* ---- LDS peaks ----------------------------------------------------------
  * The propagation loop's store lives in LDS (§5: the shared-memory store was

@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["pccp_kernels.hip", "pccp_micro.hip", "pccp_abi.cpp"]
+SOURCES = ["pccp_kernels.hip", "pccp_micro.hip", "pccp_float.hip", "pccp_abi.cpp"]
 LIB = os.path.join(HERE, "libpccp.so")
 ARCH = os.environ.get("PCCP_OFFLOAD_ARCH", "gfx950")
 

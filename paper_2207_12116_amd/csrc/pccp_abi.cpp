@@ -50,6 +50,9 @@ struct pccp_model {
     std::vector<int32_t> reif;  // 4 per item: b, si, sj, d
     std::vector<int32_t> dec;
     int32_t objective = -1;
+    // guarded commands: 4 per command (x, side, k, div); guards (y, side, c)
+    // and terms (a, y) by CSR pointers
+    std::vector<int32_t> cmd, cmd_gptr{0}, guard, cmd_tptr{0}, cterm;
 };
 
 extern "C" int32_t pccp_model_create(pccp_model **out)
@@ -98,6 +101,22 @@ extern "C" int32_t pccp_model_add_reified_overlap(pccp_model *m, int32_t b, int3
     return PCCP_OK;
 }
 
+extern "C" int32_t pccp_model_add_guarded(pccp_model *m, int32_t x, int32_t side, int32_t k,
+                                          int32_t div, int32_t nguards, const int32_t *gvar,
+                                          const int32_t *gside, const int32_t *gc, int32_t nterms,
+                                          const int32_t *coef, const int32_t *var)
+{
+    if (!m || nguards < 0 || nterms < 0 || (nguards > 0 && (!gvar || !gside || !gc)) ||
+        (nterms > 0 && (!coef || !var)))
+        return fail(PCCP_E_INVALID_ARG, "pccp_model_add_guarded: bad arguments");
+    m->cmd.insert(m->cmd.end(), {x, side, k, div});
+    for (int32_t g = 0; g < nguards; ++g) m->guard.insert(m->guard.end(), {gvar[g], gside[g], gc[g]});
+    m->cmd_gptr.push_back((int32_t)(m->guard.size() / 3));
+    for (int32_t t = 0; t < nterms; ++t) m->cterm.insert(m->cterm.end(), {coef[t], var[t]});
+    m->cmd_tptr.push_back((int32_t)(m->cterm.size() / 2));
+    return PCCP_OK;
+}
+
 extern "C" int32_t pccp_model_set_decision_vars(pccp_model *m, int32_t n, const int32_t *vars)
 {
     if (!m || n < 0 || (n > 0 && !vars))
@@ -128,10 +147,13 @@ extern "C" int32_t pccp_model_info(const pccp_model *m, int32_t *nvars, int32_t 
 // ------------------------------------------------------------------ model files
 // Format (little-endian): the line "PCCP-MODEL 1", one line of JSON with
 // the top-level integer fields nvars, nrows, nterms, nreif, ndec and
-// objective (other fields, e.g. a generator's parameters, are ignored),
-// then the int32 arrays lb[nvars], ub[nvars], row_ptr[nrows + 1],
-// coef[nterms], var[nterms], rhs[nrows], reif[4 nreif] (b, si, sj, d),
-// dec[ndec].
+// objective, and optionally ncmd, nguards, ncterms (absent = 0; other
+// fields, e.g. a generator's parameters, are ignored), then the int32
+// arrays lb[nvars], ub[nvars], row_ptr[nrows + 1], coef[nterms],
+// var[nterms], rhs[nrows], reif[4 nreif] (b, si, sj, d), dec[ndec], and
+// when ncmd > 0: cmd[4 ncmd] (x, side, k, div), cmd_gptr[ncmd + 1],
+// guard[3 nguards] (y, side, c), cmd_tptr[ncmd + 1], cterm[2 ncterms]
+// (a, y).
 static const char kModelMagic[] = "PCCP-MODEL 1\n";
 
 // value of the top-level integer field `key` of a one-line JSON object
@@ -171,18 +193,22 @@ extern "C" int32_t pccp_model_save_file(const pccp_model *m, const char *path)
     if (!m || !path) return fail(PCCP_E_INVALID_ARG, "pccp_model_save_file: bad arguments");
     FILE *f = fopen(path, "wb");
     if (!f) return fail(PCCP_E_INVALID_ARG, std::string("pccp_model_save_file: cannot open ") + path);
-    char hdr[256];
+    char hdr[320];
+    const size_t ncmd = m->cmd.size() / 4;
     snprintf(hdr, sizeof(hdr),
              "{\"nvars\": %zu, \"nrows\": %zu, \"nterms\": %zu, \"nreif\": %zu, \"ndec\": %zu, "
-             "\"objective\": %d}\n",
+             "\"objective\": %d, \"ncmd\": %zu, \"nguards\": %zu, \"ncterms\": %zu}\n",
              m->lb.size(), m->rhs.size(), m->coef.size(), m->reif.size() / 4, m->dec.size(),
-             (int)m->objective);
+             (int)m->objective, ncmd, m->guard.size() / 3, m->cterm.size() / 2);
     bool ok = fputs(kModelMagic, f) >= 0 && fputs(hdr, f) >= 0;
     auto put = [&](const std::vector<int32_t> &v) {
         if (ok && !v.empty()) ok = fwrite(v.data(), 4, v.size(), f) == v.size();
     };
     put(m->lb); put(m->ub); put(m->row_ptr); put(m->coef); put(m->var); put(m->rhs);
     put(m->reif); put(m->dec);
+    if (ncmd > 0) {
+        put(m->cmd); put(m->cmd_gptr); put(m->guard); put(m->cmd_tptr); put(m->cterm);
+    }
     ok = (fclose(f) == 0) && ok;
     return ok ? PCCP_OK : fail(PCCP_E_INVALID_ARG, std::string("pccp_model_save_file: write failed: ") + path);
 }
@@ -203,13 +229,21 @@ extern "C" int32_t pccp_model_load_file(const char *path, pccp_model **out)
         return ch == '\n';
     };
     std::string magic, hdr;
-    int64_t V = -1, R = -1, T = -1, Q = -1, D = -1, obj = -2;
+    int64_t V = -1, R = -1, T = -1, Q = -1, D = -1, obj = -2, NC = 0, NG = 0, NT = 0;
+    // an optional field: absent is 0, present must be an integer
+    auto opt_int = [&](const char *key, int64_t &out) {
+        if (hdr.find(std::string("\"") + key + "\"") == std::string::npos) { out = 0; return true; }
+        return json_top_int(hdr, key, out);
+    };
     if (!line(magic) || magic + "\n" != kModelMagic || !line(hdr) ||
         !json_top_int(hdr, "nvars", V) || !json_top_int(hdr, "nrows", R) ||
         !json_top_int(hdr, "nterms", T) || !json_top_int(hdr, "nreif", Q) ||
         !json_top_int(hdr, "ndec", D) || !json_top_int(hdr, "objective", obj) || V < 0 ||
         V > kMaxVars || R < 0 || T < 0 || Q < 0 || D < 0 || obj < -1 || obj >= V ||
-        R > INT32_MAX - 1 || T > INT32_MAX || Q > INT32_MAX / 4) {
+        R > INT32_MAX - 1 || T > INT32_MAX || Q > INT32_MAX / 4 ||
+        !opt_int("ncmd", NC) || !opt_int("nguards", NG) || !opt_int("ncterms", NT) ||
+        NC < 0 || NG < 0 || NT < 0 || NC > INT32_MAX / 4 - 1 || NG > INT32_MAX / 3 ||
+        NT > INT32_MAX / 2 || (NC == 0 && (NG > 0 || NT > 0))) {
         fclose(f);
         return fail(PCCP_E_MODEL, std::string("pccp_model_load_file: bad header in ") + path);
     }
@@ -223,6 +257,10 @@ extern "C" int32_t pccp_model_load_file(const char *path, pccp_model **out)
     };
     get(m->lb, V); get(m->ub, V); get(m->row_ptr, R + 1); get(m->coef, T); get(m->var, T);
     get(m->rhs, R); get(m->reif, 4 * Q); get(m->dec, D);
+    if (NC > 0) {
+        get(m->cmd, 4 * NC); get(m->cmd_gptr, NC + 1); get(m->guard, 3 * NG);
+        get(m->cmd_tptr, NC + 1); get(m->cterm, 2 * NT);
+    }
     const bool at_end = ok && fgetc(f) == EOF;
     fclose(f);
     if (ok && at_end) {
@@ -230,6 +268,13 @@ extern "C" int32_t pccp_model_load_file(const char *path, pccp_model **out)
         // at least one term per row (as pccp_model_add_linear_le builds it)
         ok = m->row_ptr[0] == 0 && m->row_ptr[R] == T;
         for (int64_t r = 0; ok && r < R; ++r) ok = m->row_ptr[r + 1] > m->row_ptr[r];
+        // the command pointers run from 0 to their counts without decreasing
+        if (ok && NC > 0) {
+            ok = m->cmd_gptr[0] == 0 && m->cmd_gptr[NC] == NG && m->cmd_tptr[0] == 0 &&
+                 m->cmd_tptr[NC] == NT;
+            for (int64_t q = 0; ok && q < NC; ++q)
+                ok = m->cmd_gptr[q + 1] >= m->cmd_gptr[q] && m->cmd_tptr[q + 1] >= m->cmd_tptr[q];
+        }
     }
     if (!ok || !at_end) {
         delete m;
@@ -254,6 +299,10 @@ struct Compiled {
     std::vector<int2> brows;
     std::vector<uint32_t> bterms;
     int32_t bgroup = 4, bchunks = 1, nbterms = 0;
+    // guarded commands (see pccp_types.h, kind 5)
+    std::vector<int4> cmds;
+    std::vector<uint32_t> ccnt;
+    std::vector<int2> cent;
     // learned-branching tables (see pccp_types.h)
     std::vector<float> fstat;
     std::vector<int32_t> fr_ptr, fb_ptr, fb;
@@ -298,6 +347,15 @@ static void compile_adjacency(Compiled &c)
     for (size_t i = 0; i < c.brows.size(); ++i)
         for (int32_t t = 0; t < c.brows[i].y; ++t)
             add((int32_t)(c.bterms[SL * i + t] & 0xffff), (uint32_t)i, 3, kAdjLb);
+    // a guarded command reads the bound each guard tests and the bound each
+    // term of f is read through (a variable read twice is listed twice)
+    for (size_t q = 0; q < c.cmds.size(); ++q) {
+        const int ng = (int)(c.ccnt[q] & 0xffffu), nt = (int)(c.ccnt[q] >> 16), e0 = c.cmds[q].w;
+        for (int u = 0; u < ng + nt; ++u) {
+            const uint32_t w = (uint32_t)c.cent[e0 + u].x;
+            add((int32_t)(w & 0xffff), (uint32_t)q, 4, ((w >> 16) & 1u) ? kAdjUb : kAdjLb);
+        }
+    }
     c.adj_ptr.assign(V + 1, 0);
     c.adj.clear();
     for (int32_t x = 0; x < V; ++x) {
@@ -473,10 +531,53 @@ static int32_t compile_model(const pccp_model *m, Compiled &c)
         c.reif.push_back(make_int2((int32_t)((uint32_t)it[0] | ((uint32_t)it[1] << 16)),
                                    (int32_t)((uint32_t)it[2] | ((uint32_t)(uint16_t)(int16_t)it[3] << 16))));
     }
+    // guarded commands: the targets, guards and terms in range, div >= 1, and
+    // |k| + sum |a| * |bound| < 2^30 so that f fits in int32
+    const size_t NCMD = m->cmd.size() / 4;
+    if (m->cmd_gptr.size() != NCMD + 1 || m->cmd_tptr.size() != NCMD + 1)
+        return fail(PCCP_E_MODEL, "guarded commands: inconsistent pointers");
+    for (size_t q = 0; q < NCMD; ++q) {
+        const int32_t *cm = &m->cmd[4 * q];
+        const std::string tag = "guarded command " + std::to_string(q);
+        if (cm[0] < 0 || cm[0] >= V) return fail(PCCP_E_MODEL, tag + ": target out of range");
+        if (cm[1] != 0 && cm[1] != 1) return fail(PCCP_E_MODEL, tag + ": side must be 0 or 1");
+        if (cm[3] < 1) return fail(PCCP_E_MODEL, tag + ": div must be >= 1");
+        const int32_t g0 = m->cmd_gptr[q], g1 = m->cmd_gptr[q + 1];
+        const int32_t t0 = m->cmd_tptr[q], t1 = m->cmd_tptr[q + 1];
+        if (g0 < 0 || g1 < g0 || (size_t)g1 * 3 > m->guard.size() || t0 < 0 || t1 < t0 ||
+            (size_t)t1 * 2 > m->cterm.size())
+            return fail(PCCP_E_MODEL, tag + ": inconsistent pointers");
+        if (g1 - g0 > 65535 || t1 - t0 > 65535)
+            return fail(PCCP_E_UNSUPPORTED, tag + ": more than 65535 guards or terms");
+        int64_t tot = std::llabs((int64_t)cm[2]);
+        c.cmds.push_back(make_int4((int32_t)((uint32_t)cm[0] | ((uint32_t)cm[1] << 16)), cm[2], cm[3],
+                                   (int32_t)c.cent.size()));
+        c.ccnt.push_back((uint32_t)(g1 - g0) | ((uint32_t)(t1 - t0) << 16));
+        for (int32_t g = g0; g < g1; ++g) {
+            const int32_t *gd = &m->guard[3 * (size_t)g];
+            if (gd[0] < 0 || gd[0] >= V) return fail(PCCP_E_MODEL, tag + ": guard variable out of range");
+            if (gd[1] != 0 && gd[1] != 1) return fail(PCCP_E_MODEL, tag + ": guard side must be 0 or 1");
+            c.cent.push_back(make_int2((int32_t)((uint32_t)gd[0] | ((uint32_t)gd[1] << 16)), gd[2]));
+        }
+        for (int32_t t = t0; t < t1; ++t) {
+            const int32_t a = m->cterm[2 * (size_t)t], y = m->cterm[2 * (size_t)t + 1];
+            if (y < 0 || y >= V) return fail(PCCP_E_MODEL, tag + ": term variable out of range");
+            if (a == 0) return fail(PCCP_E_MODEL, tag + ": zero coefficient");
+            tot += std::llabs((int64_t)a) * mag[y];
+            if (tot >= LIM) return fail(PCCP_E_OVERFLOW, tag + ": |k| + sum |a|*|bound| >= 2^30");
+            // the bound that keeps f monotone: lb for a > 0 in a lower-bound
+            // tell, ub for a < 0; the opposite in an upper-bound tell
+            const bool reads_ub = cm[1] == 0 ? a < 0 : a > 0;
+            c.cent.push_back(make_int2((int32_t)((uint32_t)y | ((uint32_t)reads_ub << 16)), a));
+        }
+        if (tot >= LIM) return fail(PCCP_E_OVERFLOW, tag + ": |k| >= 2^30");
+    }
+    if (c.cent.size() > (size_t)INT32_MAX)
+        return fail(PCCP_E_UNSUPPORTED, "guarded commands: too many guards and terms");
     compile_features(m, c);
     // adjacency entries hold 16-bit indices
     if (c.diff.size() <= 65536 && c.reif.size() <= 65536 && c.rows.size() <= 65536 &&
-        c.brows.size() <= 65536)
+        c.brows.size() <= 65536 && c.cmds.size() <= 65536)
         compile_adjacency(c);
     else
         c.adj_ptr.assign(c.nvars + 1, 0);
@@ -621,7 +722,10 @@ extern "C" int32_t pccp_solver_create(const pccp_model *m, const pccp_config *cf
     const size_t o_fb = o_fbp + al(4 * c.fb_ptr.size());
     const size_t o_adjp = o_fb + al(4 * c.fb.size());
     const size_t o_adj = o_adjp + al(4 * c.adj_ptr.size());
-    const size_t total = o_adj + al(4 * c.adj.size()) + 256;
+    const size_t o_cmd = o_adj + al(4 * c.adj.size());
+    const size_t o_ccnt = o_cmd + al(16 * c.cmds.size());
+    const size_t o_cent = o_ccnt + al(4 * c.ccnt.size());
+    const size_t total = o_cent + al(8 * c.cent.size()) + 256;
     rc = s->tables.ensure(total);
     if (rc == PCCP_OK) rc = s->dmodel.ensure(sizeof(DevModel));
     if (rc != PCCP_OK) { delete s; return rc; }
@@ -644,6 +748,9 @@ extern "C" int32_t pccp_solver_create(const pccp_model *m, const pccp_config *cf
     put(o_fb, c.fb.data(), 4 * c.fb.size());
     put(o_adjp, c.adj_ptr.data(), 4 * c.adj_ptr.size());
     put(o_adj, c.adj.data(), 4 * c.adj.size());
+    put(o_cmd, c.cmds.data(), 16 * c.cmds.size());
+    put(o_ccnt, c.ccnt.data(), 4 * c.ccnt.size());
+    put(o_cent, c.cent.data(), 8 * c.cent.size());
     DevModel &dm = s->hmodel;
     dm.nvars = c.nvars;
     dm.ndiff = (int32_t)c.diff.size();
@@ -664,7 +771,10 @@ extern "C" int32_t pccp_solver_create(const pccp_model *m, const pccp_config *cf
     dm.bgroup = c.bgroup;
     dm.bchunks = c.bchunks;
     dm.nbterms = c.nbterms;
-    dm.pad0 = 0;
+    dm.ncmd = (int32_t)c.cmds.size();
+    dm.cmds = reinterpret_cast<const int4 *>(base + o_cmd);
+    dm.ccnt = reinterpret_cast<const uint32_t *>(base + o_ccnt);
+    dm.cent = reinterpret_cast<const int2 *>(base + o_cent);
     dm.brows = reinterpret_cast<const int2 *>(base + o_brows);
     dm.bterms = reinterpret_cast<const uint32_t *>(base + o_bterms);
     dm.lb0 = reinterpret_cast<const int32_t *>(base + o_lb);
@@ -800,7 +910,7 @@ extern "C" int32_t pccp_get_domains(pccp_solver *s, int32_t *lb, int32_t *ub, in
 struct ShapeNeed {
     int max_vars = 0;
     size_t max_desc = 0;
-    int max_items[4] = {0, 0, 0, 0};
+    int max_items[kDepKinds] = {0, 0, 0, 0, 0};   // per kind; [4] = guarded commands
     int feat_ndec = 0;        // learned branching: feature scratch per candidate
     bool lists_ok = false;    // item lists (every kind <= 65536 propagators)
     bool dep_ok = false;      // adjacency of every instance built
@@ -813,18 +923,19 @@ struct ShapeNeed {
 // table of that kind).
 struct DepLayout {
     int vshift = 0, qw = 0;
-    int wcap[4] = {0, 0, 0, 0};
+    int wcap[kDepKinds] = {0, 0, 0, 0, 0};
     int jcap = 0;       // two-phase expansion for workgroups of 8 or more wavefronts
 };
 
-static DepLayout dep_layout(int max_vars, const int items[4], int scale)
+static DepLayout dep_layout(int max_vars, const int items[kDepKinds], int scale)
 {
     DepLayout d;
     const int Vp = (max_vars + 3) & ~3;
     while ((32 << d.vshift) < Vp) ++d.vshift;
+    // queued bits for the kinds listed at most once (all but commands)
     const int64_t tot = (int64_t)items[0] + items[1] + items[2] + items[3];
     d.qw = (int)((tot + 31) / 32);
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < kDepKinds; ++k)
         d.wcap[k] = std::min(items[k], std::max(64, (items[k] + scale - 1) / scale));
     return d;
 }
@@ -916,7 +1027,7 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
     int32_t rc = check_cfg(cfg);
     if (rc != PCCP_OK) return rc;
     int max_vars = 0, max_ndec = 1;
-    int max_items[4] = {0, 0, 0, 0};
+    int max_items[kDepKinds] = {0, 0, 0, 0, 0};
     size_t max_desc = 0;
     for (int i = 0; i < n; ++i) {
         if (!sv[i]) return fail(PCCP_E_INVALID_ARG, "search: solver is NULL");
@@ -930,6 +1041,7 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
         max_items[1] = std::max(max_items[1], (int)sv[i]->c.reif.size());
         max_items[2] = std::max(max_items[2], (int)sv[i]->c.rows.size());
         max_items[3] = std::max(max_items[3], (int)sv[i]->c.brows.size());
+        max_items[4] = std::max(max_items[4], (int)sv[i]->c.cmds.size());
     }
     HIPCHK(hipSetDevice(s0->device));
     const bool learned = s0->branching == PCCP_BRANCH_MLP && s0->mlp != nullptr;
@@ -937,57 +1049,77 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
     ShapeNeed need;
     need.max_vars = max_vars;
     need.max_desc = max_desc;
-    for (int k = 0; k < 4; ++k) need.max_items[k] = max_items[k];
+    for (int k = 0; k < kDepKinds; ++k) need.max_items[k] = max_items[k];
     need.feat_ndec = learned ? max_ndec : 0;
     // list entries are 16-bit descriptor indices
+    // item lists leave the guarded commands out; work lists hold them too
     need.lists_ok = *std::max_element(max_items, max_items + 4) <= 65536;
-    need.dep_ok = need.lists_ok;
+    need.dep_ok = *std::max_element(max_items, max_items + kDepKinds) <= 65536;
     rc = choose_shape(cfg, need, s0->num_cus, s0->lds_max, sh);
     if (rc != PCCP_OK) return rc;
     const int qcap = cfg.queue_cap > 0 ? std::max(cfg.queue_cap, n) : std::max(4 * sh.grid, n + sh.grid);
     const int slot_bytes = (int)(((size_t)sizeof(RecHdr) + sizeof(int2) * (size_t)cfg.max_depth + 15) & ~size_t(15));
     const int Vp = (max_vars + 3) & ~3;
-    Workspace &ws = s0->ws;
-    if ((rc = ws.models.ensure(sizeof(DevModel) * n)) ||
-        (rc = ws.inst.ensure(sizeof(InstState) * n)) ||
-        (rc = ws.globals.ensure(sizeof(SearchGlobals))) ||
-        (rc = ws.qseq.ensure(sizeof(unsigned long long) * qcap)) ||
-        (rc = ws.qdata.ensure((size_t)slot_bytes * qcap)) ||
-        (rc = ws.best.ensure(sizeof(int32_t) * (size_t)n * max_ndec)))
-        return rc;
-    if (!sh.k.root_lds && (rc = ws.roots.ensure(sizeof(int32_t) * 2 * (size_t)Vp * sh.grid)))
-        return rc;
     // trail: 8 entries of 16 bytes per store variable per workgroup, within
     // [4096, 2^18] entries; a path whose changes do not fit falls back to
     // recomputation
     const int tcap = !sh.k.dep ? 0 : cfg.trail_cap > 0 ? cfg.trail_cap
                                                        : std::min(std::max(8 * Vp, 4096), 1 << 18);
-    if (sh.k.dep && (rc = ws.trail.ensure(sizeof(int4) * (size_t)tcap * sh.grid)))
-        return rc;
-    if ((rc = ws.gstack.ensure(sizeof(int4) * (size_t)cfg.max_depth * sh.grid)))
-        return rc;
+    // the pieces of the workspace, in bytes (0 = not used by this shape)
+    const size_t z_models = sizeof(DevModel) * n, z_inst = sizeof(InstState) * n;
+    const size_t z_glob = sizeof(SearchGlobals), z_qseq = sizeof(unsigned long long) * qcap;
+    const size_t z_qdata = (size_t)slot_bytes * qcap, z_best = sizeof(int32_t) * (size_t)n * max_ndec;
+    const size_t z_roots = sh.k.root_lds ? 0 : sizeof(int32_t) * 2 * (size_t)Vp * sh.grid;
+    const size_t z_trail = sh.k.dep ? sizeof(int4) * (size_t)tcap * sh.grid : 0;
+    const size_t z_gstack = sizeof(int4) * (size_t)cfg.max_depth * sh.grid;
+    DevModel *w_models = nullptr;
+    InstState *w_inst = nullptr;
+    SearchGlobals *w_glob = nullptr;
+    unsigned long long *w_qseq = nullptr;
+    char *w_qdata = nullptr;
+    int32_t *w_best = nullptr, *w_roots = nullptr;
+    int4 *w_trail = nullptr, *w_gstack = nullptr;
     const bool keep_sols = (mode == PCCP_ENUMERATE && n == 1 && cfg.sol_cap > 0);
-    if (keep_sols && (rc = s0->sols.ensure(sizeof(int32_t) * (size_t)cfg.sol_cap * std::max(s0->c.ndec, 1))))
-        return rc;
+    {
+        Workspace &ws = s0->ws;
+        if ((rc = ws.models.ensure(z_models)) || (rc = ws.inst.ensure(z_inst)) ||
+            (rc = ws.globals.ensure(z_glob)) || (rc = ws.qseq.ensure(z_qseq)) ||
+            (rc = ws.qdata.ensure(z_qdata)) || (rc = ws.best.ensure(z_best)))
+            return rc;
+        if (z_roots && (rc = ws.roots.ensure(z_roots))) return rc;
+        if (z_trail && (rc = ws.trail.ensure(z_trail))) return rc;
+        if ((rc = ws.gstack.ensure(z_gstack))) return rc;
+        if (keep_sols && (rc = s0->sols.ensure(sizeof(int32_t) * (size_t)cfg.sol_cap * std::max(s0->c.ndec, 1))))
+            return rc;
+        w_models = ws.models.as<DevModel>();
+        w_inst = ws.inst.as<InstState>();
+        w_glob = ws.globals.as<SearchGlobals>();
+        w_qseq = ws.qseq.as<unsigned long long>();
+        w_qdata = ws.qdata.as<char>();
+        w_best = ws.best.as<int32_t>();
+        w_roots = z_roots ? ws.roots.as<int32_t>() : nullptr;
+        w_trail = z_trail ? ws.trail.as<int4>() : nullptr;
+        w_gstack = ws.gstack.as<int4>();
+    }
     std::vector<DevModel> hm(n);
     for (int i = 0; i < n; ++i) hm[i] = sv[i]->hmodel;
-    HIPCHK(hipMemcpyAsync(ws.models.p, hm.data(), sizeof(DevModel) * n, hipMemcpyHostToDevice, s0->stream));
+    HIPCHK(hipMemcpyAsync(w_models, hm.data(), sizeof(DevModel) * n, hipMemcpyHostToDevice, s0->stream));
 
     // zeroed bytewise: the struct's bytes, padding included, key the graph cache
     SearchParams P;
     memset(&P, 0, sizeof(P));
-    P.models = ws.models.as<DevModel>();
-    P.inst = ws.inst.as<InstState>();
+    P.models = w_models;
+    P.inst = w_inst;
     P.ninst = n;
     P.mode = mode;
     P.branching = learned ? 2 : (s0->branching == PCCP_BRANCH_INPUT_ORDER ? 1 : 0);
     P.max_depth = cfg.max_depth;
-    P.g = ws.globals.as<SearchGlobals>();
-    P.q_seq = ws.qseq.as<unsigned long long>();
-    P.q_data = ws.qdata.as<char>();
+    P.g = w_glob;
+    P.q_seq = w_qseq;
+    P.q_data = w_qdata;
     P.qcap = qcap;
     P.slot_bytes = slot_bytes;
-    P.root_scratch = sh.k.root_lds ? nullptr : ws.roots.as<int32_t>();
+    P.root_scratch = sh.k.root_lds ? nullptr : w_roots;
     P.max_vars = max_vars;
     P.donate = sh.grid > 1 ? 1 : 0;
     P.node_limit = lim ? lim->node_limit : 0;
@@ -996,19 +1128,20 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
     P.cancel = lim ? lim->cancel : nullptr;
     P.sol_buf = keep_sols ? s0->sols.as<int32_t>() : nullptr;
     P.sol_cap = keep_sols ? cfg.sol_cap : 0;
-    P.best_vals = ws.best.as<int32_t>();
+    P.best_vals = w_best;
     P.max_ndec = max_ndec;
     P.mlp = learned ? reinterpret_cast<const uint16_t *>(s0->mlp) : nullptr;
     for (int k = 0; k < 4; ++k) P.max_items[k] = max_items[k];
     P.dep_vshift = sh.dep.vshift;
     P.dep_qw = sh.dep.qw;
-    for (int k = 0; k < 4; ++k) P.dep_wcap[k] = sh.dep.wcap[k];
+    for (int k = 0; k < kDepKinds; ++k) P.dep_wcap[k] = sh.dep.wcap[k];
     P.dep_jcap = sh.dep.jcap;
-    P.trail = sh.k.dep ? ws.trail.as<int4>() : nullptr;
+    P.trail = sh.k.dep ? w_trail : nullptr;
     P.tcap = tcap;
-    P.gstack = ws.gstack.as<int4>();
+    P.gstack = w_gstack;
 
     if (cfg.launch == 0) {
+        Workspace &ws = s0->ws;
         // the graph bakes in the launch parameters: rebuild it when they change
         std::vector<char> key(sizeof(P) + 8 * sizeof(int64_t));
         memcpy(key.data(), &P, sizeof(P));
@@ -1180,12 +1313,67 @@ extern "C" int32_t pccp_solver_capacity(const pccp_solver *s, int32_t *wgs_per_c
     need.max_items[1] = (int)s->c.reif.size();
     need.max_items[2] = (int)s->c.rows.size();
     need.max_items[3] = (int)s->c.brows.size();
+    need.max_items[4] = (int)s->c.cmds.size();
     need.lists_ok = *std::max_element(need.max_items, need.max_items + 4) <= 65536;
-    need.dep_ok = need.lists_ok;
+    need.dep_ok = *std::max_element(need.max_items, need.max_items + kDepKinds) <= 65536;
     int32_t rc = choose_shape(cfg, need, s->num_cus, s->lds_max, sh);
     if (rc != PCCP_OK) return rc;
     if (wgs_per_cu) *wgs_per_cu = sh.wgs_per_cu;
     if (num_cus) *num_cus = s->num_cus;
+    return PCCP_OK;
+}
+
+// ------------------------------------------------------------------ incremental propagation
+extern "C" int32_t pccp_propagate_batch_incr(pccp_solver *s, int32_t nbox, const int32_t *lb_in,
+                                             const int32_t *ub_in, const int32_t *dvar,
+                                             const int32_t *dlo, const int32_t *dhi,
+                                             int32_t *lb_out, int32_t *ub_out, int32_t *status,
+                                             int32_t *sweeps)
+{
+    if (!s || nbox < 0 || (nbox > 0 && (!lb_in || !ub_in || !dvar || !dlo || !dhi || !lb_out ||
+                                        !ub_out || !status)))
+        return fail(PCCP_E_INVALID_ARG, "pccp_propagate_batch_incr: bad arguments");
+    const Compiled &c = s->c;
+    const int items[kDepKinds] = {(int)c.diff.size(), (int)c.reif.size(), (int)c.rows.size(),
+                                  (int)c.brows.size(), (int)c.cmds.size()};
+    if (*std::max_element(items, items + kDepKinds) > 65536)
+        return fail(PCCP_E_UNSUPPORTED,
+                    "dependency-driven propagation needs at most 65536 propagators of each kind");
+    if (nbox == 0) return PCCP_OK;
+    const int block = s->cfg.wg_size;
+    // the longest work lists that fit next to the store (a sweep whose list
+    // would overflow runs that kind's whole table)
+    DepLayout dl;
+    size_t lds = 0;
+    bool fits = false;
+    for (int li = 0; li < 8 && !fits; ++li) {
+        dl = dep_layout(c.nvars, items, 1 << li);
+        dl.jcap = block >= 512 ? 512 : 0;
+        lds = propagate_lds_bytes(c.nvars, 0, false) + dep_lds_bytes(dl.vshift, dl.qw, dl.wcap, dl.jcap);
+        fits = lds <= s->lds_max;
+    }
+    if (!fits)
+        return fail(PCCP_E_LDS_CAPACITY, "the store and the dependency bitmaps do not fit in LDS");
+    IncrParams A;
+    memset(&A, 0, sizeof(A));
+    A.nbox = nbox;
+    A.dep_vshift = dl.vshift;
+    A.dep_qw = dl.qw;
+    A.dep_jcap = dl.jcap;
+    for (int k = 0; k < kDepKinds; ++k) A.dep_wcap[k] = dl.wcap[k];
+    A.lb_in = lb_in;
+    A.ub_in = ub_in;
+    A.dvar = dvar;
+    A.dlo = dlo;
+    A.dhi = dhi;
+    A.lb_out = lb_out;
+    A.ub_out = ub_out;
+    A.status = status;
+    A.sweeps = sweeps;
+    const int grid = std::min(nbox, std::max(1, s->num_cus * 8));
+    HIPCHK(hipSetDevice(s->device));
+    HIPCHK(launch_propagate_incr(reinterpret_cast<const DevModel *>(s->dmodel.p), A, grid, block, lds,
+                                 s->stream));
     return PCCP_OK;
 }
 

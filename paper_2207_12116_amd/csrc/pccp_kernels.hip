@@ -5,10 +5,15 @@
 // Design (the paper's own GPU solver, §5, was written for a Turing laptop
 // GPU; this keeps what holds on gfx950 and changes the rest):
 //   * One workgroup per subproblem (§5: one block per subproblem).  The
-//     store of the subproblem (lb[], ub[] as int32 SoA) lives in LDS.
-//   * Every propagator runs every sweep (eventless propagation, §5).  Each
-//     lane takes descriptors t = tid, tid + W, ... of each kind in turn
-//     (§5, fixed point loop: strided loop over the propagators).
+//     store of the subproblem lives in LDS as one (lb, ub) int32 pair per
+//     variable (int2), so one 64-bit LDS read fetches both bounds.
+//   * Two propagation modes.  Every table every sweep (eventless, §5): each
+//     lane takes descriptors t = tid, tid + W, ... of each kind in turn (§5,
+//     fixed point loop: strided loop over the propagators).  Dependency-
+//     driven (the improvement §6 names): a sweep runs only the propagators
+//     that read a bound the previous sweep tightened, found through a
+//     variable -> propagator adjacency; the same least fixed point by
+//     chaotic iteration (§3 Theorem 2).
 //   * A tell is a lattice join: LDS atomic max on lb, atomic min on ub
 //     (ds_max_i32 / ds_min_i32, no return).  The plain load + compare +
 //     store of the load/store compilation (§4) can lose an update when two
@@ -26,10 +31,13 @@
 //     crosses the opposite bound it read, which bounds the number of sweeps
 //     on failing stores, and confirmed by a scan of the store at the fixed
 //     point (§5: failure can be examined after the loop).
-//   * Search (§5): full recomputation on backtracking.  Each workgroup keeps
-//     the fixed point of its subproblem's root; a backtrack copies it back
-//     and re-applies the decisions of the new path.  Descending keeps the
-//     current store.  Embarrassingly parallel search with dynamically
+//   * Search (§5): each workgroup keeps the fixed point of its
+//     subproblem's root.  Descending keeps the current store.  A backtrack
+//     either undoes the path's changes from a trail (dependency-driven mode:
+//     the first tell of a node on a variable saves the bounds it had) or,
+//     where the trail overflowed or in the other modes, recomputes: copies
+//     the root back and re-applies the decisions of the new path (§5: full
+//     recomputation).  Embarrassingly parallel search with dynamically
 //     generated subproblems (§5): a workgroup donates the right branch
 //     closest to its subproblem root to a bounded lock-free MPMC queue when
 //     other workgroups are idle.
@@ -184,10 +192,10 @@ enum : int {
     C_SKIP = 27,                            // the record taken was dropped
     C_CNT = 12,                             // item-list counts: 5 words per list
                                             // (R, A, B) = 4 kinds, row terms
-    C_DCNT = 12,                            // or work-list counts: 6 words per set
-                                            // (2 sets) = 4 kinds, terms of kinds 3, 4
-    C_TTOP = 24,                            // entries pushed on the trail (dependency-driven
-    C_THI = 25,                             // deepest path level without a whole trail  only)
+    C_DCNT = 12,                            // or work-list counts: 7 words per set
+                                            // (2 sets) = 5 kinds, terms of kinds 3, 4
+    C_TTOP = 26,                            // entries pushed on the trail (dependency-driven
+    C_THI = 31,                             // deepest path level without a whole trail  only)
     C_JCNT = 28,                            // entries of the expansion's job list
     C_MAXW = 29,                            // deepest decision-stack level written (every mode)
     C_ATOM = 30,                            // lattice joins issued by the node's sweeps
@@ -200,6 +208,7 @@ struct View {
     int32_t nvars, ndiff, nreif, nrows, nterms, ndec, objective;
     int32_t row_group, row_chunks;
     int32_t nbrows, bgroup, bchunks, nbterms;
+    int32_t ncmd;
     const int2 *diff_;
     const int2 *reif_;
     const int4 *rows_;
@@ -209,6 +218,9 @@ struct View {
     const int32_t *dec_;
     const int32_t *adjp_;         // always global memory
     const uint32_t *adj_;
+    const int4 *cmds_;            // guarded commands: always global memory
+    const uint32_t *ccnt_;
+    const int2 *cent_;
     // Indices are non-negative: taking them as unsigned lets a global load
     // use a uniform base plus a 32-bit per-lane offset.
     __device__ __forceinline__ int2 brows(int t) const { return DL ? brows_[(uint32_t)t] : gread(brows_ + (uint32_t)t); }
@@ -220,6 +232,9 @@ struct View {
     __device__ __forceinline__ int32_t dec(int t) const { return DL ? dec_[(uint32_t)t] : gread(dec_ + (uint32_t)t); }
     __device__ __forceinline__ int32_t adjp(int x) const { return gread(adjp_ + (uint32_t)x); }
     __device__ __forceinline__ uint32_t adj(int t) const { return gread(adj_ + (uint32_t)t); }
+    __device__ __forceinline__ int4 cmd(int t) const { return gread(cmds_ + (uint32_t)t); }
+    __device__ __forceinline__ uint32_t ccnt(int t) const { return gread(ccnt_ + (uint32_t)t); }
+    __device__ __forceinline__ int2 cent(int t) const { return gread(cent_ + (uint32_t)t); }
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
@@ -255,6 +270,8 @@ __device__ inline View<false> view_global(const DevModel &m)
     v.terms_ = uptr(m.terms); v.dec_ = uptr(m.dec);
     v.brows_ = uptr(m.brows); v.bterms_ = uptr(m.bterms);
     v.adjp_ = uptr(m.adj_ptr); v.adj_ = uptr(m.adj);
+    v.ncmd = m.ncmd;
+    v.cmds_ = uptr(m.cmds); v.ccnt_ = uptr(m.ccnt); v.cent_ = uptr(m.cent);
     return v;
 }
 
@@ -293,6 +310,8 @@ __device__ inline View<true> stage_descriptors(const DevModel &m, char *dst)
     v.rows_ = rows; v.diff_ = diff; v.reif_ = reif; v.terms_ = terms; v.dec_ = dec;
     v.brows_ = brows; v.bterms_ = bterms;
     v.adjp_ = uptr(m.adj_ptr); v.adj_ = uptr(m.adj);
+    v.ncmd = m.ncmd;
+    v.cmds_ = uptr(m.cmds); v.ccnt_ = uptr(m.ccnt); v.cent_ = uptr(m.cent);
     return v;
 }
 
@@ -379,7 +398,7 @@ struct Dep {
     int32_t *jcnt;            // LDS word: entries in jobs (may pass jcap)
     int jcap;                 // 0: one-phase expansion
     int vshift, vmask, vw, qw;
-    int woff[4], wcap[4], qoff[4];
+    int woff[kDepKinds], wcap[kDepKinds], qoff[kDepKinds];
     int tcap;
     bool trail_on;
 };
@@ -872,6 +891,72 @@ __device__ __forceinline__ void sweep_brows(const View<DL> &v, int2 *st, const L
     }
 }
 
+// kind 5: guarded commands {g_1, ..., g_n} => x <- f (§3, guarded normal
+// form; §2, ask and tell).  One lane per command: the guards are entailment
+// tests on single bounds (lb(y) >= c or ub(y) <= c); when all hold, f =
+// k + sum_t a_t y_t is formed from the bounds that keep it monotone (for a
+// lower-bound tell: lb(y) when a > 0, ub(y) when a < 0; the opposite for an
+// upper-bound tell), divided by div with rounding toward the sound side
+// (ceil for lb, floor for ub), and joined into the target bound if tighter.
+// The model is validated so that |k| + sum |a_t| max |bound(y_t)| < 2^30:
+// f cannot overflow int32 on a store that has not failed.  Commands are not
+// compacted into item lists; they run whole-table in the every-table and
+// item-list modes, and from their work list in the dependency-driven mode.
+template <bool DL, bool MK = false>
+__device__ __forceinline__ void sweep_cmd(const View<DL> &v, int2 *st, const ListIO &io,
+                                          const Dep &dp, bool &chg, bool &bad, uint32_t &nat)
+{
+    const int tid = threadIdx.x, lane = tid & 63, W = blockDim.x, n = io.n;
+    for (int c0 = uni(tid - lane); c0 < n; c0 += W) {
+        const int t = c0 + lane;
+        bool fire = false, lbt = false;
+        int x = 0, nb = 0;
+        int2 dx = make_int2(0, 0);
+        if (t < n) {
+            const int q = io.in ? (int)io.in[t] : t;
+            const int4 c = v.cmd(q);
+            const uint32_t cn = v.ccnt(q);
+            const int ng = (int)(cn & 0xffffu), nt = (int)(cn >> 16), e0 = c.w;
+            bool hold = true;
+            for (int g = 0; g < ng && hold; ++g) {
+                const int2 e = v.cent(e0 + g);
+                const int2 d = dom(st, e.x & 0xffff);
+                hold = ((e.x >> 16) & 1) ? d.y <= e.y : d.x >= e.y;
+            }
+            if (hold) {
+                int f = c.y;
+                for (int u = 0; u < nt; ++u) {
+                    const int2 e = v.cent(e0 + ng + u);
+                    const int2 d = dom(st, e.x & 0xffff);
+                    f += e.y * (((e.x >> 16) & 1) ? d.y : d.x);
+                }
+                x = c.x & 0xffff;
+                lbt = ((c.x >> 16) & 1) == 0;
+                const int div = c.z;
+                dx = dom(st, x);
+                if (lbt) {
+                    nb = div == 1 ? f : -floor_div_pos(-f, div);
+                    fire = nb > dx.x;
+                } else {
+                    nb = div == 1 ? f : floor_div_pos(f, div);
+                    fire = nb < dx.y;
+                }
+            }
+        }
+        nat += lanes(fire);
+        if (fire) {
+            chg = true;
+            if (lbt) {
+                tell_m<MK, true>(st, dp, x, nb, dx);
+                bad |= nb > dx.y;
+            } else {
+                tell_m<MK, false>(st, dp, x, nb, dx);
+                bad |= nb < dx.x;
+            }
+        }
+    }
+}
+
 // The item lists of one node, per kind (0 difference rows, 1 reified items,
 // 2 linear rows, 3 Boolean rows): the first sweep runs in[k] (nin[k]
 // entries; nullptr = the whole table; tin = terms of the rows in in[2] and
@@ -879,12 +964,17 @@ __device__ __forceinline__ void sweep_brows(const View<DL> &v, int2 *st, const L
 // their counts in cnt[k] and the kept rows' terms in cnt[4]; later sweeps
 // run the kept lists.
 constexpr int kKinds = 4;
-constexpr int kKindsDep = 4;
+constexpr int kKindsDep = kDepKinds;
+constexpr int kDepSetWords = kDepKinds + 2;  // per set: the kinds' list lengths, then row terms
 constexpr int kListWords = kKinds + 1;
 // Item lists (the live mode) and work lists (the dependency-driven mode) are
 // never used together; each must stay clear of the words every mode uses.
 static_assert(C_CNT + 3 * kListWords <= C_SKIP, "item-list counts overlap C_SKIP");
-static_assert(C_DCNT + 2 * 6 <= C_TTOP, "work-list counts overlap the trail words");
+static_assert(C_DCNT + 2 * kDepSetWords <= C_TTOP, "work-list counts overlap the trail words");
+static_assert(C_TTOP != C_SKIP && C_TTOP != C_JCNT && C_TTOP != C_MAXW && C_TTOP != C_ATOM &&
+                  C_THI != C_SKIP && C_THI != C_JCNT && C_THI != C_MAXW && C_THI != C_ATOM &&
+                  C_THI < 32 && C_THI >= C_DCNT + 2 * kDepSetWords,
+              "the trail words need words of their own in the dependency-driven mode");
 static_assert(C_MAXW >= C_CNT + 3 * kListWords && C_MAXW != C_SKIP && C_MAXW != C_JCNT &&
                   C_MAXW < 32, "the stack word must lie outside every count range");
 static_assert(C_ATOM >= C_CNT + 3 * kListWords && C_ATOM != C_SKIP && C_ATOM != C_JCNT &&
@@ -935,9 +1025,10 @@ __device__ int propagate_wg(const View<DL> &v, int2 *st, int32_t *ctl, const Nod
         sweep_reif<DL, LEAN ? 2 : 4>(v, st, r, nodep, chg, bad, nat);
         sweep_rows<DL, LEAN ? 2 : 4>(v, st, w, nodep, chg, bad, nat);
         sweep_brows<DL, LEAN ? 1 : 2>(v, st, b, nodep, chg, bad, nat);
+        if (v.ncmd) sweep_cmd(v, st, ListIO{nullptr, v.ncmd, nullptr, nullptr, nullptr}, nodep, chg, bad, nat);
         ex[0] += (unsigned)d.n;
         ex[1] += (unsigned)r.n;
-        ex[2] += (unsigned)(w.n + b.n);
+        ex[2] += (unsigned)(w.n + b.n + v.ncmd);
         ex[3] += (unsigned)terms;
         const int flags = (__any(chg) ? 1 : 0) | (__any(bad) ? 2 : 0);
         if (lane == 0 && flags)
@@ -965,7 +1056,7 @@ __device__ int propagate_wg(const View<DL> &v, int2 *st, int32_t *ctl, const Nod
 // Work lists of the next sweep from the change bitmaps of the last one:
 // every propagator that reads a tightened bound (rows once: the queued bit
 // qm of a row is set when it is listed; see dep_queue).  Clears the bitmaps.  cnt: list
-// counts of the 4 kinds, then the terms of the listed rows of kinds 3 and
+// counts of the 5 kinds, then the terms of the listed rows of kinds 3 and
 // 4; zeroed by the caller before a barrier.  A count past its list's
 // capacity means the next sweep runs that kind's whole table.
 // Bitmap word w is read by wavefront w % nw, so the variables of one
@@ -977,12 +1068,13 @@ __device__ __forceinline__ void dep_queue(const View<DL> &v, const Dep &dp, int3
                                           uint32_t e, uint32_t reads)
 {
     const int lane = threadIdx.x & 63;
-    const int k = (int)((e >> 16) & 3u), idx = (int)(e & 0xffffu);
+    const int k = (int)((e >> 16) & 7u), idx = (int)(e & 0xffffu);
     bool fire = (e & reads) != 0;
-    // difference rows and reified items may be listed twice (two of their
-    // variables changed): running one twice costs less than the queued
-    // bit's round trip; rows, which visit many terms, are listed once
-    if (fire && k >= 2) {
+    // difference rows, reified items and guarded commands may be listed
+    // twice (two of their variables changed): running one twice costs less
+    // than the queued bit's round trip; rows, which visit many terms, are
+    // listed once
+    if (fire && (k == 2 || k == 3)) {
         const int p = idx + (k == 2 ? dp.qoff[2] : dp.qoff[3]);
         const uint32_t qb = 1u << (p & 31);
         fire = !(__hip_atomic_fetch_or(dp.qm + (p >> 5), qb, __ATOMIC_RELAXED,
@@ -1001,8 +1093,8 @@ __device__ __forceinline__ void dep_queue(const View<DL> &v, const Dep &dp, int3
             const int r = pos + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
             if (r < dp.wcap[kk]) dp.wl[dp.woff[kk] + r] = (uint16_t)idx;
-            if (kk >= 2)
-                __hip_atomic_fetch_add(cnt + 2 + kk, kk == 2 ? v.rows(idx).y : v.brows(idx).y,
+            if (kk == 2 || kk == 3)
+                __hip_atomic_fetch_add(cnt + kDepKinds + kk - 2, kk == 2 ? v.rows(idx).y : v.brows(idx).y,
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
@@ -1085,7 +1177,7 @@ __device__ void dep_expand_jobs(const View<DL> &v, const Dep &dp, int32_t *cnt)
     if (n > dp.jcap) {
         // too many changed variables: every table next sweep
         if (threadIdx.x == 0)
-            for (int k = 0; k < 4; ++k) cnt[k] = dp.wcap[k] + 1;
+            for (int k = 0; k < kDepKinds; ++k) cnt[k] = dp.wcap[k] + 1;
         return;
     }
     for (int r0 = 0; r0 < n; r0 += 64) {
@@ -1139,7 +1231,7 @@ __device__ int propagate_dep(const View<DL> &v, int2 *st, int32_t *ctl, const De
         ctl[C_FLAG2] = 0;
         ctl[C_POSTFAIL] = 0;
         *reinterpret_cast<unsigned long long *>(ctl + C_KEY) = ~0ull;
-        for (int k = 0; k < 12; ++k) ctl[C_DCNT + k] = 0;
+        for (int k = 0; k < 2 * kDepSetWords; ++k) ctl[C_DCNT + k] = 0;
         ctl[C_JCNT] = 0;
     }
     if (full)
@@ -1162,24 +1254,24 @@ __device__ int propagate_dep(const View<DL> &v, int2 *st, int32_t *ctl, const De
         lds_barrier();
     };
     if (!full) expand(ctl + C_DCNT);
-    const int tab[4] = {v.ndiff, v.nreif, v.nrows, v.nbrows};
+    const int tab[kDepKinds] = {v.ndiff, v.nreif, v.nrows, v.nbrows, v.ncmd};
     int slot = 0;
     bool all = full;
     for (;;) {
-        const int32_t *c = ctl + C_DCNT + 6 * set;
-        ListIO io[4];
-        bool whole[4];
+        const int32_t *c = ctl + C_DCNT + kDepSetWords * set;
+        ListIO io[kDepKinds];
+        bool whole[kDepKinds];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kDepKinds; ++k) {
             const int n = all ? 0 : uni(lds_ld(&c[k]));
             whole[k] = all || n > dp.wcap[k];
             io[k] = whole[k] ? ListIO{nullptr, tab[k], nullptr, nullptr, nullptr}
                              : ListIO{dp.wl + dp.woff[k], n, nullptr, nullptr, nullptr};
         }
-        const int terms = (whole[2] ? v.nterms : uni(lds_ld(&c[4]))) +
-                          (whole[3] ? v.nbterms : uni(lds_ld(&c[5])));
+        const int terms = (whole[2] ? v.nterms : uni(lds_ld(&c[kDepKinds]))) +
+                          (whole[3] ? v.nbterms : uni(lds_ld(&c[kDepKinds + 1])));
         if (tid == 0) {
-            for (int k = 0; k < 6; ++k) ctl[C_DCNT + 6 * (set ^ 1) + k] = 0;
+            for (int k = 0; k < kDepSetWords; ++k) ctl[C_DCNT + kDepSetWords * (set ^ 1) + k] = 0;
             ctl[C_JCNT] = 0;    // read by the last expansion before the barrier ending it
         }
         // the queued bits of the lists run now are cleared for the next expansion
@@ -1189,9 +1281,10 @@ __device__ int propagate_dep(const View<DL> &v, int2 *st, int32_t *ctl, const De
         sweep_reif<DL, LEAN ? 2 : 4, true>(v, st, io[1], dp, chg, bad, nat);
         sweep_rows<DL, LEAN ? 2 : 4, true>(v, st, io[2], dp, chg, bad, nat);
         sweep_brows<DL, LEAN ? 1 : 2, true>(v, st, io[3], dp, chg, bad, nat);
+        if (io[4].n) sweep_cmd<DL, true>(v, st, io[4], dp, chg, bad, nat);
         ex[0] += (unsigned)io[0].n;
         ex[1] += (unsigned)io[1].n;
-        ex[2] += (unsigned)(io[2].n + io[3].n);
+        ex[2] += (unsigned)(io[2].n + io[3].n + io[4].n);
         ex[3] += (unsigned)terms;
         const int flags = (__any(chg) ? 1 : 0) | (__any(bad) ? 2 : 0);
         if (lane == 0 && flags)
@@ -1215,7 +1308,7 @@ __device__ int propagate_dep(const View<DL> &v, int2 *st, int32_t *ctl, const De
         slot = next;
         set ^= 1;
         all = false;
-        expand(ctl + C_DCNT + 6 * set);
+        expand(ctl + C_DCNT + kDepSetWords * set);
     }
 }
 
@@ -1489,6 +1582,100 @@ __global__ __launch_bounds__(1024) void propagate_batch_kernel(
     }
 }
 
+// A tell by one thread outside the sweeps (a decision, the objective
+// bound), with marks and, with dp.trail_on, the trail.
+template <bool LB>
+__device__ __forceinline__ void tell_one(int2 *st, const Dep &dp, int x, int32_t v)
+{
+    const int2 d = st[x];
+    if (LB ? v <= d.x : v >= d.y) return;
+    tell_m<true, LB>(st, dp, x, v, d);
+}
+
+// ------------------------------------------- incremental fixed points
+// One workgroup per box.  The box is a fixed point of instance `m` joined
+// with one decision on one variable; only the propagators that read a bound
+// the decision tightened run in the first sweep, and each later sweep runs
+// those that read a bound the one before tightened (dependency-driven
+// propagation: a chaotic iteration that leaves out only propagators whose
+// inputs did not change, so it reaches the same least fixed point, §3
+// Theorem 2).  status[k]: 0 fixed point, 1 failed, -1 dvar[k] outside the
+// store (the box is copied unchanged).
+__global__ __launch_bounds__(1024) void propagate_incr_kernel(const DevModel *mp, IncrParams A)
+{
+    extern __shared__ __align__(16) char smem[];
+    const DevModel m = *mp;
+    const int tid = threadIdx.x, W = blockDim.x;
+    const int Vp = (m.nvars + 3) & ~3;
+    int32_t *ctl = reinterpret_cast<int32_t *>(smem);
+    int2 *st = reinterpret_cast<int2 *>(ctl + kCtlWords);
+    char *p = reinterpret_cast<char *>(st + Vp);
+    const int vw = 1 << A.dep_vshift;
+    Dep dp{};
+    dp.lm = reinterpret_cast<uint32_t *>(p);
+    dp.um = dp.lm + vw;
+    dp.tm = dp.um + vw;
+    p += align16(12 * (size_t)vw);
+    dp.qm = reinterpret_cast<uint32_t *>(p);
+    p += align16(4 * (size_t)A.dep_qw);
+    dp.wl = reinterpret_cast<uint16_t *>(p);
+    p += align16(2 * (size_t)(A.dep_wcap[0] + A.dep_wcap[1] + A.dep_wcap[2] + A.dep_wcap[3] +
+                              A.dep_wcap[4]));
+    dp.jobs = reinterpret_cast<uint32_t *>(p);
+    dp.jcap = A.dep_jcap;
+    dp.jcnt = ctl + C_JCNT;
+    dp.vshift = A.dep_vshift;
+    dp.vmask = vw - 1;
+    dp.vw = vw;
+    dp.qw = A.dep_qw;
+    const int items[kDepKinds] = {m.ndiff, m.nreif, m.nrows, m.nbrows, m.ncmd};
+    int wo = 0, qo = 0;
+    for (int k = 0; k < kDepKinds; ++k) {
+        dp.woff[k] = wo;
+        dp.wcap[k] = A.dep_wcap[k];
+        dp.qoff[k] = qo;
+        wo += A.dep_wcap[k];
+        qo += items[k];
+    }
+    dp.trail = nullptr;
+    dp.tcap = 0;
+    dp.ttop = ctl + C_TTOP;
+    dp.trail_on = false;
+    const View<false> v = view_global(m);
+    for (int w = tid; w < dp.qw; w += W) dp.qm[w] = 0;
+    for (int box = blockIdx.x; box < A.nbox; box += gridDim.x) {
+        const size_t off = (size_t)box * m.nvars;
+        load_box(st, A.lb_in + off, A.ub_in + off, m.nvars);
+        for (int w = tid; w < 3 * vw; w += W) dp.lm[w] = 0;
+        const int x = gread(A.dvar + box);
+        const bool valid = x >= 0 && x < m.nvars;
+        lds_barrier();
+        if (tid == 0 && valid) {
+            // the decision: joins with marks, so the first sweep runs the
+            // propagators that read the bounds it tightened
+            tell_one<true>(st, dp, x, gread(A.dlo + box));
+            tell_one<false>(st, dp, x, gread(A.dhi + box));
+        }
+        lds_barrier();
+        uint32_t nsw = 0, nat = 0;
+        unsigned long long ex[4] = {0, 0, 0, 0};
+        int rc = 0;
+        if (valid) rc = propagate_dep<false, true, true>(v, st, ctl, dp, false, nsw, ex, nat);
+        post_scan(v, st, ctl, 0, false);
+        const int failed = rc | lds_ld(&ctl[C_POSTFAIL]);
+        for (int y = tid; y < m.nvars; y += W) {
+            const int2 d = st[y];
+            gwrite(A.lb_out + off + y, d.x);
+            gwrite(A.ub_out + off + y, d.y);
+        }
+        if (tid == 0) {
+            A.status[box] = valid ? failed : -1;
+            if (A.sweeps) A.sweeps[box] = (int32_t)nsw;
+        }
+        lds_barrier();
+    }
+}
+
 // ------------------------------------------------------------ the queue
 // Bounded lock-free MPMC queue of subtree records (D. Vyukov's bounded
 // queue: one sequence number per slot).  Only lane 0 of a workgroup calls
@@ -1566,16 +1753,6 @@ __device__ unsigned long long solution_hash(const int2 *st, const View<DL> &v, i
 
 
 // ------------------------------------------------------------ search
-// A tell by one thread outside the sweeps (a decision, the objective
-// bound), with marks and, with dp.trail_on, the trail.
-template <bool LB>
-__device__ __forceinline__ void tell_one(int2 *st, const Dep &dp, int x, int32_t v)
-{
-    const int2 d = st[x];
-    if (LB ? v <= d.x : v >= d.y) return;
-    tell_m<true, LB>(st, dp, x, v, d);
-}
-
 // The decision stack.  Level k of the path is {var | side << 16 |
 // donated << 17, value, trail start of level k + 1, 0}; every level is kept
 // in this workgroup's slice of global memory and the kRing deepest levels
@@ -1682,7 +1859,8 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? 6 : 7) : 1) void s
         dp.qm = reinterpret_cast<uint32_t *>(p);
         p += align16(4 * (size_t)P.dep_qw);
         dp.wl = reinterpret_cast<uint16_t *>(p);
-        p += align16(2 * (size_t)(P.dep_wcap[0] + P.dep_wcap[1] + P.dep_wcap[2] + P.dep_wcap[3]));
+        p += align16(2 * (size_t)(P.dep_wcap[0] + P.dep_wcap[1] + P.dep_wcap[2] + P.dep_wcap[3] +
+                                  P.dep_wcap[4]));
         dp.jobs = reinterpret_cast<uint32_t *>(p);
         p += align16(4 * (size_t)P.dep_jcap);
         dp.jcap = P.dep_jcap;
@@ -1692,12 +1870,12 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? 6 : 7) : 1) void s
         dp.vw = vw;
         dp.qw = P.dep_qw;
         int wo = 0, qo = 0;
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kDepKinds; ++k) {
             dp.woff[k] = wo;
             dp.wcap[k] = P.dep_wcap[k];
             dp.qoff[k] = qo;
             wo += P.dep_wcap[k];
-            qo += P.max_items[k];
+            qo += k < 4 ? P.max_items[k] : 0;
         }
         dp.trail = P.trail + (size_t)blockIdx.x * (size_t)P.tcap;
         dp.tcap = P.tcap;
@@ -2393,10 +2571,11 @@ size_t search_lds_bytes(int max_vars, int max_depth, size_t max_desc, bool desc_
     return align16(b);
 }
 
-size_t dep_lds_bytes(int vshift, int qw, const int wcap[4], int jcap)
+size_t dep_lds_bytes(int vshift, int qw, const int wcap[kDepKinds], int jcap)
 {
     return align16(12 * ((size_t)1 << vshift)) + align16(4 * (size_t)qw) +
-           align16(2 * (size_t)(wcap[0] + wcap[1] + wcap[2] + wcap[3])) + align16(4 * (size_t)jcap);
+           align16(2 * (size_t)(wcap[0] + wcap[1] + wcap[2] + wcap[3] + wcap[4])) +
+           align16(4 * (size_t)jcap);
 }
 
 size_t propagate_lds_bytes(int nvars, size_t desc, bool desc_lds)
@@ -2440,6 +2619,15 @@ hipError_t launch_propagate_batch(const DevModel *m_dev, int nbox, const int32_t
         hipLaunchKernelGGL(propagate_batch_kernel<false>, dim3(grid), dim3(block), lds, stream,
                            m_dev, nbox, lb_in, ub_in, lb_out, ub_out, status, sweeps);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_propagate_incr(const DevModel *m_dev, const IncrParams &A, int grid, int block,
+                                 size_t lds, hipStream_t stream)
+{
+    hipError_t e = set_lds_limit(propagate_incr_kernel, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(propagate_incr_kernel, dim3(grid), dim3(block), lds, stream, m_dev, A);
     return hipGetLastError();
 }
 

@@ -22,14 +22,20 @@ size_t search_lds_bytes(int max_vars, int max_depth, size_t max_desc, bool desc_
                         int feat_ndec, int list_items, size_t dep_bytes);
 // LDS of dependency-driven propagation: three variable bitmaps of
 // 1 << vshift words, qw words of propagator marks, work lists of wcap[k]
-// 16-bit entries and (two-phase expansion) a job list of jcap words
-size_t dep_lds_bytes(int vshift, int qw, const int wcap[4], int jcap);
+// 16-bit entries (k < kDepKinds) and (two-phase expansion) a job list of
+// jcap words
+size_t dep_lds_bytes(int vshift, int qw, const int wcap[kDepKinds], int jcap);
 size_t propagate_lds_bytes(int nvars, size_t desc, bool desc_lds);
 
 hipError_t launch_propagate_batch(const DevModel *m_dev, int nbox, const int32_t *lb_in,
                                   const int32_t *ub_in, int32_t *lb_out, int32_t *ub_out,
                                   int32_t *status, int32_t *sweeps, int grid, int block,
                                   size_t lds, bool desc_lds, hipStream_t stream);
+
+// incremental fixed points (dependency-driven); lds = propagate_lds_bytes
+// (no tables) + dep_lds_bytes of A's layout
+hipError_t launch_propagate_incr(const DevModel *m_dev, const IncrParams &A, int grid, int block,
+                                 size_t lds, hipStream_t stream);
 
 // Which search-kernel variant: descriptor tables in LDS, subtree-root store
 // in LDS, learned branching, item lists of non-entailed propagators,

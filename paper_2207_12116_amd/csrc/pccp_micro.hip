@@ -19,13 +19,16 @@ constexpr int kMicroWords = 8192;       // 32 KiB of LDS per workgroup (int32 wo
 constexpr int kMicroIters = 2048;
 constexpr int kMicroUnroll = 8;
 
-// each thread reads int2 pairs tid, tid + 256, ... (mod the array), 8
-// independent loads in flight per step
-__global__ __launch_bounds__(kMicroBlock) void lds_read_kernel(int *sink)
+// each thread reads int2 pairs tid + k * stride (mod the array), 8
+// independent loads in flight per step.  The stride and the stored values
+// come from the host at run time and every value enters a running
+// multiply-add, so the compiler can neither see that the addresses repeat
+// nor fold the loop into a closed form: every load is issued.
+__global__ __launch_bounds__(kMicroBlock) void lds_read_kernel(int *sink, int stride, int seed)
 {
     __shared__ int2 a[kMicroWords / 2];
     const int tid = threadIdx.x;
-    for (int i = tid; i < kMicroWords / 2; i += kMicroBlock) a[i] = make_int2(i, ~i);
+    for (int i = tid; i < kMicroWords / 2; i += kMicroBlock) a[i] = make_int2(i ^ seed, ~i + seed);
     __syncthreads();
     int acc0 = 0, acc1 = 0;
     constexpr int N = kMicroWords / 2;
@@ -33,11 +36,11 @@ __global__ __launch_bounds__(kMicroBlock) void lds_read_kernel(int *sink)
         int2 v[kMicroUnroll];
 #pragma unroll
         for (int u = 0; u < kMicroUnroll; ++u)
-            v[u] = a[(tid + (it * kMicroUnroll + u) * kMicroBlock) & (N - 1)];
+            v[u] = a[(tid + (it * kMicroUnroll + u) * stride) & (N - 1)];
 #pragma unroll
         for (int u = 0; u < kMicroUnroll; ++u) {
-            acc0 ^= v[u].x;
-            acc1 += v[u].y;
+            acc0 = acc0 * 3 + v[u].x;
+            acc1 ^= v[u].y;
         }
     }
     sink[blockIdx.x * kMicroBlock + tid] = acc0 ^ acc1;
@@ -97,7 +100,10 @@ extern "C" int32_t pccp_measure_lds_peaks(pccp_lds_peaks *out)
     for (int k = 0; k < 3 && e == hipSuccess; ++k) {
         for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {   // the first run warms up
             e = hipEventRecord(e0, 0);
-            if (k == 0) hipLaunchKernelGGL(lds_read_kernel, dim3(grid), dim3(kMicroBlock), 0, 0, sink);
+            // stride 256: the 64 lanes of a wavefront read 64 consecutive
+            // pairs (512 bytes), conflict-free
+            if (k == 0) hipLaunchKernelGGL(lds_read_kernel, dim3(grid), dim3(kMicroBlock), 0, 0, sink,
+                                           kMicroBlock, 0x5bd1e995);
             if (k == 1) hipLaunchKernelGGL(lds_atomic_kernel<false>, dim3(grid), dim3(kMicroBlock), 0, 0, sink);
             if (k == 2) hipLaunchKernelGGL(lds_atomic_kernel<true>, dim3(grid), dim3(kMicroBlock), 0, 0, sink);
             if (e == hipSuccess) e = hipGetLastError();

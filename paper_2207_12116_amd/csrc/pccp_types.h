@@ -29,6 +29,14 @@ constexpr int kCtlWords = 96;   // LDS control block (int32 words)
 //   domains).  row = {rhs, number of terms}; terms row-major with a fixed
 //   stride of bgroup * bchunks slots per row, term = var | (a << 16), the
 //   unused slots of a row hold 0 (a = 0).
+// Kind 5 - guarded command  {g_1, ..., g_n} => x <- f  (§3, guarded normal
+//   form), f = k + sum_t a_t y_t: when every guard is entailed (guard
+//   (y, 0, c): lb(y) >= c; (y, 1, c): ub(y) <= c), side 0 joins
+//   ceil(f / div) into lb(x), side 1 joins floor(f / div) into ub(x), each
+//   term read through the bound that keeps f monotone.
+//   cmd = {x | side << 16, k, div, first entry}; cnt = guards | terms << 16;
+//   entries: the guards {y | side << 16, c}, then the terms
+//   {y | (reads ub) << 16, a}.
 struct DevModel {
     int32_t nvars;
     int32_t ndiff, nreif, nrows, nterms;
@@ -38,7 +46,7 @@ struct DevModel {
     int32_t nbrows;               // kind 4 rows
     int32_t bgroup, bchunks;      // kind 4: lanes per row, term slots per lane
     int32_t nbterms;              // kind 4 terms (without the padding)
-    int32_t pad0;
+    int32_t ncmd;                 // kind 5 commands
     const int32_t *lb0, *ub0;     // initial box
     const int2 *diff;             // kind 1
     const int2 *reif;             // kind 2
@@ -47,6 +55,9 @@ struct DevModel {
     const int2 *brows;            // kind 4 rows {rhs, len}
     const uint32_t *bterms;       // kind 4 terms [nbrows * bgroup * bchunks]
     const int32_t *dec;           // decision variables (tie-break order)
+    const int4 *cmds;             // kind 5 commands
+    const uint32_t *ccnt;         // kind 5 guard and term counts
+    const int2 *cent;             // kind 5 guards and terms
     // learned branching: per decision variable q, fstat[8q..8q+4] =
     // {lo, 1/H, degree share, static load, 1/N}; rows x - y <= c leaving
     // x = dec[q] as fr[fr_ptr[q]..fr_ptr[q+1]) = {y, c}; b of the reified
@@ -59,12 +70,13 @@ struct DevModel {
     // dependency-driven propagation: the propagators that read variable x
     // are adj[adj_ptr[x]..adj_ptr[x+1]), entry = index in its kind's table
     // | kind << 16 (0 difference rows, 1 reified items, 2 linear rows,
-    // 3 Boolean rows) | reads lb(x) << 18 | reads ub(x) << 19
+    // 3 Boolean rows, 4 guarded commands) | reads lb(x) << 19 | reads ub(x) << 20
     const int32_t *adj_ptr;
     const uint32_t *adj;
 };
-constexpr uint32_t kAdjLb = 1u << 18;
-constexpr uint32_t kAdjUb = 1u << 19;
+constexpr uint32_t kAdjLb = 1u << 19;
+constexpr uint32_t kAdjUb = 1u << 20;
+constexpr int kDepKinds = 5;     // propagator kinds of the dependency-driven work lists
 
 constexpr int kNumFeat = 6;
 constexpr int kHidden = 64;
@@ -111,6 +123,19 @@ struct SearchGlobals {
     long long t_start;                  // wall_clock64() when the search was initialised
 };
 
+// Incremental fixed points: box k is the fixed point (lb_in, ub_in) joined
+// with lb(dvar[k]) >= dlo[k] and ub(dvar[k]) <= dhi[k]; the LDS layout of the
+// dependency-driven loop as in SearchParams (dep_*).
+struct IncrParams {
+    int32_t nbox;
+    int32_t dep_vshift, dep_qw, dep_jcap;
+    int32_t dep_wcap[kDepKinds];
+    const int32_t *lb_in, *ub_in;
+    const int32_t *dvar, *dlo, *dhi;
+    int32_t *lb_out, *ub_out;
+    int32_t *status, *sweeps;
+};
+
 struct SearchParams {
     const DevModel *models;     // [ninst]
     InstState *inst;            // [ninst]
@@ -142,7 +167,7 @@ struct SearchParams {
     // dep_qw words of propagator marks, work lists of dep_wcap[k] entries,
     // and a trail of tcap entries per workgroup in global memory
     int32_t dep_vshift, dep_qw;
-    int32_t dep_wcap[4];
+    int32_t dep_wcap[kDepKinds];
     int4 *trail;                // [grid * tcap] {x, lb, ub, 0}
     int32_t tcap;
     int32_t dep_jcap;           // job-list entries of the two-phase expansion (0: one phase)

@@ -30,6 +30,7 @@ BRANCH_FIRST_FAIL, BRANCH_INPUT_ORDER, BRANCH_MLP = 0, 1, 2
 
 _P32 = C.POINTER(C.c_int32)
 _I32, _I64, _VP = C.c_int32, C.c_int64, C.c_void_p
+_PF = C.POINTER(C.c_float)
 
 
 class Config(C.Structure):
@@ -90,6 +91,10 @@ EXPORTS = [
     "pccp_mlp_get_params", "pccp_mlp_train_step", "pccp_mlp_get_grads", "pccp_mlp_scores",
     "pccp_mlp_weights", "pccp_model_save_file", "pccp_model_load_file",
     "pccp_get_solution_hash", "pccp_autotune", "pccp_measure_lds_peaks",
+    "pccp_propagate_batch_incr", "pccp_model_add_guarded",
+    "pccp_fmodel_create", "pccp_fmodel_destroy", "pccp_fmodel_add_vars",
+    "pccp_fmodel_add_linear_le", "pccp_fsolver_create", "pccp_fsolver_destroy",
+    "pccp_fpropagate_batch",
 ]
 
 _lib = None
@@ -122,10 +127,20 @@ def lib():
         "pccp_model_info": [_VP, _P32, _P32, _P32, _P32, _P32],
         "pccp_solver_create": [_VP, C.POINTER(Config), _VP, C.POINTER(_VP)],
         "pccp_solver_destroy": [_VP],
+        "pccp_fmodel_create": [C.POINTER(_VP)],
+        "pccp_fmodel_destroy": [_VP],
+        "pccp_fmodel_add_vars": [_VP, _I32, _PF, _PF, _P32],
+        "pccp_fmodel_add_linear_le": [_VP, _I32, _PF, _P32, C.c_float],
+        "pccp_fsolver_create": [_VP, _I32, _VP, C.POINTER(_VP)],
+        "pccp_fsolver_destroy": [_VP],
+        "pccp_fpropagate_batch": [_VP, _I32, _VP, _VP, _VP, _VP, _VP, _VP],
         "pccp_propagate": [_VP, _P32, _P32, _P32],
         "pccp_get_domains": [_VP, _P32, _P32, _I32],
         "pccp_propagate_batch": [_VP, _I32, _VP, _VP, _VP, _VP, _VP, _VP],
+        "pccp_propagate_batch_incr": [_VP, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP],
         "pccp_solve": [_VP, _I32, C.POINTER(Limits), _P32],
+        "pccp_model_add_guarded": [_VP, _I32, _I32, _I32, _I32, _I32, _P32, _P32, _P32, _I32,
+                                   _P32, _P32],
         "pccp_batch_solve": [C.POINTER(_VP), _I32, _I32, C.POINTER(Config),
                              C.POINTER(Limits), _P32],
         "pccp_get_stats": [_VP, C.POINTER(Stats)],
@@ -207,6 +222,20 @@ class ModelHandle:
                  "add_linear_le")
         for b_, si, sj, d in _i32(model.reif).reshape(-1, 4).tolist():
             _chk(L.pccp_model_add_reified_overlap(h, b_, si, sj, d), "add_reified_overlap")
+        if model.ncmd:
+            cmd = _i32(model.cmd).reshape(-1, 4)
+            gptr, tptr = _i32(model.cmd_gptr), _i32(model.cmd_tptr)
+            guard = _i32(model.cmd_guard).reshape(-1, 3)
+            term = _i32(model.cmd_term).reshape(-1, 2)
+            for q in range(model.ncmd):
+                x, side, k, div = (int(v) for v in cmd[q])
+                g = guard[gptr[q]:gptr[q + 1]]
+                t = term[tptr[q]:tptr[q + 1]]
+                gv, gs, gc = (np.ascontiguousarray(g[:, i]) for i in range(3))
+                ta, ty = np.ascontiguousarray(t[:, 0]), np.ascontiguousarray(t[:, 1])
+                _chk(L.pccp_model_add_guarded(h, x, side, k, div, int(g.shape[0]), _p(gv), _p(gs),
+                                              _p(gc), int(t.shape[0]), _p(ta), _p(ty)),
+                     "add_guarded")
         dec = _i32(model.decision)
         _chk(L.pccp_model_set_decision_vars(h, int(dec.shape[0]), _p(dec)), "set_decision_vars")
         _chk(L.pccp_model_set_objective(h, int(model.objective)), "set_objective")
@@ -291,6 +320,24 @@ class Solver:
             C.c_void_p(status.data_ptr()),
             C.c_void_p(sweeps.data_ptr()) if sweeps is not None else None),
             "pccp_propagate_batch")
+
+    def propagate_batch_incr(self, lb_in, ub_in, dvar, dlo, dhi, lb_out, ub_out, status,
+                             sweeps=None):
+        """Fixed points of fixed-point boxes joined with one decision each
+        (lb(dvar) >= dlo, ub(dvar) <= dhi), by dependency-driven propagation;
+        int32 CUDA tensors [nbox, nvars] and [nbox].  Enqueued on the solver's
+        stream."""
+        nbox = int(lb_in.shape[0])
+        for t in (lb_in, ub_in, lb_out, ub_out):
+            assert t.is_cuda and t.is_contiguous() and t.shape == (nbox, self.model.nvars)
+        for t in (dvar, dlo, dhi, status):
+            assert t.is_cuda and t.is_contiguous() and t.numel() >= nbox
+        if sweeps is not None:
+            assert sweeps.is_cuda and sweeps.numel() >= nbox
+        v = lambda t: C.c_void_p(t.data_ptr())
+        _chk(lib().pccp_propagate_batch_incr(
+            self.h, nbox, v(lb_in), v(ub_in), v(dvar), v(dlo), v(dhi), v(lb_out), v(ub_out),
+            v(status), v(sweeps) if sweeps is not None else None), "pccp_propagate_batch_incr")
 
     # ---- search
     def solve(self, mode=None, node_limit=0, time_limit=0.0, cancel=None):
@@ -454,3 +501,55 @@ class MLP:
         w = _VP()
         _chk(lib().pccp_mlp_weights(self.h, C.byref(w)), "pccp_mlp_weights")
         return int(w.value)
+
+
+# ---------------------------------------------------------------- float stores
+class FSolver:
+    """A float model (instances.FModel) built in the library and uploaded to
+    the current HIP device."""
+
+    def __init__(self, model, wg_size: int = 0, stream=None):
+        L = lib()
+        self.model = model
+        mh = _VP()
+        _chk(L.pccp_fmodel_create(C.byref(mh)), "pccp_fmodel_create")
+        try:
+            lb = np.ascontiguousarray(model.lb, dtype=np.float32)
+            ub = np.ascontiguousarray(model.ub, dtype=np.float32)
+            _chk(L.pccp_fmodel_add_vars(mh, model.nvars, lb.ctypes.data_as(_PF),
+                                        ub.ctypes.data_as(_PF), None), "pccp_fmodel_add_vars")
+            ptr = np.asarray(model.row_ptr, dtype=np.int32)
+            coef = np.ascontiguousarray(model.coef, dtype=np.float32)
+            var = np.ascontiguousarray(model.var, dtype=np.int32)
+            for r in range(model.nrows):
+                a, b = int(ptr[r]), int(ptr[r + 1])
+                cc, vv = np.ascontiguousarray(coef[a:b]), np.ascontiguousarray(var[a:b])
+                _chk(L.pccp_fmodel_add_linear_le(mh, b - a, cc.ctypes.data_as(_PF), _p(vv),
+                                                 float(model.rhs[r])), "pccp_fmodel_add_linear_le")
+            self.stream = _current_stream() if stream is None else int(stream)
+            h = _VP()
+            _chk(L.pccp_fsolver_create(mh, int(wg_size), C.c_void_p(self.stream), C.byref(h)),
+                 "pccp_fsolver_create")
+            self.h = h
+        finally:
+            L.pccp_fmodel_destroy(mh)
+
+    def propagate_batch(self, lb_in, ub_in, lb_out, ub_out, status, sweeps=None):
+        """Fixed points of float boxes: float32 CUDA tensors [nbox, nvars],
+        int32 status / sweeps [nbox].  Enqueued on the solver's stream."""
+        nbox = int(lb_in.shape[0])
+        for t in (lb_in, ub_in, lb_out, ub_out):
+            assert t.is_cuda and t.is_contiguous() and t.shape == (nbox, self.model.nvars)
+        assert status.is_cuda and status.numel() >= nbox
+        v = lambda t: C.c_void_p(t.data_ptr())
+        _chk(lib().pccp_fpropagate_batch(self.h, nbox, v(lb_in), v(ub_in), v(lb_out), v(ub_out),
+                                         v(status), v(sweeps) if sweeps is not None else None),
+             "pccp_fpropagate_batch")
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.pccp_fsolver_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()

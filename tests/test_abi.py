@@ -82,7 +82,8 @@ def test_model_file_round_trip_without_device(tmp_path):
     back to the same bytes."""
     import numpy as np
     from paper_2207_12116_amd import instances as I
-    for model in (I.rcpsp(30, 2), I.tiny_csp(3), I.jobshop(3, 3, 1)):
+    for model in (I.rcpsp(30, 2), I.tiny_csp(3), I.jobshop(3, 3, 1),
+                  I.jobshop(3, 3, 1, guarded=True)):
         mh = pccp.ModelHandle(model)
         p1 = str(tmp_path / "lib.pccp")
         mh.save(p1)
@@ -92,6 +93,11 @@ def test_model_file_round_trip_without_device(tmp_path):
                 model.objective]
         for a, b in zip(got, want):
             assert np.array_equal(np.asarray(a), np.asarray(b))
+        back = I.load_model(p1)
+        assert back.ncmd == model.ncmd
+        for f in ("cmd", "cmd_gptr", "cmd_guard", "cmd_tptr", "cmd_term"):
+            assert np.array_equal(np.asarray(getattr(back, f)).reshape(-1),
+                                  np.asarray(getattr(model, f)).reshape(-1)), f
         p2 = str(tmp_path / "gen.pccp")
         I.save_model(model, p2)
         h2 = pccp.ModelHandle.from_file(p2)
@@ -105,6 +111,7 @@ def test_model_file_round_trip_without_device(tmp_path):
 
 
 def test_model_file_errors_without_device(tmp_path):
+    import numpy as np
     from paper_2207_12116_amd import instances as I
     L = pccp.lib()
     h = ctypes.c_void_p()
@@ -123,6 +130,19 @@ def test_model_file_errors_without_device(tmp_path):
         h = ctypes.c_void_p()
         assert L.pccp_model_load_file(p.encode(), ctypes.byref(h)) == pccp.E_MODEL, name
         assert not h.value
+    # guarded-command pointers that stop short of their count, or decrease
+    for name in ("short", "decreasing"):
+        gm = I.jobshop(3, 3, 1, guarded=True)
+        gm.cmd_tptr = gm.cmd_tptr.copy()
+        if name == "short":
+            gm.cmd_tptr[-1] -= 1
+        else:
+            i = int(np.argmax(np.diff(gm.cmd_tptr) > 0))
+            gm.cmd_tptr[i], gm.cmd_tptr[i + 1] = gm.cmd_tptr[i + 1], gm.cmd_tptr[i]
+        bad = str(tmp_path / f"cmdptr_{name}.pccp")
+        I.save_model(gm, bad)
+        h = ctypes.c_void_p()
+        assert L.pccp_model_load_file(bad.encode(), ctypes.byref(h)) == pccp.E_MODEL, name
     # a row pointer that decreases
     m = I.tiny_rcpsp(5, 1)
     m.lin_ptr = m.lin_ptr.copy()

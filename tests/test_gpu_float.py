@@ -1,0 +1,119 @@
+"""Float interval stores on the GPU against the oracle (oracle/fprop.c),
+bit for bit: the tells are monotone, so the least fixed point is unique
+(§3 Theorem 2) and the concurrent sweeps must reach the oracle's store
+exactly, rounding included.  Root boxes and random sub-boxes of the tiny CSP
+over the reals and of sparse random systems up to 4000 variables, several
+workgroup sizes; boxes that fail; canonical zeros; invalid models refused."""
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2207_12116_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2207_12116_amd import pccp
+    pccp.lib()
+    return pccp
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _subboxes(model, rng, count, frac=0.3):
+    out = [(model.lb.copy(), model.ub.copy())]
+    for _ in range(count - 1):
+        lb, ub = model.lb.copy(), model.ub.copy()
+        for v in range(model.nvars):
+            if rng.random() < frac:
+                a = np.float32(rng.uniform(float(lb[v]), float(ub[v])))
+                b = np.float32(rng.uniform(float(lb[v]), float(ub[v])))
+                lo, hi = min(a, b), max(a, b)
+                r = rng.random()
+                if r < 0.4:
+                    lb[v], ub[v] = lo, hi
+                elif r < 0.7:
+                    lb[v] = lo
+                else:
+                    ub[v] = hi
+        out.append((lb, ub))
+    return out
+
+
+def _run(P, model, boxes, wg):
+    import torch
+    dev = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda")
+    lbs = dev(np.stack([b[0] for b in boxes]))
+    ubs = dev(np.stack([b[1] for b in boxes]))
+    olb, oub = torch.empty_like(lbs), torch.empty_like(ubs)
+    st = torch.full((len(boxes),), 7, dtype=torch.int32, device="cuda")
+    sw = torch.zeros(len(boxes), dtype=torch.int32, device="cuda")
+    s = P.FSolver(model, wg_size=wg)
+    s.propagate_batch(lbs, ubs, olb, oub, st, sw)
+    torch.cuda.synchronize()
+    return st.cpu().numpy(), olb.cpu().numpy(), oub.cpu().numpy(), sw.cpu().numpy()
+
+
+FMODELS = [("csp%d" % s, lambda s=s: I.float_csp(s)) for s in (0, 1, 2, 3)] + \
+          [("net100", lambda: I.float_network(100, 1)), ("net1000", lambda: I.float_network(1000, 2)),
+           ("net4000", lambda: I.float_network(4000, 3, rows_per_var=1))]
+
+
+@pytest.mark.parametrize("name,mk", FMODELS, ids=[m[0] for m in FMODELS])
+@pytest.mark.parametrize("wg", [64, 256, 1024])
+def test_float_fixpoints_bit_exact(P, name, mk, wg):
+    model = mk()
+    om = O.OracleFModel(model)
+    rng = random.Random(sum(map(ord, name)) + wg)
+    nbox = 64 if model.nvars <= 1000 else 8
+    boxes = _subboxes(model, rng, nbox)
+    say("float fixpoints", name, wg, nbox)
+    gst, glb, gub, gsw = _run(P, model, boxes, wg)
+    nfail = 0
+    for k, (lb0, ub0) in enumerate(boxes):
+        st, lb, ub, _ = O.fpropagate(om, lb0, ub0)
+        assert int(gst[k]) == st, (name, k)
+        if st == O.FIXPOINT:
+            assert np.array_equal(glb[k].view(np.uint32), lb.view(np.uint32)), (name, k)
+            assert np.array_equal(gub[k].view(np.uint32), ub.view(np.uint32)), (name, k)
+        else:
+            nfail += 1
+    assert (gsw >= 1).all()
+    say("float fixpoints", name, wg, "failed", nfail, "of", nbox)
+
+
+def test_float_failure_and_zeros(P):
+    # no real solution: x + y <= 1, x >= 0.75, y >= 0.5
+    m = I._fmodel([0.0, 0.0], [10.0, 10.0],
+                  [([1.0, 1.0], [0, 1], 1.0), ([-1.0], [0], -0.75), ([-1.0], [1], -0.5)], {})
+    st, lb, ub, _ = _run(P, m, [(m.lb, m.ub)], 64)
+    assert st[0] == 1
+    # zero bounds come back canonical: -0 below, +0 above
+    m = I._fmodel([0.0, -1.0], [1.0, 0.0], [([1.0, 1.0], [0, 1], 0.0),
+                                            ([-1.0, -1.0], [0, 1], 0.0)], {})
+    box = (np.float32([0.0, -0.0]), np.float32([-0.0, 0.0]))
+    st, lb, ub, _ = _run(P, m, [box], 64)
+    ref = O.fpropagate(m, *box)
+    assert st[0] == ref[0] == 0
+    assert np.array_equal(lb[0].view(np.uint32), ref[1].view(np.uint32))
+    assert np.array_equal(ub[0].view(np.uint32), ref[2].view(np.uint32))
+    assert np.signbit(lb[0][0]) and not np.signbit(ub[0][0])
+
+
+def test_float_models_refused(P):
+    bad = [I._fmodel([0.0], [np.inf], [([1.0], [0], 1.0)], {}),          # infinite bound
+           I._fmodel([0.0], [1.0], [([0.0], [0], 1.0)], {}),             # zero coefficient
+           I._fmodel([0.0, 0.0], [1.0, 1.0], [([1.0, 1.0], [0, 0], 1.0)], {})]   # repeated
+    for m in bad:
+        with pytest.raises(P.PccpError) as e:
+            P.FSolver(m)
+        assert e.value.code == P.E_MODEL
