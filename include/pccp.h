@@ -316,6 +316,27 @@ typedef struct {
  * deeper than max_depth. */
 int32_t pccp_solve(pccp_solver *s, int32_t mode, const pccp_limits *limits, int32_t *outcome);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * search as pccp_solve, on the same kernels, with the whole search
+ * workspace (queue, per-instance state, decision stacks, trail, subtree
+ * roots) taken from a static device array of 64 MiB that the library holds
+ * on every device it is loaded on until the process ends.  It calls no
+ * hipMalloc, hipFree or allocating library routine and launches the kernels
+ * directly (no graph).  The solver (created beforehand) is the input; the
+ * outcome, stats, best objective and values, solution count and hash are
+ * the outputs, read with the usual calls.  The list of solutions is not
+ * kept (pccp_get_solutions refuses any non-empty range).
+ * Returns PCCP_E_NOMEM, before any device work, when the launch shape needs
+ * more than 64 MiB (16 bytes x max_depth per workgroup for the stacks, plus
+ * 16 bytes x trail_cap per workgroup with dependency-driven propagation, plus
+ * the queue): lower cfg.num_wgs, max_depth or trail_cap.  Every call on a
+ * device shares that device's array: calls that overlap on one GPU (two host
+ * threads, two streams) race and give wrong results.  The array keeps the
+ * last call's contents; each call initialises what it reads. */
+int32_t pccp_solve_noalloc(pccp_solver *s, int32_t mode, const pccp_limits *limits,
+                           int32_t *outcome);
+
 /* The same search over n solvers' models in ONE persistent launch (one
  * shared queue; instances of different sizes).  All solvers must live on
  * the current device; the launch uses solvers[0]'s stream and cfg (may be

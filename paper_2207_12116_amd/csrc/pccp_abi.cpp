@@ -1016,7 +1016,7 @@ static int32_t choose_shape(const pccp_config &cfg, const ShapeNeed &nd, int num
 }
 
 static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const pccp_config *cfgp,
-                          const pccp_limits *lim, int32_t *outcomes)
+                          const pccp_limits *lim, int32_t *outcomes, bool noalloc = false)
 {
     if (!sv || n < 1 || !outcomes || (mode != PCCP_ENUMERATE && mode != PCCP_MINIMIZE))
         return fail(PCCP_E_INVALID_ARG, "search: bad arguments");
@@ -1079,8 +1079,38 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
     char *w_qdata = nullptr;
     int32_t *w_best = nullptr, *w_roots = nullptr;
     int4 *w_trail = nullptr, *w_gstack = nullptr;
-    const bool keep_sols = (mode == PCCP_ENUMERATE && n == 1 && cfg.sol_cap > 0);
-    {
+    // the solution list is kept by the allocating form only
+    const bool keep_sols = (!noalloc && mode == PCCP_ENUMERATE && n == 1 && cfg.sol_cap > 0);
+    if (noalloc) {
+        // carve every piece out of the library's static device array
+        auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+        const size_t need = al(z_models) + al(z_inst) + al(z_glob) + al(z_qseq) + al(z_qdata) +
+                            al(z_best) + al(z_roots) + al(z_trail) + al(z_gstack);
+        if (need > kScratchBytes)
+            return fail(PCCP_E_NOMEM, "pccp_solve_noalloc: the search needs " + std::to_string(need) +
+                                          " bytes of workspace, more than the static " +
+                                          std::to_string(kScratchBytes) +
+                                          " (lower num_wgs, max_depth or trail_cap)");
+        void *sp = nullptr;
+        HIPCHK(scratch_address(&sp));
+        char *base = reinterpret_cast<char *>(sp);
+        size_t off = 0;
+        auto carve = [&](size_t b) -> char * {
+            if (b == 0) return nullptr;
+            char *q = base + off;
+            off += al(b);
+            return q;
+        };
+        w_models = reinterpret_cast<DevModel *>(carve(z_models));
+        w_inst = reinterpret_cast<InstState *>(carve(z_inst));
+        w_glob = reinterpret_cast<SearchGlobals *>(carve(z_glob));
+        w_qseq = reinterpret_cast<unsigned long long *>(carve(z_qseq));
+        w_qdata = carve(z_qdata);
+        w_best = reinterpret_cast<int32_t *>(carve(z_best));
+        w_roots = reinterpret_cast<int32_t *>(carve(z_roots));
+        w_trail = reinterpret_cast<int4 *>(carve(z_trail));
+        w_gstack = reinterpret_cast<int4 *>(carve(z_gstack));
+    } else {
         Workspace &ws = s0->ws;
         if ((rc = ws.models.ensure(z_models)) || (rc = ws.inst.ensure(z_inst)) ||
             (rc = ws.globals.ensure(z_glob)) || (rc = ws.qseq.ensure(z_qseq)) ||
@@ -1140,7 +1170,7 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
     P.tcap = tcap;
     P.gstack = w_gstack;
 
-    if (cfg.launch == 0) {
+    if (cfg.launch == 0 && !noalloc) {
         Workspace &ws = s0->ws;
         // the graph bakes in the launch parameters: rebuild it when they change
         std::vector<char> key(sizeof(P) + 8 * sizeof(int64_t));
@@ -1230,6 +1260,14 @@ extern "C" int32_t pccp_solve(pccp_solver *s, int32_t mode, const pccp_limits *l
     if (!s || !outcome) return fail(PCCP_E_INVALID_ARG, "pccp_solve: bad arguments");
     pccp_solver *sv[1] = {s};
     return run_search(sv, 1, mode, nullptr, limits, outcome);
+}
+
+extern "C" int32_t pccp_solve_noalloc(pccp_solver *s, int32_t mode, const pccp_limits *limits,
+                                      int32_t *outcome)
+{
+    if (!s || !outcome) return fail(PCCP_E_INVALID_ARG, "pccp_solve_noalloc: bad arguments");
+    pccp_solver *sv[1] = {s};
+    return run_search(sv, 1, mode, nullptr, limits, outcome, true);
 }
 
 extern "C" int32_t pccp_batch_solve(pccp_solver *const *solvers, int32_t n, int32_t mode,

@@ -47,6 +47,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "pccp_launch.h"
 #include "pccp_types.h"
 
@@ -2712,6 +2714,34 @@ hipError_t build_search_graph(const SearchParams &P, int grid, int block, size_t
     if (e == hipSuccess) e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     return e;
+}
+
+// The workspace of the search entry point that allocates nothing (for
+// callers that cannot call hipMalloc).  Every device the library is loaded
+// on holds one copy until the process ends; in host code the name stands
+// for no device address, so kernels get the address that
+// hipGetSymbolAddress returns on the device that runs them.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(void **ptr)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t search_occupancy(int block, size_t lds, const SearchShape &k, int *wgs_per_cu)

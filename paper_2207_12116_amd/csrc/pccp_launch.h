@@ -65,6 +65,12 @@ hipError_t launch_mlp_sync_bf16(const float *params, uint16_t *wbf, hipStream_t 
 hipError_t launch_mlp_scores(const float *params, const uint16_t *wbf, int use_bf16,
                              const float *feat, int ncand, float *scores, hipStream_t stream);
 
+// The search workspace of pccp_solve_noalloc: a static device array of
+// kScratchBytes per device.  scratch_address gives its address on the
+// current device (looked up once per device, then cached).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+hipError_t scratch_address(void **ptr);
+
 hipError_t search_occupancy(int block, size_t lds, const SearchShape &k, int *wgs_per_cu);
 
 }  // namespace pccp

@@ -91,7 +91,7 @@ EXPORTS = [
     "pccp_mlp_get_params", "pccp_mlp_train_step", "pccp_mlp_get_grads", "pccp_mlp_scores",
     "pccp_mlp_weights", "pccp_model_save_file", "pccp_model_load_file",
     "pccp_get_solution_hash", "pccp_autotune", "pccp_measure_lds_peaks",
-    "pccp_propagate_batch_incr", "pccp_model_add_guarded",
+    "pccp_solve_noalloc", "pccp_propagate_batch_incr", "pccp_model_add_guarded",
     "pccp_fmodel_create", "pccp_fmodel_destroy", "pccp_fmodel_add_vars",
     "pccp_fmodel_add_linear_le", "pccp_fsolver_create", "pccp_fsolver_destroy",
     "pccp_fpropagate_batch",
@@ -139,6 +139,7 @@ def lib():
         "pccp_propagate_batch": [_VP, _I32, _VP, _VP, _VP, _VP, _VP, _VP],
         "pccp_propagate_batch_incr": [_VP, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP],
         "pccp_solve": [_VP, _I32, C.POINTER(Limits), _P32],
+        "pccp_solve_noalloc": [_VP, _I32, C.POINTER(Limits), _P32],
         "pccp_model_add_guarded": [_VP, _I32, _I32, _I32, _I32, _I32, _P32, _P32, _P32, _I32,
                                    _P32, _P32],
         "pccp_batch_solve": [C.POINTER(_VP), _I32, _I32, C.POINTER(Config),
@@ -345,6 +346,16 @@ class Solver:
         out = C.c_int32(0)
         lim = _limits(node_limit, time_limit, cancel)
         _chk(lib().pccp_solve(self.h, int(mode), C.byref(lim), C.byref(out)), "pccp_solve")
+        return int(out.value)
+
+    def solve_noalloc(self, mode=None, node_limit=0, time_limit=0.0, cancel=None):
+        """pccp_solve_noalloc: the search with its workspace in the library's
+        static device array (no allocation; no solution list kept)."""
+        mode = self.model.mode if mode is None else mode
+        out = C.c_int32(0)
+        lim = _limits(node_limit, time_limit, cancel)
+        _chk(lib().pccp_solve_noalloc(self.h, int(mode), C.byref(lim), C.byref(out)),
+             "pccp_solve_noalloc")
         return int(out.value)
 
     def stats(self) -> dict:
