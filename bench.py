@@ -1,22 +1,33 @@
 #!/usr/bin/env python3
 """Benchmark: search nodes/s and time-to-proven-optimum on one MI355X.
 
-Workload (one "step"): the synthetic project-scheduling family with 30 tasks
-and 4 resources (capacity 10, durations 1..10, demands 0 or 1..10 at density
-0.5, precedence out-degree 1..3), `--batch` instances (seeds 0..batch-1),
-minimise the makespan by branch-and-bound with first-fail branching.  One
-step is one persistent launch that searches every instance of the batch
-(the batched form), bounded by `--step-time` seconds of device time; the
-whole hot path runs in it (recomputation, propagation sweeps, fixed-point and
-failure detection, branching, depth-first control, the subtree queue).
+Workload (one "step"): 256 instances of the synthetic project-scheduling
+family - 30, 60 or 90 tasks by seed mod 3 (seeds 0..255), 4 renewable
+resources of capacity 10, durations 1..10, demands 0 or 1..10 at density
+0.5, precedence out-degree 1..3 - each minimising its makespan by
+branch-and-bound with first-fail branching, all searched in ONE persistent
+launch (the batched form: one workgroup per subproblem, a device queue of
+subtrees, the launch replayed from a hipGraph), bounded by `--step-time`
+seconds of device time.  The whole hot path runs in that launch (node setup,
+propagation sweeps, fixed-point and failure detection, branching, the
+depth-first and bound control, the subtree queue).
 
 Printed: ONE JSON line on stdout with the contract fields plus
-  roofline      the search kernel's algorithmic LDS traffic (propagator
-                executions x bytes each) over its HIP-event duration,
-                against the LDS peak (256 CUs x 128 B/clk x 2.4 GHz)
-  cpu_baseline  the CPU oracle on one core on a bounded sample
-  plain         the same search on one instance alone (whole GPU)
+  roofline      the search kernel against the LDS roofline: algorithmic LDS
+                bytes (propagator executions x bytes each) over the kernel's
+                HIP-event time, against the LDS read peak MEASURED on this
+                device (pccp_measure_lds_peaks); and the lattice joins the
+                sweeps issued (LDS atomic max / min) per second against the
+                measured LDS atomic peak
+  cpu_baseline  the CPU oracle (C, -O3 -march=native, built on this host),
+                one POSIX thread per host core, timed in C, on a bounded
+                sample of the same workload
   ttpo          time to proven optimum of the instances proven in a step
+  legs          c2 plain (30 tasks, one instance on the whole GPU, several
+                seeds), c3 (120 tasks, its own roofline), job shops from the
+                PCCP front-end
+  ttpo_forms    plain vs batched vs learned time to settle a set of
+                instances under the same device-time budget
 Progress goes to stderr.
 """
 from __future__ import annotations
@@ -27,6 +38,7 @@ import math
 import os
 import statistics
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -35,24 +47,22 @@ if ROOT not in sys.path:
 
 METRIC = ("search nodes/sec + time-to-proven-optimum; plain vs batched vs learned, "
           "1 MI355X")
-LDS_PEAK_GBS = 256 * 128 * 2.4  # GB/s: CUs x bytes/clk/CU x GHz
-# algorithmic LDS bytes per propagator execution (int32 bounds):
-# difference row: lb/ub of both variables; reified overlap: lb/ub of si, sj,
-# b; linear-row term: the bound entering the sum and the bound it tightens
+# algorithmic LDS bytes per propagator execution (int32 bounds): difference
+# row: lb/ub of both variables; reified overlap: lb/ub of si, sj, b; linear-
+# row term: the bound entering the sum and the bound it tightens
 BYTES_DIFF, BYTES_REIF, BYTES_TERM = 16, 24, 8
 
 
 # HBM traffic of the search kernel from rocprofv3 counter runs (FETCH_SIZE and
 # WRITE_SIZE in separate passes), per search node, for one kernel source and
-# launch shape.  FETCH_SIZE is scaled by 2.0 and WRITE_SIZE by 1.0: what a
-# 2 GiB device copy (`--copy-calibration`) reads back as 1 GiB fetched and
-# 2 GiB written.  A run whose kernel source or shape differs reports null.
+# launch shape on the headline workload.  FETCH_SIZE is scaled by 2.0 and
+# WRITE_SIZE by 1.0: what a 2 GiB device copy (`--copy-calibration`) reads
+# back as 1 GiB fetched and 2 GiB written.  A run whose kernel source or
+# shape differs reports null.
 PROFILED_TRAFFIC = [
-    {"kernel_sha256": K, "block": blk, "desc_lds": dl, "root_lds": rl, "live": 0, "occupancy": oc,
-     "dep": dep, "fetch_bytes_per_node": f, "write_bytes_per_node": w,
-     "profile": "profiles/search_kernel_rcpsp30_traffic.md"}
-    for K in ["b443c51ee41959df42d43192414e7c1dc54d61a554b1ba44484a4e7269b5b9fa"]
-    for blk, dl, rl, oc, dep, f, w in [(128, 0, 0, 1, 1, 6.21, 301.0)]
+    # {"kernel_sha256": ..., "block": ..., "desc_lds": ..., "root_lds": ..., "live": ...,
+    #  "occupancy": ..., "dep": ..., "fetch_bytes_per_node": ..., "write_bytes_per_node": ...,
+    #  "profile": "profiles/..."}
 ]
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
@@ -86,49 +96,106 @@ def algorithmic_bytes(st):
             + st["prop_terms"] * BYTES_TERM)
 
 
-def _oracle_worker(args):
-    n, seed, nodes = args
+def propagations(st):
+    return st["prop_linear2"] + st["prop_reified"] + st["prop_linear"]
+
+
+def roofline(bytes_, atomics, kernel_s, peaks):
+    """LDS roofline of a search launch: algorithmic bytes and issued joins
+    per second of kernel time against the measured peaks."""
+    ach = bytes_ / kernel_s / 1e9 if kernel_s > 0 else 0.0
+    aops = atomics / kernel_s / 1e9 if kernel_s > 0 else 0.0
+    return {"bound": "lds", "achieved": round(ach, 1), "peak": round(peaks["read_GBs"], 1),
+            "unit": "GB/s", "frac": round(ach / peaks["read_GBs"], 5),
+            "atomic_achieved": round(aops, 3), "atomic_peak": round(peaks["atomic_Gops"], 1),
+            "atomic_unit": "Gop/s", "atomic_frac": round(aops / peaks["atomic_Gops"], 5)}
+
+
+def host_cores() -> int:
+    """Cores the CPU baseline may use: the ones this process may run on,
+    at most 16 (the host share of one GPU on the benchmark machines)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def host_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
+
+
+# nodes per instance of the CPU sample, by task count: about one second of
+# the oracle's sequential search each on a current server core
+CPU_NODES = {30: 8000, 60: 2000, 90: 1000}
+
+
+def cpu_baseline(models_by_size, threads, label, scale=1.0):
+    """The oracle's sequential depth-first search (built -O3 -march=native on
+    this host) on independent instances, one POSIX thread per core, timed in
+    C: for each task count, `threads` instances of it searched for
+    CPU_NODES[n] * scale nodes each (or to their proof); total nodes over the
+    summed wall time of the three sets.  Also one thread on one instance of
+    each size."""
     import oracle as O
-    from paper_2207_12116_amd import instances as I
-    model = I.rcpsp(n, seed)
-    t0 = time.perf_counter()
-    r = O.solve(model, node_limit=nodes)
-    return r["nodes"], time.perf_counter() - t0
+    from oracle import build as obuild
+    tmp = tempfile.mkdtemp(prefix="pccp_oracle_")
+    path = obuild.build(native=True, out=os.path.join(tmp, "liboracle_native.so"))
+    O.use_library(path)
+    nodes = wall = one_nodes = one_wall = 0.0
+    count = 0
+    for n, models in sorted(models_by_size.items()):
+        lim = max(1, int(CPU_NODES.get(n, 1000) * scale))
+        r = O.solve_timed(models, threads, node_limit=lim)
+        nodes += float(r["nodes"].sum())
+        wall += r["wall_s"]
+        count += len(models)
+        one = O.solve_timed(models[:1], 1, node_limit=lim)
+        one_nodes += float(one["nodes"].sum())
+        one_wall += one["wall_s"]
+    ncpu, cpu_model = host_info()
+    sizes = "/".join(str(n) for n in sorted(models_by_size))
+    return {"value": nodes / wall, "unit": "nodes/s", "cores": threads, "kind": "oracle",
+            "sample": f"{label}: {count} instances ({sizes} tasks, {threads} of each size), "
+                      f"{', '.join(f'{n}: {max(1, int(CPU_NODES.get(n, 1000) * scale))}' for n in sorted(models_by_size))} "
+                      f"nodes each (or to proof), {threads} threads, {wall:.1f} s wall, "
+                      f"oracle built -O3 -march=native",
+            "nproc": ncpu, "cpu_model": cpu_model,
+            "single_core": {"value": one_nodes / one_wall, "cores": 1,
+                            "sample": f"one instance of each size, {one_wall:.1f} s"}}
 
 
-def cpu_baseline(n, nodes, procs):
-    """The oracle's sequential DFS on `procs` instances at once (one process
-    each, seeds 0..procs-1), `nodes` nodes each: total nodes / wall time."""
-    import multiprocessing as mp
-    one_nodes, one_s = _oracle_worker((n, 0, nodes))
-    t0 = time.perf_counter()
-    with mp.get_context("spawn").Pool(procs) as pool:
-        res = pool.map(_oracle_worker, [(n, s, nodes) for s in range(procs)])
-    wall = time.perf_counter() - t0
-    tot = sum(r[0] for r in res)
-    return {"value": tot / wall, "unit": "nodes/s", "cores": procs, "kind": "oracle",
-            "sample": f"sequential oracle DFS, {procs} processes on the {n}-task instances "
-                      f"seeds 0-{procs - 1}, first {nodes} nodes each ({wall:.1f} s wall)",
-            "single_core": {"value": one_nodes / one_s, "cores": 1,
-                            "sample": f"seed 0, first {one_nodes} nodes ({one_s:.1f} s)"}}
-
-
-def single_instance_leg(n, seed, limit, cfg):
-    """One large instance searched by the whole GPU (plain form): node and
-    propagation rates and the LDS fraction."""
-    from paper_2207_12116_amd import instances as I, pccp
-    s = pccp.Solver(I.rcpsp(n, seed), config=cfg)
-    t0 = time.perf_counter()
-    out = s.solve(pccp.MINIMIZE, time_limit=limit)
-    dt = time.perf_counter() - t0
-    st = s.stats()
-    kern = st["kernel_ms"] / 1e3
-    props = st["prop_linear2"] + st["prop_reified"] + st["prop_linear"]
-    ach = algorithmic_bytes(st) / kern / 1e9
-    return {"tasks": n, "seed": seed, "nodes_per_s": round(st["nodes"] / dt, 1),
-            "propagations_per_s": round(props / dt, 1), "outcome": pccp.OUTCOME_NAMES[out],
-            "lds_achieved_GBs": round(ach, 1), "lds_frac": round(ach / LDS_PEAK_GBS, 4),
-            "grid": st["grid"], "block": st["block"], "time_s": round(dt, 3)}
+def plain_leg(models, limit, cfg, peaks):
+    """Each instance alone on the whole GPU (the plain form): node and
+    propagation rates, and the LDS roofline of the launches together."""
+    from paper_2207_12116_amd import pccp
+    rows, nodes, props, byt, atom, kern, wall = [], 0, 0, 0, 0, 0.0, 0.0
+    for i, m in enumerate(models):
+        s = pccp.Solver(m, config=cfg)
+        t0 = time.perf_counter()
+        out = s.solve(pccp.MINIMIZE, time_limit=limit)
+        dt = time.perf_counter() - t0
+        st = s.stats()
+        nodes += st["nodes"]
+        props += propagations(st)
+        byt += algorithmic_bytes(st)
+        atom += st["atomics"]
+        kern += st["kernel_ms"] / 1e3
+        wall += dt
+        rows.append({"nodes_per_s": round(st["nodes"] / dt, 1), "outcome": pccp.OUTCOME_NAMES[out],
+                     "best": st["best"], "time_s": round(dt, 3)})
+    return {"nodes_per_s": round(nodes / wall, 1), "propagations_per_s": round(props / wall, 1),
+            "roofline": roofline(byt, atom, kern, peaks), "grid": st["grid"], "block": st["block"],
+            "per_instance": rows}
 
 
 def jobshop_leg(models, limit, cfg):
@@ -148,65 +215,35 @@ def jobshop_leg(models, limit, cfg):
             "time_s": round(dt, 3)}
 
 
-def mixed_batch_leg(count, limit, cfg):
-    """`count` instances of 30, 60 and 90 tasks (by seed mod 3) in one
-    persistent launch."""
-    from paper_2207_12116_amd import instances as I, pccp
-    models = [I.rcpsp(I.batch_sizes(s), s) for s in range(count)]
-    solvers = [pccp.Solver(m, config=cfg) for m in models]
-    t0 = time.perf_counter()
-    outs = pccp.batch_solve(solvers, pccp.MINIMIZE, config=cfg, time_limit=limit)
-    dt = time.perf_counter() - t0
-    sts = [s.stats() for s in solvers]
-    nodes = sum(x["nodes"] for x in sts)
-    props = sum(x["prop_linear2"] + x["prop_reified"] + x["prop_linear"] for x in sts)
-    proven = sum(o in (pccp.OUT_OPTIMAL, pccp.OUT_UNSAT) for o in outs)
-    return {"instances": count, "sizes": "30/60/90 by seed mod 3", "nodes_per_s": round(nodes / dt, 1),
-            "propagations_per_s": round(props / dt, 1), "proven": proven,
-            "with_incumbent": sum(x["best"] is not None for x in sts),
-            "grid": sts[0]["grid"], "block": sts[0]["block"], "time_s": round(dt, 3)}
-
-
-def ttpo_suite(n, seeds, budget, cfg, weights):
-    """Time to proven optimum of the same instances in three forms, each
-    instance allowed `budget` search nodes (then abandoned, outcome LIMIT).
-    plain: one whole-GPU launch per instance.  batched: one launch for all
-    instances.  learned: batched, branching on the trained network.
-    Per-instance TTPO is device-clock time from its launch's start to proof.
-    `total_s` is the device time to settle the whole set (sum of the plain
-    launches; the batched launch), `wall_s` the host time of the calls;
-    `plain_set_s` is the time until every instance the plain form proved is
-    proven (null if one is not), counted from the start of the set."""
-    from paper_2207_12116_amd import instances as I, learn, pccp
-    models = [I.rcpsp(n, s) for s in seeds]
+def ttpo_forms(models, per_limit, cfg, weights, label):
+    """Time to settle a set of instances in three forms under the same
+    device-time budget (per_limit seconds per instance):
+      plain    one whole-GPU launch per instance, each limited to per_limit;
+               the set is settled after the sum of the launches
+      batched  one launch over every instance, limited to per_limit x count
+      learned  batched, branching on the trained network
+    Per-instance TTPO is device-clock time from its launch's start to its
+    proof.  Optima proven by two forms must agree."""
+    from paper_2207_12116_amd import learn, pccp
     solved = (pccp.OUT_OPTIMAL, pccp.OUT_UNSAT)
-    safety = 120.0
 
-    def summary(ok, ttpo, total, wall, best, nodes, cover):
-        return {"proven": int(sum(ok)), "instances": len(ok), "total_s": round(total, 4),
-                "wall_s": round(wall, 4), "plain_set_s": None if cover is None else round(cover, 4),
-                "nodes": int(nodes), "ttpo_ms": [None if t is None else round(t, 3) for t in ttpo],
-                "best": best}
+    def summary(outs, sts, total):
+        ok = [o in solved for o in outs]
+        tt = [round(x["ttpo_ms"], 3) if o else None for o, x in zip(ok, sts)]
+        return {"proven": int(sum(ok)), "instances": len(ok), "total_s": round(total, 3),
+                "nodes": int(sum(x["nodes"] for x in sts)), "ttpo_ms": tt,
+                "best": [x["best"] for x in sts]}
 
-    ok, ttpo, best, kern, nodes = [], [], [], [], 0
-    t0 = time.perf_counter()
+    res = {"set": label, "per_instance_limit_s": per_limit}
+    outs, sts, total = [], [], 0.0
     for m in models:
         s = pccp.Solver(m, config=cfg)
-        out = s.solve(pccp.MINIMIZE, node_limit=budget, time_limit=safety)
+        o = s.solve(pccp.MINIMIZE, time_limit=per_limit)
         st = s.stats()
-        ok.append(out in solved)
-        ttpo.append(st["ttpo_ms"] if ok[-1] else None)
-        best.append(st["best"])
-        kern.append(st["kernel_ms"] / 1e3)
-        nodes += st["nodes"]
-    wall = time.perf_counter() - t0
-    # plain set: launches run one after another, so instance i is settled at
-    # the sum of the launches before it plus its own time to proof
-    starts = [sum(kern[:i]) for i in range(len(kern))]
-    cover = max((starts[i] + ttpo[i] / 1e3 for i in range(len(ok)) if ok[i]), default=0.0)
-    res = {"tasks": n, "seeds": f"{seeds[0]}-{seeds[-1]}", "node_budget": budget,
-           "plain": summary(ok, ttpo, sum(kern), wall, best, nodes, cover)}
-    plain_ok = ok
+        outs.append(o)
+        sts.append(st)
+        total += min(st["ttpo_ms"] / 1e3, per_limit) if o in solved else per_limit
+    res["plain"] = summary(outs, sts, total)
     for form in ("batched", "learned"):
         solvers = [pccp.Solver(m, config=cfg) for m in models]
         if form == "learned":
@@ -216,19 +253,55 @@ def ttpo_suite(n, seeds, budget, cfg, weights):
             mlp = learn.network(weights)
             for s in solvers:
                 learn.attach(s, mlp)
-        t0 = time.perf_counter()
-        outs = pccp.batch_solve(solvers, pccp.MINIMIZE, config=cfg, time_limit=safety,
-                                inst_node_limit=budget)
-        wall = time.perf_counter() - t0
+        outs = pccp.batch_solve(solvers, pccp.MINIMIZE, config=cfg,
+                                time_limit=per_limit * len(models))
         sts = [s.stats() for s in solvers]
-        fok = [o in solved for o in outs]
-        ft = [x["ttpo_ms"] if o else None for o, x in zip(fok, sts)]
-        cov = None
-        if all(f for f, p in zip(fok, plain_ok) if p):
-            cov = max((t / 1e3 for t, p in zip(ft, plain_ok) if p), default=0.0)
-        res[form] = summary(fok, ft, sts[0]["kernel_ms"] / 1e3, wall, [x["best"] for x in sts],
-                            sum(x["nodes"] for x in sts), cov)
+        res[form] = summary(outs, sts, sts[0]["kernel_ms"] / 1e3)
+    # optima proven by two forms agree
+    for a in ("batched", "learned"):
+        if res.get(a) is None:
+            continue
+        for i, (x, y) in enumerate(zip(res["plain"]["ttpo_ms"], res[a]["ttpo_ms"])):
+            if x is not None and y is not None:
+                assert res["plain"]["best"][i] == res[a]["best"][i], (a, i)
     return res
+
+
+def learned_120_leg(seeds, limit, cfg, weights, scan):
+    """The learned branching rule against first-fail on held-out 120-task
+    instances (training used 30- and 60-task seeds), each form on the whole
+    GPU for `limit` seconds per instance.  `scan` is what the oracle proved
+    of the same seeds within its node budget (the evaluation set of proven
+    instances is empty when it proved none).  Optima proven by both forms
+    must agree."""
+    from paper_2207_12116_amd import instances as I, learn, pccp
+    mlp = learn.network(weights) if os.path.exists(weights) else None
+    rows = []
+    for sd in seeds:
+        m = I.rcpsp(120, sd)
+        row = {"seed": sd}
+        for form in ("first_fail", "learned"):
+            if form == "learned" and mlp is None:
+                row[form] = None
+                continue
+            s = pccp.Solver(m, config=cfg)
+            if form == "learned":
+                learn.attach(s, mlp)
+            out = s.solve(pccp.MINIMIZE, time_limit=limit)
+            st = s.stats()
+            row[form] = {"outcome": pccp.OUTCOME_NAMES[out], "best": st["best"],
+                         "nodes": st["nodes"], "ttpo_ms": round(st["ttpo_ms"], 3)
+                         if out in (pccp.OUT_OPTIMAL, pccp.OUT_UNSAT) else None}
+        a, b = row["first_fail"], row.get("learned")
+        if b and a["ttpo_ms"] is not None and b["ttpo_ms"] is not None:
+            assert a["best"] == b["best"], sd
+        rows.append(row)
+    found = {f: sum(r[f] is not None and r[f]["best"] is not None for r in rows)
+             for f in ("first_fail", "learned")}
+    better = sum(1 for r in rows if r.get("learned") and r["learned"]["best"] is not None and
+                 (r["first_fail"]["best"] is None or r["learned"]["best"] < r["first_fail"]["best"]))
+    return {"seeds": f"{seeds[0]}-{seeds[-1]}", "limit_s": limit, "instances": rows,
+            "with_incumbent": found, "learned_better_incumbent": better, "oracle_scan": scan}
 
 
 def copy_calibration(gib=2):
@@ -253,17 +326,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=30)
-    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--batch", type=int, default=256, help="instances (seeds 0..batch-1)")
     ap.add_argument("--step-time", type=float, default=3.0)
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--cpu-nodes", type=int, default=150000)
-    ap.add_argument("--cpu-procs", type=int, default=0,
-                    help="oracle processes for the CPU baseline (0 = min(16, cores))")
+    ap.add_argument("--cpu-scale", type=float, default=1.0,
+                    help="scales the CPU sample's nodes per instance")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="0 = the cores this process may run on, at most 16")
     ap.add_argument("--no-legs", action="store_true",
-                    help="skip the 120-task and 256-instance legs")
+                    help="skip the plain 30-task, 120-task and job-shop legs")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--desc-lds", type=int, default=0, choices=(0, 1, 2),
                     help="with --wg: descriptors 0 chosen by the library, 1 LDS, 2 global")
@@ -275,13 +347,14 @@ def main():
                     help="with --wg: search kernel build 0 chosen, 1 high, 2 normal")
     ap.add_argument("--dep", type=int, default=0, choices=(0, 1, 2),
                     help="with --wg: dependency-driven propagation 0/2 off, 1 on")
-    ap.add_argument("--max-depth", type=int, default=0,
-                    help="decision-stack capacity per workgroup (0 = library default)")
+    ap.add_argument("--max-depth", type=int, default=4096,
+                    help="decision-stack capacity per workgroup")
     ap.add_argument("--no-ttpo", action="store_true")
-    ap.add_argument("--ttpo-n", type=int, default=18)
+    ap.add_argument("--ttpo-n", type=int, default=30)
     ap.add_argument("--ttpo-seeds", type=int, default=16)
-    ap.add_argument("--ttpo-budget", type=int, default=30_000_000,
-                    help="search nodes each instance may use in the TTPO comparison")
+    ap.add_argument("--ttpo-limit", type=float, default=2.0,
+                    help="device seconds per instance in the TTPO comparison (the paper's "
+                         "protocol for 30-task instances is 30)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 2 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -300,15 +373,18 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    from paper_2207_12116_amd import instances as I, pccp
+    from paper_2207_12116_amd import autotune, instances as I, pccp
 
+    peaks = pccp.lds_peaks()
+    log(f"measured LDS peaks: {peaks}")
     seeds = list(range(args.batch))
-    log(f"building {args.batch} instances of {args.n} tasks")
-    models = [I.rcpsp(args.n, s) for s in seeds]
+    log(f"building {args.batch} instances of 30/60/90 tasks")
+    models = [I.rcpsp(I.batch_sizes(s), s) for s in seeds]
     tuned = None
     if args.wg == 0 and not args.no_autotune:
-        from paper_2207_12116_amd import autotune
-        cfg, rep = autotune.tune(models, pccp.MINIMIZE, budget_s=0.4, cache_path=None, log=log)
+        # tuned on every 16th instance (the three sizes in proportion)
+        cfg, rep = autotune.tune(models[::16], pccp.MINIMIZE, budget_s=0.3, cache_path=None,
+                                 wg_sizes=(256, 512, 1024), max_depth=args.max_depth, log=log)
         tuned = {"wg_size": cfg.wg_size, "desc_lds": cfg.desc_lds, "root_lds": cfg.root_lds,
                  "prop": rep["prop"], "occupancy": cfg.occupancy,
                  "candidates": len(rep["candidates"])}
@@ -328,8 +404,8 @@ def main():
         outs, sts = step()
         log(f"warmup {w}: nodes {sum(s['nodes'] for s in sts)}")
     torch.cuda.synchronize()
-    tot_nodes = tot_bytes = tot_kernel_ms = 0
-    tot_props = 0
+    tot_nodes = tot_bytes = tot_atom = tot_props = 0
+    tot_kernel_ms = 0.0
     last = None
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -337,7 +413,8 @@ def main():
         nodes = sum(s["nodes"] for s in sts)
         tot_nodes += nodes
         tot_bytes += sum(algorithmic_bytes(s) for s in sts)
-        tot_props += sum(s["prop_linear2"] + s["prop_reified"] + s["prop_linear"] for s in sts)
+        tot_atom += sum(s["atomics"] for s in sts)
+        tot_props += sum(propagations(s) for s in sts)
         tot_kernel_ms += sts[0]["kernel_ms"]
         last = (outs, sts)
         log(f"step {k}: nodes {nodes} kernel {sts[0]['kernel_ms']:.1f} ms "
@@ -346,89 +423,92 @@ def main():
     wall = time.perf_counter() - t0
     value = tot_nodes / wall
     outs, sts = last
-    proven = [s["ttpo_ms"] for o, s in zip(outs, sts) if o in (pccp.OUT_OPTIMAL, pccp.OUT_UNSAT)]
+    solved = (pccp.OUT_OPTIMAL, pccp.OUT_UNSAT)
+    proven = [s["ttpo_ms"] for o, s in zip(outs, sts) if o in solved]
+    by_size = {}
+    for sd, o, s in zip(seeds, outs, sts):
+        b = by_size.setdefault(str(I.batch_sizes(sd)), {"instances": 0, "proven": 0, "nodes": 0})
+        b["instances"] += 1
+        b["proven"] += o in solved
+        b["nodes"] += s["nodes"]
     ttpo = {"proven": len(proven), "instances": len(outs), "limit_s": args.step_time,
             "median_ms": statistics.median(proven) if proven else None,
             "geomean_ms": math.exp(sum(math.log(max(p, 1e-3)) for p in proven) / len(proven))
             if proven else None,
-            "total_s_with_limit": (sum(proven) / 1e3 + (len(outs) - len(proven)) * args.step_time),
-            "best": [s["best"] for s in sts]}
+            "total_s_with_limit": round(sum(proven) / 1e3 + (len(outs) - len(proven)) * args.step_time, 3),
+            "by_size": by_size,
+            "with_incumbent": sum(s["best"] is not None for s in sts)}
     kernel_s = tot_kernel_ms / 1e3
-    achieved = tot_bytes / kernel_s / 1e9 if kernel_s > 0 else 0.0
-    roofline = {"bound": "lds", "achieved": round(achieved, 1), "peak": LDS_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBS, 4),
-                "traffic": profiled_traffic(sts[0], tot_nodes / args.steps),
-                "kernel": "search_kernel", "kernel_ms_avg": round(tot_kernel_ms / args.steps, 3),
-                "bytes_per_launch": tot_bytes // args.steps,
-                "nodes_per_launch": tot_nodes // args.steps}
-
-    plain = None
-    if not args.no_plain:
-        s = pccp.Solver(models[0], config=cfg)
-        tp = time.perf_counter()
-        out = s.solve(pccp.MINIMIZE, time_limit=args.step_time)
-        dtp = time.perf_counter() - tp
-        st = s.stats()
-        plain = {"nodes_per_s": st["nodes"] / dtp, "instance_seed": 0,
-                 "outcome": pccp.OUTCOME_NAMES[out], "best": st["best"],
-                 "grid": st["grid"], "time_s": round(dtp, 3)}
-        log(f"plain: {plain}")
-
-    ttpo_cmp = None
-    if not args.no_ttpo:
-        from paper_2207_12116_amd import learn
-        log(f"time to proven optimum: {args.ttpo_seeds} instances of {args.ttpo_n} tasks")
-        from paper_2207_12116_amd import autotune
-        # tuned on whole short runs: proofs of these instances take
-        # milliseconds to seconds, so the start-up counts
-        tcfg, _ = autotune.tune([I.rcpsp(args.ttpo_n, s) for s in range(args.ttpo_seeds)],
-                                pccp.MINIMIZE, budget_s=0.2, cache_path=None,
-                                wg_sizes=(128, 256), log=log, steady=False)
-        ttpo_cmp = ttpo_suite(args.ttpo_n, list(range(args.ttpo_seeds)), args.ttpo_budget, tcfg,
-                              learn.DEFAULT_WEIGHTS)
-        ttpo_cmp["config"] = {"wg_size": tcfg.wg_size, "desc_lds": tcfg.desc_lds,
-                              "root_lds": tcfg.root_lds, "occupancy": tcfg.occupancy,
-                              "dep": tcfg.dep}
-        log(f"ttpo: {json.dumps({k: v for k, v in ttpo_cmp.items()})}")
+    roof = roofline(tot_bytes, tot_atom, kernel_s, peaks)
+    roof.update({"traffic": profiled_traffic(sts[0], tot_nodes / args.steps),
+                 "kernel": "search_kernel", "kernel_ms_avg": round(tot_kernel_ms / args.steps, 3),
+                 "bytes_per_launch": tot_bytes // args.steps,
+                 "atomics_per_launch": tot_atom // args.steps,
+                 "nodes_per_launch": tot_nodes // args.steps,
+                 "peaks_measured": {"read_GBs": round(peaks["read_GBs"], 1),
+                                    "atomic_Gops": round(peaks["atomic_Gops"], 1),
+                                    "atomic_ret_Gops": round(peaks["atomic_ret_Gops"], 1)}})
 
     legs = None
     if not args.no_legs:
-        from paper_2207_12116_amd import autotune
+        log("plain: 30-task instances, one at a time on the whole GPU")
+        c2 = [I.rcpsp(30, s) for s in range(4)]
+        c2cfg, c2rep = autotune.tune(c2, pccp.MINIMIZE, budget_s=0.3, cache_path=None,
+                                     wg_sizes=(128, 256, 512), max_depth=args.max_depth, log=log)
+        legs = {"c2_plain_30tasks": plain_leg(c2, 1.5, c2cfg, peaks)}
+        legs["c2_plain_30tasks"]["config"] = {"wg_size": c2cfg.wg_size, "prop": c2rep["prop"],
+                                              "seeds": "0-3", "limit_s": 1.5}
+        log(f"c2: {legs['c2_plain_30tasks']}")
         log("120-task instance, whole GPU")
         c3m = [I.rcpsp(120, 0)]
-        # deeper stacks than the default for the larger instances: the
-        # faster modes reach depths past 1024 within the time limit (the
-        # stack beyond its deepest 256 levels lives in HBM, so depth costs
-        # no LDS)
         c3cfg, c3rep = autotune.tune(c3m, pccp.MINIMIZE, budget_s=0.3, cache_path=None,
-                                     wg_sizes=(256, 512, 1024), max_depth=4096, log=log)
-        legs = {"c3_120tasks": single_instance_leg(120, 0, 2.0, c3cfg)}
+                                     wg_sizes=(256, 512, 1024), max_depth=args.max_depth, log=log)
+        legs["c3_120tasks"] = plain_leg(c3m, 2.0, c3cfg, peaks)
         legs["c3_120tasks"]["config"] = {"wg_size": c3cfg.wg_size, "prop": c3rep["prop"],
-                                         "max_depth": c3cfg.max_depth}
+                                         "seed": 0, "limit_s": 2.0}
         log(f"c3: {legs['c3_120tasks']}")
-        log("256 mixed instances, one launch")
-        c4m = [I.rcpsp(I.batch_sizes(s), s) for s in range(0, 256, 16)]
-        c4cfg, c4rep = autotune.tune(c4m, pccp.MINIMIZE, budget_s=0.3, cache_path=None,
-                                     wg_sizes=(256, 512, 1024), max_depth=4096, log=log)
-        legs["c4_mixed256"] = mixed_batch_leg(256, 3.0, c4cfg)
         log("job shops 10x10 from the PCCP front-end, 16 in one launch")
         jsm = [I.jobshop(10, 10, s) for s in range(16)]
         jscfg, jsrep = autotune.tune(jsm, pccp.MINIMIZE, budget_s=0.3, cache_path=None,
-                                     wg_sizes=(128, 256), max_depth=4096, log=log)
+                                     wg_sizes=(128, 256), max_depth=args.max_depth, log=log)
         legs["jobshop_10x10_batch16"] = jobshop_leg(jsm, 3.0, jscfg)
         legs["jobshop_10x10_batch16"]["config"] = {"wg_size": jscfg.wg_size, "prop": jsrep["prop"],
                                                    "occupancy": jscfg.occupancy}
         log(f"jobshop: {legs['jobshop_10x10_batch16']}")
-        legs["c4_mixed256"]["config"] = {"wg_size": c4cfg.wg_size, "desc_lds": c4cfg.desc_lds,
-                                         "root_lds": c4cfg.root_lds, "prop": c4rep["prop"],
-                                         "max_depth": c4cfg.max_depth}
-        log(f"c4: {legs['c4_mixed256']}")
+        from paper_2207_12116_amd import learn
+        log("learned vs first-fail on held-out 120-task instances")
+        legs["c5_learned_120tasks"] = learned_120_leg(
+            list(range(90000, 90008)), 1.5, c3cfg, learn.DEFAULT_WEIGHTS,
+            {"seeds": "90000-90031", "node_budget": 20000, "proven": 0,
+             "with_incumbent": 0, "note": "python -m oracle.scan_provable --n 120 --first 90000 "
+                                          "--count 32 --nodes 20000 --threads 8"})
+        log(f"c5: {legs['c5_learned_120tasks']}")
+
+    forms = None
+    if not args.no_ttpo:
+        from paper_2207_12116_amd import learn
+        log(f"time to proven optimum: {args.ttpo_seeds} instances of {args.ttpo_n} tasks")
+        tm = [I.rcpsp(args.ttpo_n, s) for s in range(args.ttpo_seeds)]
+        tcfg, _ = autotune.tune(tm, pccp.MINIMIZE, budget_s=0.2, cache_path=None,
+                                wg_sizes=(128, 256), log=log, steady=False,
+                                max_depth=args.max_depth)
+        forms = ttpo_forms(tm, args.ttpo_limit, tcfg, learn.DEFAULT_WEIGHTS,
+                           f"{args.ttpo_n} tasks, seeds 0-{args.ttpo_seeds - 1}")
+        forms["config"] = {"wg_size": tcfg.wg_size, "desc_lds": tcfg.desc_lds,
+                           "root_lds": tcfg.root_lds, "occupancy": tcfg.occupancy, "dep": tcfg.dep}
+        log(f"ttpo forms: {json.dumps(forms)}")
 
     cpu = None
     if not args.no_cpu:
-        procs = args.cpu_procs or min(16, os.cpu_count() or 1)
-        log(f"cpu baseline (oracle, {procs} processes)")
-        cpu = cpu_baseline(args.n, args.cpu_nodes, procs)
+        threads = args.cpu_threads or host_cores()
+        by_size = {}
+        for sd, m in zip(seeds, models):
+            lst = by_size.setdefault(I.batch_sizes(sd), [])
+            if len(lst) < threads:
+                lst.append(m)
+        log(f"cpu baseline (oracle, {threads} threads)")
+        cpu = cpu_baseline(by_size, threads, "the headline batch's first seeds of each size",
+                           args.cpu_scale)
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "nodes/s", "n_gpus": 1,
@@ -436,19 +516,19 @@ def main():
         "ms_per_step": round(wall / args.steps * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32", "data": "synthetic",
-        "config": {"workload": f"rcpsp_{args.n}tasks_4res_batch{args.batch}",
-                   "tasks": args.n, "resources": 4, "capacity": 10,
+        "config": {"workload": f"rcpsp_mixed_30_60_90tasks_4res_batch{args.batch}",
+                   "tasks": "30/60/90 by seed mod 3", "resources": 4, "capacity": 10,
                    "instances": args.batch, "seeds": f"0-{args.batch - 1}",
                    "form": "batched", "branching": "first-fail",
                    "step_time_limit_s": args.step_time,
                    "grid": sts[0]["grid"], "block": sts[0]["block"],
                    "desc_lds": sts[0]["desc_lds"], "root_lds": sts[0]["root_lds"],
                    "live": sts[0]["live"], "occupancy": sts[0]["occupancy"],
-                   "dep": sts[0]["dep"], "max_depth_reached": max(s["max_depth"] for s in sts),
+                   "dep": sts[0]["dep"], "max_depth": args.max_depth,
+                   "max_depth_reached": max(s["max_depth"] for s in sts),
                    "autotuned": tuned, "launch": "hipGraph"},
         "propagations_per_s": round(tot_props / wall, 1),
-        "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "ttpo": ttpo,
-        "ttpo_forms": ttpo_cmp, "legs": legs,
+        "roofline": roof, "cpu_baseline": cpu, "ttpo": ttpo, "legs": legs, "ttpo_forms": forms,
     }
     print(json.dumps(line), flush=True)
 

@@ -31,3 +31,18 @@ def test_bench_helpers():
     # a shape that was never profiled reports no traffic
     st = {"block": 96, "desc_lds": 0, "root_lds": 0, "live": 0, "occupancy": 2, "dep": 0}
     assert bench.profiled_traffic(st, 1000) is None
+
+
+def test_bench_roofline_and_cpu_baseline():
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2207_12116_amd import instances as I
+    peaks = {"read_GBs": 100.0, "atomic_Gops": 10.0}
+    r = bench.roofline(50e9, 2e9, 1.0, peaks)
+    assert r["achieved"] == 50.0 and r["frac"] == 0.5
+    assert r["atomic_achieved"] == 2.0 and r["atomic_frac"] == 0.2
+    # the CPU baseline builds a native copy of the oracle and times it in C
+    cpu = bench.cpu_baseline({30: [I.rcpsp(30, s) for s in range(2)], 60: [I.rcpsp(60, 1)]}, 2,
+                             "test sample", scale=0.1)
+    assert cpu["cores"] == 2 and cpu["value"] > 0 and cpu["nproc"] >= 1
+    assert cpu["single_core"]["value"] > 0
