@@ -290,7 +290,10 @@ extern "C" int32_t pccp_model_load_file(const char *path, pccp_model **out)
 // rows with their terms, decision variables.
 struct Compiled {
     int32_t nvars = 0, ndec = 0, objective = -1;
-    std::vector<int32_t> lb0, ub0, dec;
+    int32_t nI = 0;                   // variables stored as pairs; the rest are Booleans
+    std::vector<int32_t> lb0, ub0, dec;   // in store numbering
+    std::vector<int32_t> vorig, vnew;     // store index <-> the model's index
+    std::vector<int32_t> lb0_model, ub0_model;  // the initial box in the model's numbering
     std::vector<int2> diff, reif;
     std::vector<int4> rows;
     std::vector<uint32_t> terms;
@@ -425,7 +428,53 @@ static void compile_features(const pccp_model *m, Compiled &c)
     }
 }
 
-static int32_t compile_model(const pccp_model *m, Compiled &c)
+// The store keeps the variables whose initial domain is not inside [0, 1]
+// as int32 pairs and the others (Booleans) as one byte each, pairs first:
+// a copy of the model renumbered in that order (each group in the model's
+// order).  An index out of range is kept out of range, so that the checks
+// below still refuse it.
+static void renumber(const pccp_model *m, pccp_model &r, Compiled &c)
+{
+    const int32_t V = (int32_t)m->lb.size();
+    c.vorig.clear();
+    for (int pass = 0; pass < 2; ++pass)
+        for (int32_t x = 0; x < V; ++x) {
+            const bool isb = m->lb[x] >= 0 && m->ub[x] <= 1;
+            if (isb == (pass == 1)) c.vorig.push_back(x);
+        }
+    c.nI = 0;
+    for (int32_t x = 0; x < V; ++x) c.nI += !(m->lb[x] >= 0 && m->ub[x] <= 1);
+    c.vnew.assign(V, 0);
+    for (int32_t i = 0; i < V; ++i) c.vnew[c.vorig[i]] = i;
+    auto map = [&](int32_t x) { return x >= 0 && x < V ? c.vnew[x] : x; };
+    r = *m;
+    c.lb0_model = m->lb;
+    c.ub0_model = m->ub;
+    for (int32_t i = 0; i < V; ++i) {
+        r.lb[i] = m->lb[c.vorig[i]];
+        r.ub[i] = m->ub[c.vorig[i]];
+    }
+    for (int32_t &x : r.var) x = map(x);
+    for (size_t q = 0; q < r.reif.size() / 4; ++q)
+        for (int k = 0; k < 3; ++k) r.reif[4 * q + k] = map(r.reif[4 * q + k]);
+    for (int32_t &x : r.dec) x = map(x);
+    r.objective = map(r.objective);
+    for (size_t q = 0; q < r.cmd.size() / 4; ++q) r.cmd[4 * q] = map(r.cmd[4 * q]);
+    for (size_t g = 0; g < r.guard.size() / 3; ++g) r.guard[3 * g] = map(r.guard[3 * g]);
+    for (size_t t = 0; t < r.cterm.size() / 2; ++t) r.cterm[2 * t + 1] = map(r.cterm[2 * t + 1]);
+}
+
+static int32_t compile_renumbered(const pccp_model *m, Compiled &c);
+
+static int32_t compile_model(const pccp_model *m0, Compiled &c)
+{
+    if ((int64_t)m0->lb.size() > kMaxVars) return fail(PCCP_E_UNSUPPORTED, "more than 65535 variables");
+    pccp_model r;
+    renumber(m0, r, c);
+    return compile_renumbered(&r, c);
+}
+
+static int32_t compile_renumbered(const pccp_model *m, Compiled &c)
 {
     const int64_t LIM = (int64_t)1 << 30;
     const int32_t V = (int32_t)m->lb.size();
@@ -701,7 +750,7 @@ extern "C" int32_t pccp_solver_create(const pccp_model *m, const pccp_config *cf
     s->desc_bytes = model_desc_bytes((int)c.diff.size(), (int)c.reif.size(), (int)c.rows.size(),
                                      (int)c.terms.size(), c.ndec, (int)c.brows.size(),
                                      (int)c.bterms.size());
-    if (propagate_lds_bytes(c.nvars, 0, false) > s->lds_max) {
+    if (propagate_lds_bytes(store_bytes(c.nI, c.nvars), 0, false) > s->lds_max) {
         delete s;
         return fail(PCCP_E_LDS_CAPACITY, "the store (8 bytes per variable) does not fit in LDS");
     }
@@ -725,7 +774,9 @@ extern "C" int32_t pccp_solver_create(const pccp_model *m, const pccp_config *cf
     const size_t o_cmd = o_adj + al(4 * c.adj.size());
     const size_t o_ccnt = o_cmd + al(16 * c.cmds.size());
     const size_t o_cent = o_ccnt + al(4 * c.ccnt.size());
-    const size_t total = o_cent + al(8 * c.cent.size()) + 256;
+    const size_t o_vorig = o_cent + al(8 * c.cent.size());
+    const size_t o_vnew = o_vorig + al(4 * c.vorig.size());
+    const size_t total = o_vnew + al(4 * c.vnew.size()) + 256;
     rc = s->tables.ensure(total);
     if (rc == PCCP_OK) rc = s->dmodel.ensure(sizeof(DevModel));
     if (rc != PCCP_OK) { delete s; return rc; }
@@ -751,8 +802,13 @@ extern "C" int32_t pccp_solver_create(const pccp_model *m, const pccp_config *cf
     put(o_cmd, c.cmds.data(), 16 * c.cmds.size());
     put(o_ccnt, c.ccnt.data(), 4 * c.ccnt.size());
     put(o_cent, c.cent.data(), 8 * c.cent.size());
+    put(o_vorig, c.vorig.data(), 4 * c.vorig.size());
+    put(o_vnew, c.vnew.data(), 4 * c.vnew.size());
     DevModel &dm = s->hmodel;
     dm.nvars = c.nvars;
+    dm.nI = c.nI;
+    dm.vorig = reinterpret_cast<const int32_t *>(base + o_vorig);
+    dm.vnew = reinterpret_cast<const int32_t *>(base + o_vnew);
     dm.ndiff = (int32_t)c.diff.size();
     dm.nreif = (int32_t)c.reif.size();
     dm.nrows = (int32_t)c.rows.size();
@@ -828,7 +884,7 @@ extern "C" int32_t pccp_solver_destroy(pccp_solver *s)
 // ------------------------------------------------------------------ propagate
 static bool choose_prop_desc(const pccp_solver *s)
 {
-    const bool fits = propagate_lds_bytes(s->c.nvars, s->desc_bytes, true) <= s->lds_max;
+    const bool fits = propagate_lds_bytes(store_bytes(s->c.nI, s->c.nvars), s->desc_bytes, true) <= s->lds_max;
     if (s->cfg.desc_lds == 2) return false;
     return fits;
 }
@@ -843,7 +899,7 @@ extern "C" int32_t pccp_propagate_batch(pccp_solver *s, int32_t nbox, const int3
     if (s->cfg.desc_lds == 1 && !choose_prop_desc(s))
         return fail(PCCP_E_LDS_CAPACITY, "propagator tables do not fit in LDS next to the store");
     const bool dl = choose_prop_desc(s);
-    const size_t lds = propagate_lds_bytes(s->c.nvars, s->desc_bytes, dl);
+    const size_t lds = propagate_lds_bytes(store_bytes(s->c.nI, s->c.nvars), s->desc_bytes, dl);
     const int grid = std::min(nbox, std::max(1, s->num_cus * 8));
     HIPCHK(hipSetDevice(s->device));
     HIPCHK(launch_propagate_batch(reinterpret_cast<const DevModel *>(s->dmodel.p), nbox, lb_in,
@@ -863,8 +919,8 @@ extern "C" int32_t pccp_propagate(pccp_solver *s, const int32_t *lb_in, const in
     int32_t *d = s->box.as<int32_t>();
     int32_t *dlb = d, *dub = d + V, *olb = d + 2 * V, *oub = d + 3 * V, *dst = d + 4 * V;
     HIPCHK(hipSetDevice(s->device));
-    const int32_t *slb = lb_in ? lb_in : s->c.lb0.data();
-    const int32_t *sub = ub_in ? ub_in : s->c.ub0.data();
+    const int32_t *slb = lb_in ? lb_in : s->c.lb0_model.data();
+    const int32_t *sub = ub_in ? ub_in : s->c.ub0_model.data();
     HIPCHK(hipMemcpyAsync(dlb, slb, 4 * V, hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipMemcpyAsync(dub, sub, 4 * V, hipMemcpyHostToDevice, s->stream));
     rc = pccp_propagate_batch(s, 1, dlb, dub, olb, oub, dst, dst + 1);
@@ -888,7 +944,7 @@ extern "C" int32_t pccp_node_features(pccp_solver *s, int32_t nbox, const int32_
         return fail(PCCP_E_INVALID_ARG, "pccp_node_features: bad arguments");
     if (nbox == 0 || s->c.ndec == 0) return PCCP_OK;
     HIPCHK(hipSetDevice(s->device));
-    HIPCHK(launch_features(reinterpret_cast<const DevModel *>(s->dmodel.p), s->c.nvars, nbox, lb, ub,
+    HIPCHK(launch_features(reinterpret_cast<const DevModel *>(s->dmodel.p), store_bytes(s->c.nI, s->c.nvars), nbox, lb, ub,
                            feat, s->stream));
     return PCCP_OK;
 }
@@ -909,6 +965,7 @@ extern "C" int32_t pccp_get_domains(pccp_solver *s, int32_t *lb, int32_t *ub, in
 // whether its propagator counts allow 16-bit list entries.
 struct ShapeNeed {
     int max_vars = 0;
+    size_t max_store = 0;     // bytes of the largest store (store_bytes)
     size_t max_desc = 0;
     int max_items[kDepKinds] = {0, 0, 0, 0, 0};   // per kind; [4] = guarded commands
     int feat_ndec = 0;        // learned branching: feature scratch per candidate
@@ -968,7 +1025,7 @@ static int32_t choose_shape(const pccp_config &cfg, const ShapeNeed &nd, int num
     for (const Cand &cd : cands) {
         if (cfg.desc_lds != 0 && cd.d != (cfg.desc_lds == 1)) continue;
         if (cfg.root_lds != 0 && cd.r != (cfg.root_lds == 1)) continue;
-        const size_t base = search_lds_bytes(nd.max_vars, cfg.max_depth, nd.max_desc, cd.d, cd.r,
+        const size_t base = search_lds_bytes(nd.max_store, cfg.max_depth, nd.max_desc, cd.d, cd.r,
                                              nd.feat_ndec, list_items, 0);
         if (base > lds_max) continue;
         SearchShape k;
@@ -989,7 +1046,7 @@ static int32_t choose_shape(const pccp_config &cfg, const ShapeNeed &nd, int num
                 dl.jcap = sh.block >= 512 && !k.hi ? 512 : 0;
                 depb = dep_lds_bytes(dl.vshift, dl.qw, dl.wcap, dl.jcap);
             }
-            const size_t lds = search_lds_bytes(nd.max_vars, cfg.max_depth, nd.max_desc, cd.d, cd.r,
+            const size_t lds = search_lds_bytes(nd.max_store, cfg.max_depth, nd.max_desc, cd.d, cd.r,
                                                 nd.feat_ndec, list_items, depb);
             if (lds > lds_max) continue;
             int occ = 0;
@@ -1027,6 +1084,7 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
     int32_t rc = check_cfg(cfg);
     if (rc != PCCP_OK) return rc;
     int max_vars = 0, max_ndec = 1;
+    size_t max_store = 0;
     int max_items[kDepKinds] = {0, 0, 0, 0, 0};
     size_t max_desc = 0;
     for (int i = 0; i < n; ++i) {
@@ -1035,6 +1093,7 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
         if (mode == PCCP_MINIMIZE && sv[i]->c.objective < 0)
             return fail(PCCP_E_STATE, "search: MINIMIZE without an objective");
         max_vars = std::max(max_vars, sv[i]->c.nvars);
+        max_store = std::max(max_store, store_bytes(sv[i]->c.nI, sv[i]->c.nvars));
         max_ndec = std::max(max_ndec, sv[i]->c.ndec);
         max_desc = std::max(max_desc, sv[i]->desc_bytes);
         max_items[0] = std::max(max_items[0], (int)sv[i]->c.diff.size());
@@ -1048,6 +1107,7 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
     LaunchShape sh;
     ShapeNeed need;
     need.max_vars = max_vars;
+    need.max_store = max_store;
     need.max_desc = max_desc;
     for (int k = 0; k < kDepKinds; ++k) need.max_items[k] = max_items[k];
     need.feat_ndec = learned ? max_ndec : 0;
@@ -1069,7 +1129,7 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
     const size_t z_models = sizeof(DevModel) * n, z_inst = sizeof(InstState) * n;
     const size_t z_glob = sizeof(SearchGlobals), z_qseq = sizeof(unsigned long long) * qcap;
     const size_t z_qdata = (size_t)slot_bytes * qcap, z_best = sizeof(int32_t) * (size_t)n * max_ndec;
-    const size_t z_roots = sh.k.root_lds ? 0 : sizeof(int32_t) * 2 * (size_t)Vp * sh.grid;
+    const size_t z_roots = sh.k.root_lds ? 0 : max_store * sh.grid;
     const size_t z_trail = sh.k.dep ? sizeof(int4) * (size_t)tcap * sh.grid : 0;
     const size_t z_gstack = sizeof(int4) * (size_t)cfg.max_depth * sh.grid;
     DevModel *w_models = nullptr;
@@ -1149,8 +1209,9 @@ static int32_t run_search(pccp_solver *const *sv, int32_t n, int32_t mode, const
     P.q_data = w_qdata;
     P.qcap = qcap;
     P.slot_bytes = slot_bytes;
-    P.root_scratch = sh.k.root_lds ? nullptr : w_roots;
+    P.root_scratch = sh.k.root_lds ? nullptr : reinterpret_cast<char *>(w_roots);
     P.max_vars = max_vars;
+    P.max_store = (long long)max_store;
     P.donate = sh.grid > 1 ? 1 : 0;
     P.node_limit = lim ? lim->node_limit : 0;
     P.inst_node_limit = lim ? lim->inst_node_limit : 0;
@@ -1346,6 +1407,7 @@ extern "C" int32_t pccp_solver_capacity(const pccp_solver *s, int32_t *wgs_per_c
     HIPCHK(hipSetDevice(s->device));
     ShapeNeed need;
     need.max_vars = s->c.nvars;
+    need.max_store = store_bytes(s->c.nI, s->c.nvars);
     need.max_desc = s->desc_bytes;
     need.max_items[0] = (int)s->c.diff.size();
     need.max_items[1] = (int)s->c.reif.size();
@@ -1387,7 +1449,7 @@ extern "C" int32_t pccp_propagate_batch_incr(pccp_solver *s, int32_t nbox, const
     for (int li = 0; li < 8 && !fits; ++li) {
         dl = dep_layout(c.nvars, items, 1 << li);
         dl.jcap = block >= 512 ? 512 : 0;
-        lds = propagate_lds_bytes(c.nvars, 0, false) + dep_lds_bytes(dl.vshift, dl.qw, dl.wcap, dl.jcap);
+        lds = propagate_lds_bytes(store_bytes(c.nI, c.nvars), 0, false) + dep_lds_bytes(dl.vshift, dl.qw, dl.wcap, dl.jcap);
         fits = lds <= s->lds_max;
     }
     if (!fits)

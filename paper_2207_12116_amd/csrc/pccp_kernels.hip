@@ -69,24 +69,79 @@ __device__ __forceinline__ void join_ub(int32_t *p, int32_t v)
     __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// The store: variable x is the pair st[x] = (lb, ub), so one 64-bit LDS read
-// fetches both bounds.  Each half is joined on its own by a 32-bit atomic;
-// the 64-bit read is single-copy atomic per half, which is all a propagator
-// needs (it may see one bound newer than the other, as with two reads).
-__device__ __forceinline__ int2 dom(const int2 *st, int x)
+// The store of a subproblem.  A variable whose initial domain is not inside
+// [0, 1] is the pair p[x] = (lb, ub), so one 64-bit LDS read fetches both
+// bounds, and each half is joined on its own by a 32-bit atomic max / min
+// (the 64-bit read is single-copy atomic per half, which is all a
+// propagator needs: it may see one bound newer than the other, as with two
+// reads).  A Boolean (initial domain inside [0, 1]; store indices nI and
+// up) is one byte of the words b: bit 0 set means lb = 1, bit 1 set means
+// ub = 0, both set the empty interval.  Both of a Boolean's tells are then
+// atomic ORs (the join of the two-bit lattice), and a Boolean costs one
+// byte of LDS instead of eight: the reified overlaps of the scheduling
+// models have n^2 Booleans against n + 1 integers, so the store of a
+// 120-task instance shrinks from 113 KiB to 15 KiB.  Tells of values
+// outside [0, 1] on a Boolean empty it, as they would an interval.
+struct Store {
+    int2 *p;          // pairs [0, nI)
+    uint32_t *b;      // Boolean bytes: variable x >= nI at byte x - nI
+    int nI;
+};
+
+__device__ __forceinline__ Store make_store(char *base, int nI)
 {
-    const unsigned long long u =
-        __hip_atomic_load(reinterpret_cast<unsigned long long *>(const_cast<int2 *>(st + x)),
-                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    return make_int2((int32_t)(uint32_t)u, (int32_t)(uint32_t)(u >> 32));
+    Store s;
+    s.p = reinterpret_cast<int2 *>(base);
+    s.b = reinterpret_cast<uint32_t *>(base + 8 * (size_t)store_pairs(nI));
+    s.nI = nI;
+    return s;
 }
-__device__ __forceinline__ void tell_lb(int2 *st, int x, int32_t v)
+
+__device__ __forceinline__ int2 dom(const Store st, int x)
 {
-    join_lb(reinterpret_cast<int32_t *>(st) + 2 * x, v);
+    if (x < st.nI) {
+        const unsigned long long u =
+            __hip_atomic_load(reinterpret_cast<unsigned long long *>(st.p + x),
+                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        return make_int2((int32_t)(uint32_t)u, (int32_t)(uint32_t)(u >> 32));
+    }
+    const uint32_t y = (uint32_t)(x - st.nI);
+    const uint32_t w = __hip_atomic_load(st.b + (y >> 2), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const uint32_t c = w >> (8 * (y & 3u));
+    return make_int2((int32_t)(c & 1u), (int32_t)((~c >> 1) & 1u));
 }
-__device__ __forceinline__ void tell_ub(int2 *st, int x, int32_t v)
+// the bits of a Boolean for the interval (lb, ub) (only ever a non-empty
+// one, or one emptied by a bound beyond [0, 1])
+__device__ __forceinline__ uint32_t bool_bits(int32_t lb, int32_t ub)
 {
-    join_ub(reinterpret_cast<int32_t *>(st) + 2 * x + 1, v);
+    return (lb >= 1 ? 1u : 0u) | (ub <= 0 ? 2u : 0u) | (lb >= 2 || ub < 0 ? 3u : 0u);
+}
+__device__ __forceinline__ void bool_or(const Store st, int x, uint32_t bits)
+{
+    const uint32_t y = (uint32_t)(x - st.nI);
+    __hip_atomic_fetch_or(st.b + (y >> 2), bits << (8 * (y & 3u)), __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void tell_lb(const Store st, int x, int32_t v)
+{
+    if (x < st.nI) join_lb(reinterpret_cast<int32_t *>(st.p) + 2 * x, v);
+    else if (v >= 1) bool_or(st, x, v >= 2 ? 3u : 1u);
+}
+__device__ __forceinline__ void tell_ub(const Store st, int x, int32_t v)
+{
+    if (x < st.nI) join_ub(reinterpret_cast<int32_t *>(st.p) + 2 * x + 1, v);
+    else if (v <= 0) bool_or(st, x, v < 0 ? 3u : 2u);
+}
+// write a variable's interval (no concurrent tell on the same variable; a
+// Boolean's byte is written alone, its neighbours are untouched)
+__device__ __forceinline__ void set_dom(const Store st, int x, int2 d)
+{
+    if (x < st.nI) {
+        st.p[x] = d;
+    } else {
+        const uint32_t y = (uint32_t)(x - st.nI);
+        reinterpret_cast<uint8_t *>(st.b)[y] = (uint8_t)bool_bits(d.x, d.y);
+    }
 }
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -414,7 +469,7 @@ __device__ __forceinline__ void trail_push(const Dep &dp, int x, int2 rd)
 // tell lb(x) >= v (or ub(x) <= v) with marks: rd = (lb, ub) of x as the lane
 // read it before deciding to tell
 template <bool MK, bool LB>
-__device__ __forceinline__ void tell_m(int2 *st, const Dep &dp, int x, int32_t v, int2 rd)
+__device__ __forceinline__ void tell_m(const Store st, const Dep &dp, int x, int32_t v, int2 rd)
 {
     if constexpr (MK) {
         const uint32_t w = (uint32_t)x & (uint32_t)dp.vmask, bit = 1u << ((uint32_t)x >> dp.vshift);
@@ -444,7 +499,7 @@ __device__ __forceinline__ int group_sum(int x, int G)
 // kind 1: x - y <= c  =>  ub(x) <= c + ub(y),  lb(y) >= lb(x) - c;
 // entailed once ub(x) - lb(y) <= c.
 template <bool DL, bool MK = false>
-__device__ __forceinline__ void sweep_diff(const View<DL> &v, int2 *st, const ListIO &io,
+__device__ __forceinline__ void sweep_diff(const View<DL> &v, const Store st, const ListIO &io,
                                            const Dep &dp, bool &chg, bool &bad, uint32_t &nat)
 {
     constexpr int U = 2;
@@ -520,7 +575,7 @@ __device__ __forceinline__ void sweep_diff(const View<DL> &v, int2 *st, const Li
 // Entailed once b = 1 with both conjuncts entailed, or b = 0 with one of
 // them disentailed (lb(si) > ub(sj), or lb(sj) >= ub(si) + d).
 template <bool DL, int U, bool MK = false>
-__device__ __forceinline__ void sweep_reif(const View<DL> &v, int2 *st, const ListIO &io,
+__device__ __forceinline__ void sweep_reif(const View<DL> &v, const Store st, const ListIO &io,
                                            const Dep &dp, bool &chg, bool &bad, uint32_t &nat)
 {
     const int tid = threadIdx.x, lane = tid & 63, W = blockDim.x, n = io.n;
@@ -605,7 +660,7 @@ __device__ __forceinline__ bool term_tight(int a, int lbx, int ubx, int rhs, int
 }
 
 template <bool MK = false>
-__device__ __forceinline__ void term_tell(int2 *st, const Dep &dp, int x, int a, int lbx, int ubx,
+__device__ __forceinline__ void term_tell(const Store st, const Dep &dp, int x, int a, int lbx, int ubx,
                                           int rhs, int S, bool &chg, bool &bad)
 {
     if (a > 0) {
@@ -627,7 +682,7 @@ __device__ __forceinline__ void term_tell(int2 *st, const Dep &dp, int x, int a,
 // tells use the bounds already in registers.  Entailed once the sum of the
 // terms' largest values is at most rhs.
 template <bool DL, int RR, bool MK = false>
-__device__ __forceinline__ void sweep_rows(const View<DL> &v, int2 *st, const ListIO &io,
+__device__ __forceinline__ void sweep_rows(const View<DL> &v, const Store st, const ListIO &io,
                                            const Dep &dp, bool &chg, bool &bad, uint32_t &nat)
 {
     constexpr int TK = 2;
@@ -766,7 +821,7 @@ __device__ __forceinline__ void sweep_rows(const View<DL> &v, int2 *st, const Li
 // a = 0.  Entailed once the sum of a_t over the terms with ub(b_t) = 1 is at
 // most rhs.
 template <bool DL, int RB, bool MK = false>
-__device__ __forceinline__ void sweep_brows(const View<DL> &v, int2 *st, const ListIO &io,
+__device__ __forceinline__ void sweep_brows(const View<DL> &v, const Store st, const ListIO &io,
                                             const Dep &dp, bool &chg, bool &bad, uint32_t &nat)
 {
     constexpr int TB = 4;                   // term slots per lane held in registers
@@ -905,7 +960,7 @@ __device__ __forceinline__ void sweep_brows(const View<DL> &v, int2 *st, const L
 // compacted into item lists; they run whole-table in the every-table and
 // item-list modes, and from their work list in the dependency-driven mode.
 template <bool DL, bool MK = false>
-__device__ __forceinline__ void sweep_cmd(const View<DL> &v, int2 *st, const ListIO &io,
+__device__ __forceinline__ void sweep_cmd(const View<DL> &v, const Store st, const ListIO &io,
                                           const Dep &dp, bool &chg, bool &bad, uint32_t &nat)
 {
     const int tid = threadIdx.x, lane = tid & 63, W = blockDim.x, n = io.n;
@@ -998,7 +1053,7 @@ struct NodeLists {
 // LIVE: L may carry lists.  LEAN: fewer items per lane per chunk (for the
 // lists' compaction, and for the high-occupancy search kernel).
 template <bool DL, bool LIVE, bool LEAN = LIVE>
-__device__ int propagate_wg(const View<DL> &v, int2 *st, int32_t *ctl, const NodeLists &L,
+__device__ __forceinline__ int propagate_wg(const View<DL> &v, const Store st, int32_t *ctl, const NodeLists &L,
                             uint32_t &nsweeps, unsigned long long (&ex)[4], uint32_t &nat)
 {
     const int tid = threadIdx.x, lane = tid & 63;
@@ -1103,7 +1158,7 @@ __device__ __forceinline__ void dep_queue(const View<DL> &v, const Dep &dp, int3
 }
 
 template <bool DL>
-__device__ void dep_expand(const View<DL> &v, const Dep &dp, int32_t *cnt)
+__device__ __forceinline__ void dep_expand(const View<DL> &v, const Dep &dp, int32_t *cnt)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int base = 0; base < dp.vw; base += 64 * nw) {
@@ -1147,7 +1202,7 @@ __device__ void dep_expand(const View<DL> &v, const Dep &dp, int32_t *cnt)
 // loads the adjacency ranges of 64 listed variables at a time, numbers
 // their chunks of 64 entries in list order and takes chunks wid, wid + nw,
 // ...  A list longer than jcap makes the next sweep run every table.
-__device__ void dep_expand_list(const Dep &dp)
+__device__ __forceinline__ void dep_expand_list(const Dep &dp)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int base = 0; base < dp.vw; base += 64 * nw) {
@@ -1172,7 +1227,7 @@ __device__ void dep_expand_list(const Dep &dp)
 }
 
 template <bool DL>
-__device__ void dep_expand_jobs(const View<DL> &v, const Dep &dp, int32_t *cnt)
+__device__ __forceinline__ void dep_expand_jobs(const View<DL> &v, const Dep &dp, int32_t *cnt)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int n = uni(lds_ld(dp.jcnt));
@@ -1223,7 +1278,7 @@ __device__ void dep_expand_jobs(const View<DL> &v, const Dep &dp, int32_t *cnt)
 // TWO: the build may run the two-phase expansion (workgroups of 8 or more
 // wavefronts, dp.jcap > 0); the high-occupancy build never does.
 template <bool DL, bool LEAN, bool TWO>
-__device__ int propagate_dep(const View<DL> &v, int2 *st, int32_t *ctl, const Dep &dp, bool full,
+__device__ __forceinline__ int propagate_dep(const View<DL> &v, const Store st, int32_t *ctl, const Dep &dp, bool full,
                              uint32_t &nsweeps, unsigned long long (&ex)[4], uint32_t &nat)
 {
     const int tid = threadIdx.x, lane = tid & 63, W = blockDim.x;
@@ -1314,6 +1369,86 @@ __device__ int propagate_dep(const View<DL> &v, int2 *st, int32_t *ctl, const De
     }
 }
 
+// ------------------------------------------------------ store copies
+// A store occupies store_bytes(nI, nvars) bytes: pairs rounded up to an even
+// count (the padding pair holds (0, 0)), then the Boolean words rounded up
+// to a multiple of four (padding bytes 0: the open interval [0, 1]); so the
+// whole store is a whole number of 16-byte blocks and neither padding reads
+// as empty.
+
+// Does some interval of the store (every lane's share) read as empty?
+__device__ __forceinline__ bool store_failed(const Store st, int nvars)
+{
+    const int tid = threadIdx.x, W = blockDim.x;
+    bool bad = false;
+    const int np = store_pairs(st.nI) >> 1;            // two pairs per 16 bytes
+    const int4 *s4 = reinterpret_cast<const int4 *>(st.p);
+    for (int q = tid; q < np; q += W) {
+        const int4 a = s4[q];
+        bad |= (a.x > a.y) | (a.z > a.w);
+    }
+    const int nb = store_bool_words(st.nI, nvars) >> 2;  // four words per 16 bytes
+    const uint4 *b4 = reinterpret_cast<const uint4 *>(st.b);
+    for (int q = tid; q < nb; q += W) {
+        const uint4 w = b4[q];
+        bad |= (((w.x & (w.x >> 1)) | (w.y & (w.y >> 1)) | (w.z & (w.z >> 1)) |
+                 (w.w & (w.w >> 1))) & 0x01010101u) != 0u;
+    }
+    return bad;
+}
+
+// st <- the box (lb, ub) of global arrays; with `orig`, store variable x
+// reads entry orig[x] (the model's numbering), else entry x
+__device__ __forceinline__ void load_box(const Store st, const int32_t *lb0, const int32_t *ub0,
+                                         int nvars, const int32_t *orig = nullptr)
+{
+    const int tid = threadIdx.x, W = blockDim.x, nIp = store_pairs(st.nI);
+    for (int x = tid; x < nIp; x += W) {
+        const int i = x < st.nI ? (orig ? gread(orig + x) : x) : 0;
+        st.p[x] = x < st.nI ? make_int2(gread(lb0 + i), gread(ub0 + i)) : make_int2(0, 0);
+    }
+    const int nw = store_bool_words(st.nI, nvars);
+    for (int w = tid; w < nw; w += W) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int x = st.nI + 4 * w + k;
+            if (x < nvars) {
+                const int i = orig ? gread(orig + x) : x;
+                word |= bool_bits(gread(lb0 + i), gread(ub0 + i)) << (8 * k);
+            }
+        }
+        st.b[w] = word;
+    }
+}
+
+// write the store to global arrays (entry orig[x] for store variable x)
+__device__ __forceinline__ void store_box(const Store st, int32_t *lb, int32_t *ub, int nvars,
+                                          const int32_t *orig)
+{
+    const int tid = threadIdx.x, W = blockDim.x;
+    for (int x = tid; x < nvars; x += W) {
+        const int2 d = dom(st, x);
+        const int i = gread(orig + x);
+        gwrite(lb + i, d.x);
+        gwrite(ub + i, d.y);
+    }
+}
+
+// copy a whole store (bytes of the same layout) from src to dst;
+// SG/DG: source/destination in global memory (else LDS)
+template <bool SG, bool DG>
+__device__ __forceinline__ void copy_store(char *dst, const char *src, int nI, int nvars)
+{
+    const int tid = threadIdx.x, W = blockDim.x, nq = (int)(store_bytes(nI, nvars) >> 4);
+    const int4 *s4 = reinterpret_cast<const int4 *>(src);
+    int4 *d4 = reinterpret_cast<int4 *>(dst);
+    for (int q = tid; q < nq; q += W) {
+        const int4 a = SG ? gread(s4 + q) : s4[q];
+        if (DG) gwrite4(d4 + q, a); else d4[q] = a;
+    }
+}
+
 // ------------------------------------------------------ learned branching
 // Features of decision variable q in the store (lb, ub) (x = dec[q], initial
 // interval [lo, hi], H = max(1, hi - lo)):
@@ -1325,7 +1460,7 @@ __device__ int propagate_dep(const View<DL> &v, int2 *st, int32_t *ctl, const De
 // (global memory), so the propagation view stays small.
 template <bool DL>
 __device__ __forceinline__ void candidate_features(const View<DL> &v, const DevModel *m, int q,
-                                                   const int2 *st, float f[kNumFeat])
+                                                   const Store st, float f[kNumFeat])
 {
     const int x = v.dec(q);
     const float *fs = m->fstat + 8 * (size_t)q;
@@ -1405,18 +1540,12 @@ __device__ __forceinline__ unsigned long long score_key(float s, int q)
 // With branching 2 (learned), `fsc` is an LDS scratch of 8 floats per
 // decision variable and `ml` the lane's slice of the network.
 template <bool DL>
-__device__ void post_scan(const View<DL> &v, const int2 *st, int32_t *ctl,
+__device__ __forceinline__ void post_scan(const View<DL> &v, const Store st, int32_t *ctl,
                           int branching, bool branch, float *fsc = nullptr,
                           const uint16_t *mlp = nullptr, const DevModel *m = nullptr)
 {
     const int tid = threadIdx.x, W = blockDim.x, lane = tid & 63;
-    bool bad = false;
-    const int nq = ((v.nvars + 3) & ~3) >> 1;     // two variables per 16 bytes
-    const int4 *s4 = reinterpret_cast<const int4 *>(st);
-    for (int q = tid; q < nq; q += W) {
-        const int4 a = s4[q];
-        bad |= (a.x > a.y) | (a.z > a.w);
-    }
+    bool bad = store_failed(st, v.nvars);
     unsigned long long key = ~0ull;
     if (branch && branching == 2) {
         // features of every unfixed candidate into LDS ...
@@ -1465,36 +1594,8 @@ __device__ void post_scan(const View<DL> &v, const int2 *st, int32_t *ctl,
     lds_barrier();
 }
 
-// ------------------------------------------------------ store copies
-// The store of an instance with V variables occupies Vp = round_up(V, 4)
-// pairs; pairs V..Vp-1 hold (0, 0) so that the failure scan never sees an
-// empty interval there.
-
-// st <- initial box (global, V entries per array), padding zeroed
-__device__ __forceinline__ void load_box(int2 *st, const int32_t *lb0, const int32_t *ub0,
-                                         int nvars)
-{
-    const int tid = threadIdx.x, W = blockDim.x, Vp = (nvars + 3) & ~3;
-    for (int x = tid; x < Vp; x += W)
-        st[x] = x < nvars ? make_int2(gread(lb0 + x), gread(ub0 + x)) : make_int2(0, 0);
-}
-
-// copy Vp pairs (16-byte aligned, two per int4) from src to dst;
-// SG/DG: source/destination in global memory (else LDS)
-template <bool SG, bool DG>
-__device__ __forceinline__ void copy_store(int2 *dst, const int2 *src, int nvars)
-{
-    const int tid = threadIdx.x, W = blockDim.x, nq = ((nvars + 3) & ~3) >> 1;
-    const int4 *s4 = reinterpret_cast<const int4 *>(src);
-    int4 *d4 = reinterpret_cast<int4 *>(dst);
-    for (int q = tid; q < nq; q += W) {
-        const int4 a = SG ? gread(s4 + q) : s4[q];
-        if (DG) gwrite4(d4 + q, a); else d4[q] = a;
-    }
-}
-
 // apply decision word (var | side << 16, val) to the store as a join
-__device__ __forceinline__ void apply_decision(int2 *st, int2 dcs)
+__device__ __forceinline__ void apply_decision(const Store st, int2 dcs)
 {
     const int x = dcs.x & 0xffff;
     if (dcs.x & kSideBit)
@@ -1513,11 +1614,11 @@ __global__ __launch_bounds__(1024) void features_kernel(const DevModel *mp, int 
     extern __shared__ __align__(16) char smem[];
     const DevModel m = *mp;
     const int tid = threadIdx.x, W = blockDim.x;
-    int2 *st = reinterpret_cast<int2 *>(smem);
+    const Store st = make_store(smem, m.nI);
     const View<false> v = view_global(m);
     for (int box = blockIdx.x; box < nbox; box += gridDim.x) {
         const size_t off = (size_t)box * m.nvars;
-        load_box(st, lb_in + off, ub_in + off, m.nvars);
+        load_box(st, lb_in + off, ub_in + off, m.nvars, m.vorig);
         lds_barrier();
         for (int q = tid; q < m.ndec; q += W) {
             float f[kNumFeat];
@@ -1529,10 +1630,10 @@ __global__ __launch_bounds__(1024) void features_kernel(const DevModel *mp, int 
     }
 }
 
-hipError_t launch_features(const DevModel *m_dev, int nvars, int nbox, const int32_t *lb_in,
+hipError_t launch_features(const DevModel *m_dev, size_t store, int nbox, const int32_t *lb_in,
                            const int32_t *ub_in, float *out, hipStream_t stream)
 {
-    const size_t lds = sizeof(int2) * (size_t)((nvars + 3) & ~3);
+    const size_t lds = store;
     const int grid = nbox < 2048 ? nbox : 2048;
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(features_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1553,17 +1654,18 @@ __global__ __launch_bounds__(1024) void propagate_batch_kernel(
 {
     extern __shared__ __align__(16) char smem[];
     const DevModel m = *mp;
-    const int tid = threadIdx.x, W = blockDim.x;
+    const int tid = threadIdx.x;
     int32_t *ctl = reinterpret_cast<int32_t *>(smem);
-    int2 *st = reinterpret_cast<int2 *>(ctl + kCtlWords);
-    char *dsc = reinterpret_cast<char *>(st + ((m.nvars + 3) & ~3));
+    char *sb = reinterpret_cast<char *>(ctl + kCtlWords);
+    const Store st = make_store(sb, m.nI);
+    char *dsc = sb + store_bytes(m.nI, m.nvars);
     View<DL> v;
     if constexpr (DL) v = stage_descriptors(m, dsc); else v = view_global(m);
     const NodeLists L{{nullptr, nullptr, nullptr, nullptr}, {m.ndiff, m.nreif, m.nrows, m.nbrows},
                       m.nterms + m.nbterms, {nullptr, nullptr, nullptr, nullptr}, nullptr};
     for (int box = blockIdx.x; box < nbox; box += gridDim.x) {
         const size_t off = (size_t)box * m.nvars;
-        load_box(st, lb_in + off, ub_in + off, m.nvars);
+        load_box(st, lb_in + off, ub_in + off, m.nvars, m.vorig);
         uint32_t nsw = 0;
         unsigned long long ex[4] = {0, 0, 0, 0};
         lds_barrier();
@@ -1571,11 +1673,7 @@ __global__ __launch_bounds__(1024) void propagate_batch_kernel(
         const int rc = propagate_wg<DL, false>(v, st, ctl, L, nsw, ex, nat);
         post_scan(v, st, ctl, 0, false);
         const int failed = rc | lds_ld(&ctl[C_POSTFAIL]);
-        for (int x = tid; x < m.nvars; x += W) {
-            const int2 d = st[x];
-            gwrite(lb_out + off + x, d.x);
-            gwrite(ub_out + off + x, d.y);
-        }
+        store_box(st, lb_out + off, ub_out + off, m.nvars, m.vorig);
         if (tid == 0) {
             status[box] = failed;
             if (sweeps) sweeps[box] = (int32_t)nsw;
@@ -1587,9 +1685,9 @@ __global__ __launch_bounds__(1024) void propagate_batch_kernel(
 // A tell by one thread outside the sweeps (a decision, the objective
 // bound), with marks and, with dp.trail_on, the trail.
 template <bool LB>
-__device__ __forceinline__ void tell_one(int2 *st, const Dep &dp, int x, int32_t v)
+__device__ __forceinline__ void tell_one(const Store st, const Dep &dp, int x, int32_t v)
 {
-    const int2 d = st[x];
+    const int2 d = dom(st, x);
     if (LB ? v <= d.x : v >= d.y) return;
     tell_m<true, LB>(st, dp, x, v, d);
 }
@@ -1608,10 +1706,10 @@ __global__ __launch_bounds__(1024) void propagate_incr_kernel(const DevModel *mp
     extern __shared__ __align__(16) char smem[];
     const DevModel m = *mp;
     const int tid = threadIdx.x, W = blockDim.x;
-    const int Vp = (m.nvars + 3) & ~3;
     int32_t *ctl = reinterpret_cast<int32_t *>(smem);
-    int2 *st = reinterpret_cast<int2 *>(ctl + kCtlWords);
-    char *p = reinterpret_cast<char *>(st + Vp);
+    char *sb = reinterpret_cast<char *>(ctl + kCtlWords);
+    const Store st = make_store(sb, m.nI);
+    char *p = sb + store_bytes(m.nI, m.nvars);
     const int vw = 1 << A.dep_vshift;
     Dep dp{};
     dp.lm = reinterpret_cast<uint32_t *>(p);
@@ -1647,10 +1745,11 @@ __global__ __launch_bounds__(1024) void propagate_incr_kernel(const DevModel *mp
     for (int w = tid; w < dp.qw; w += W) dp.qm[w] = 0;
     for (int box = blockIdx.x; box < A.nbox; box += gridDim.x) {
         const size_t off = (size_t)box * m.nvars;
-        load_box(st, A.lb_in + off, A.ub_in + off, m.nvars);
+        load_box(st, A.lb_in + off, A.ub_in + off, m.nvars, m.vorig);
         for (int w = tid; w < 3 * vw; w += W) dp.lm[w] = 0;
-        const int x = gread(A.dvar + box);
-        const bool valid = x >= 0 && x < m.nvars;
+        const int xo = gread(A.dvar + box);
+        const bool valid = xo >= 0 && xo < m.nvars;
+        const int x = valid ? gread(m.vnew + xo) : 0;
         lds_barrier();
         if (tid == 0 && valid) {
             // the decision: joins with marks, so the first sweep runs the
@@ -1665,11 +1764,7 @@ __global__ __launch_bounds__(1024) void propagate_incr_kernel(const DevModel *mp
         if (valid) rc = propagate_dep<false, true, true>(v, st, ctl, dp, false, nsw, ex, nat);
         post_scan(v, st, ctl, 0, false);
         const int failed = rc | lds_ld(&ctl[C_POSTFAIL]);
-        for (int y = tid; y < m.nvars; y += W) {
-            const int2 d = st[y];
-            gwrite(A.lb_out + off + y, d.x);
-            gwrite(A.ub_out + off + y, d.y);
-        }
+        store_box(st, A.lb_out + off, A.ub_out + off, m.nvars, m.vorig);
         if (tid == 0) {
             A.status[box] = valid ? failed : -1;
             if (A.sweeps) A.sweeps[box] = (int32_t)nsw;
@@ -1682,7 +1777,7 @@ __global__ __launch_bounds__(1024) void propagate_incr_kernel(const DevModel *mp
 // Bounded lock-free MPMC queue of subtree records (D. Vyukov's bounded
 // queue: one sequence number per slot).  Only lane 0 of a workgroup calls
 // these.
-__device__ long long q_claim_pop(const SearchParams &P)
+__device__ __forceinline__ long long q_claim_pop(const SearchParams &P)
 {
     SearchGlobals *g = P.g;
     unsigned long long pos = g_load(&g->q_head);
@@ -1700,12 +1795,12 @@ __device__ long long q_claim_pop(const SearchParams &P)
     }
 }
 
-__device__ void q_release_slot(const SearchParams &P, unsigned long long pos)
+__device__ __forceinline__ void q_release_slot(const SearchParams &P, unsigned long long pos)
 {
     g_store_rel(&P.q_seq[pos % (unsigned)P.qcap], pos + (unsigned long long)P.qcap);
 }
 
-__device__ long long q_claim_push(const SearchParams &P)
+__device__ __forceinline__ long long q_claim_push(const SearchParams &P)
 {
     SearchGlobals *g = P.g;
     unsigned long long pos = g_load(&g->q_tail);
@@ -1723,7 +1818,7 @@ __device__ long long q_claim_push(const SearchParams &P)
     }
 }
 
-__device__ void q_publish(const SearchParams &P, unsigned long long pos)
+__device__ __forceinline__ void q_publish(const SearchParams &P, unsigned long long pos)
 {
     g_store_rel(&P.q_seq[pos % (unsigned)P.qcap], pos + 1);
 }
@@ -1735,11 +1830,11 @@ __device__ inline RecHdr *q_slot(const SearchParams &P, unsigned long long pos)
 
 // FNV-1a 64 over the little-endian bytes, finalised by MurmurHash3 fmix64.
 template <bool DL>
-__device__ unsigned long long solution_hash(const int2 *st, const View<DL> &v, int n)
+__device__ __forceinline__ unsigned long long solution_hash(const Store st, const View<DL> &v, int n)
 {
     unsigned long long h = 0xcbf29ce484222325ull;
     for (int i = 0; i < n; ++i) {
-        const uint32_t val = (uint32_t)st[v.dec(i)].x;
+        const uint32_t val = (uint32_t)dom(st, v.dec(i)).x;
         for (int k = 0; k < 4; ++k) {
             h ^= (val >> (8 * k)) & 0xffu;
             h *= 0x100000001b3ull;
@@ -1795,7 +1890,7 @@ struct Lane0 {
 static_assert(sizeof(Lane0) <= 4 * (kCtlWords - 32), "Lane0 must fit in the control block");
 
 // lane 0: publish this workgroup's counters for instance `is`
-__device__ void flush_counters(Lane0 &z, InstState *is, int mode)
+__device__ __forceinline__ void flush_counters(Lane0 &z, InstState *is, int mode)
 {
     g_add(&is->nodes, z.nodes);
     g_add(&is->fails, z.fails);
@@ -1827,19 +1922,20 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? 6 : 7) : 1) void s
     constexpr bool LIVE = PM == 1, DEP = PM == 2;
     extern __shared__ __align__(16) char smem[];
     const int tid = threadIdx.x, W = blockDim.x;
-    const int Vp = (P.max_vars + 3) & ~3;
+    const size_t SB = (size_t)P.max_store;    // bytes of the largest store of the launch
     int32_t *ctl = reinterpret_cast<int32_t *>(smem);
     Lane0 &z = *reinterpret_cast<Lane0 *>(ctl + 32);
-    int2 *st = reinterpret_cast<int2 *>(ctl + kCtlWords);
-    int2 *rst;
+    char *stb = reinterpret_cast<char *>(ctl + kCtlWords);   // the current store
+    char *rstb;                                                // the subtree root's store
     char *p;
     if (RL) {
-        rst = st + Vp;
-        p = reinterpret_cast<char *>(rst + Vp);
+        rstb = stb + SB;
+        p = rstb + SB;
     } else {
-        rst = reinterpret_cast<int2 *>(P.root_scratch) + (size_t)blockIdx.x * Vp;
-        p = reinterpret_cast<char *>(st + Vp);
+        rstb = P.root_scratch + (size_t)blockIdx.x * SB;
+        p = stb + SB;
     }
+    Store st = make_store(stb, 0);          // laid out for each instance taken
     const Stack stk{reinterpret_cast<int4 *>(p),
                     P.gstack + (size_t)blockIdx.x * (size_t)P.max_depth, ctl + C_MAXW};
     p += align16(sizeof(int4) * (size_t)kRing);
@@ -1959,6 +2055,7 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? 6 : 7) : 1) void s
         if (inst != cur_inst) {
             if (tid == 0) z.local_best = INT32_MAX;
             if constexpr (DL) v = stage_descriptors(m, dsc); else v = view_global(m);
+            st = make_store(stb, m.nI);
             cur_inst = inst;
         }
         const int nvars = m.nvars, ndec = m.ndec, objective = m.objective;
@@ -2120,10 +2217,10 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? 6 : 7) : 1) void s
                         const unsigned long long idx = g_add(&is->solutions, 1ull);
                         if (P.sol_buf && (long long)idx < P.sol_cap)
                             for (int q = 0; q < ndec; ++q)
-                                P.sol_buf[(size_t)idx * ndec + q] = st[v.dec(q)].x;
+                                P.sol_buf[(size_t)idx * ndec + q] = dom(st, v.dec(q)).x;
                         g_add(&is->sol_hash, solution_hash(st, v, ndec));
                     } else {
-                        const int32_t obj = st[objective].x;
+                        const int32_t obj = dom(st, objective).x;
                         if (obj < z.local_best) z.local_best = obj;
                         const int32_t old = __hip_atomic_fetch_min(
                             &is->best, obj, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
@@ -2132,7 +2229,7 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? 6 : 7) : 1) void s
                             while (!g_cas(&is->best_lock, zz, 1)) { zz = 0; __builtin_amdgcn_s_sleep(1); }
                             if (obj < is->pad[0]) {
                                 for (int q = 0; q < ndec; ++q)
-                                    P.best_vals[(size_t)inst * P.max_ndec + q] = st[v.dec(q)].x;
+                                    P.best_vals[(size_t)inst * P.max_ndec + q] = dom(st, v.dec(q)).x;
                                 is->pad[0] = obj;
                                 is->best_owner = blockIdx.x;
                             }
@@ -2154,7 +2251,7 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? 6 : 7) : 1) void s
                 }
                 if (first) {
                     // the subtree root's fixed point, kept for recomputation
-                    copy_store<false, !RL>(rst, st, nvars);
+                    copy_store<false, !RL>(rstb, stb, m.nI, nvars);
                     first = false;
                     if (!RL) full_barrier(); else lds_barrier();
                 }
@@ -2165,7 +2262,7 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? 6 : 7) : 1) void s
                 if (tid == 0) {
                     const int q = (int)(uint32_t)(key & 0xffffffffull);
                     const int x = v.dec(q);
-                    const int val = st[x].x;
+                    const int val = dom(st, x).x;
                     // level depth; with DEP its entry also keeps where the
                     // child's trail segment starts
                     stk.put(depth, make_int4(x, val, DEP ? ctl[C_TTOP] : 0, 0));
@@ -2175,7 +2272,7 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? 6 : 7) : 1) void s
                         d1.trail_on = true;
                         tell_one<false>(st, d1, x, val);
                     } else {
-                        st[x].y = val;  // left child: x = lb(x)
+                        tell_ub(st, x, val);  // left child: x = lb(x)
                     }
                     // donate the open right branch closest to the subtree
                     // root when other workgroups are waiting for work
@@ -2247,7 +2344,7 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? 6 : 7) : 1) void s
                         if (k < depth) e0 = uni(stk.get(k - 1).z);
                         for (int i = e0 + tid; i < e1; i += W) {
                             const int4 t = gread(dp.trail + i);
-                            st[t.x] = make_int2(t.y, t.z);
+                            set_dom(st, t.x, make_int2(t.y, t.z));
                         }
                         lds_barrier();
                     }
@@ -2271,7 +2368,7 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? 6 : 7) : 1) void s
             }
             depth = nd;
             // recompute: subtree root fixed point + decisions below it
-            copy_store<!RL, false>(st, rst, nvars);
+            copy_store<!RL, false>(stb, rstb, m.nI, nvars);
             if (LIVE) {
                 in_sel = 1;
                 out_sel = 2;
@@ -2559,12 +2656,11 @@ hipError_t launch_mlp_scores(const float *params, const uint16_t *wbf, int use_b
 }
 
 // ------------------------------------------------------------ launchers
-size_t search_lds_bytes(int max_vars, int max_depth, size_t max_desc, bool desc_lds, bool root_lds,
+size_t search_lds_bytes(size_t max_store, int max_depth, size_t max_desc, bool desc_lds, bool root_lds,
                         int feat_ndec, int list_items, size_t dep_bytes)
 {
-    const size_t Vp = (size_t)((max_vars + 3) & ~3);
-    size_t b = sizeof(int32_t) * kCtlWords + Vp * sizeof(int2);
-    if (root_lds) b += Vp * sizeof(int2);
+    size_t b = sizeof(int32_t) * kCtlWords + max_store;
+    if (root_lds) b += max_store;
     b += align16(sizeof(int4) * (size_t)kRing);
     if (feat_ndec > 0) b += align16(32 * (size_t)feat_ndec);
     if (list_items > 0) b += 3 * align16(sizeof(uint16_t) * (size_t)list_items);
@@ -2580,10 +2676,9 @@ size_t dep_lds_bytes(int vshift, int qw, const int wcap[kDepKinds], int jcap)
            align16(4 * (size_t)jcap);
 }
 
-size_t propagate_lds_bytes(int nvars, size_t desc, bool desc_lds)
+size_t propagate_lds_bytes(size_t store, size_t desc, bool desc_lds)
 {
-    const size_t Vp = (size_t)((nvars + 3) & ~3);
-    size_t b = sizeof(int32_t) * kCtlWords + Vp * sizeof(int2);
+    size_t b = sizeof(int32_t) * kCtlWords + store;
     if (desc_lds) b += desc;
     return align16(b);
 }

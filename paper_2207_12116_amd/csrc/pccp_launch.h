@@ -18,14 +18,15 @@ size_t model_desc_bytes(int ndiff, int nreif, int nrows, int nterms, int ndec, i
 // list_items: sum over kinds of the largest table in the launch when the
 // search keeps item lists (three LDS buffers of 16-bit indices), else 0;
 // the decision stack takes a fixed LDS ring whatever max_depth is
-size_t search_lds_bytes(int max_vars, int max_depth, size_t max_desc, bool desc_lds, bool root_lds,
+// max_store: bytes of the largest store of the launch (store_bytes)
+size_t search_lds_bytes(size_t max_store, int max_depth, size_t max_desc, bool desc_lds, bool root_lds,
                         int feat_ndec, int list_items, size_t dep_bytes);
 // LDS of dependency-driven propagation: three variable bitmaps of
 // 1 << vshift words, qw words of propagator marks, work lists of wcap[k]
 // 16-bit entries (k < kDepKinds) and (two-phase expansion) a job list of
 // jcap words
 size_t dep_lds_bytes(int vshift, int qw, const int wcap[kDepKinds], int jcap);
-size_t propagate_lds_bytes(int nvars, size_t desc, bool desc_lds);
+size_t propagate_lds_bytes(size_t store, size_t desc, bool desc_lds);
 
 hipError_t launch_propagate_batch(const DevModel *m_dev, int nbox, const int32_t *lb_in,
                                   const int32_t *ub_in, int32_t *lb_out, int32_t *ub_out,
@@ -52,7 +53,7 @@ hipError_t launch_search(const SearchParams &P, int grid, int block, size_t lds,
 hipError_t build_search_graph(const SearchParams &P, int grid, int block, size_t lds,
                               const SearchShape &k, hipGraphExec_t *exec);
 
-hipError_t launch_features(const DevModel *m_dev, int nvars, int nbox, const int32_t *lb_in,
+hipError_t launch_features(const DevModel *m_dev, size_t store, int nbox, const int32_t *lb_in,
                            const int32_t *ub_in, float *out, hipStream_t stream);
 
 constexpr int kMlpMaxCand = 256;

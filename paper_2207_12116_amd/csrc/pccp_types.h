@@ -37,8 +37,24 @@ constexpr int kCtlWords = 96;   // LDS control block (int32 words)
 //   cmd = {x | side << 16, k, div, first entry}; cnt = guards | terms << 16;
 //   entries: the guards {y | side << 16, c}, then the terms
 //   {y | (reads ub) << 16, a}.
+// The store of one instance (see Store in the kernels): the variables whose
+// initial domain is not inside [0, 1] first, as (lb, ub) int32 pairs
+// (indices [0, nI)), then the Booleans, one byte each (indices [nI, nvars)).
+// The compiled model numbers its variables in that order; vorig / vnew map
+// between that numbering and the model's own.
+__host__ __device__ inline int store_pairs(int nI) { return (nI + 1) & ~1; }
+__host__ __device__ inline int store_bool_words(int nI, int nvars)
+{
+    return (((nvars - nI) + 3) / 4 + 3) & ~3;
+}
+__host__ __device__ inline size_t store_bytes(int nI, int nvars)
+{
+    return 8 * (size_t)store_pairs(nI) + 4 * (size_t)store_bool_words(nI, nvars);
+}
+
 struct DevModel {
     int32_t nvars;
+    int32_t nI;                   // variables stored as int32 pairs (the others are Booleans)
     int32_t ndiff, nreif, nrows, nterms;
     int32_t ndec, objective;
     int32_t row_group;            // lanes per linear row in a sweep (4, 8 or 16)
@@ -55,6 +71,8 @@ struct DevModel {
     const int2 *brows;            // kind 4 rows {rhs, len}
     const uint32_t *bterms;       // kind 4 terms [nbrows * bgroup * bchunks]
     const int32_t *dec;           // decision variables (tie-break order)
+    const int32_t *vorig;         // store index -> the model's variable index
+    const int32_t *vnew;          // the model's variable index -> store index
     const int4 *cmds;             // kind 5 commands
     const uint32_t *ccnt;         // kind 5 guard and term counts
     const int2 *cent;             // kind 5 guards and terms
@@ -148,8 +166,10 @@ struct SearchParams {
     char *q_data;               // [qcap * slot_bytes]
     int32_t qcap;
     int32_t slot_bytes;
-    int32_t *root_scratch;      // [grid * 2 * Vp] (global subproblem roots, (lb, ub) pairs)
-    int32_t max_vars;           // largest instance in the launch
+    char *root_scratch;         // [grid * max_store] (global subproblem root stores)
+    int32_t max_vars;           // largest instance in the launch (variables)
+    int32_t pad1;
+    long long max_store;        // bytes of the largest store (store_bytes) in the launch
     int32_t donate;             // allow donation (0 in single-workgroup runs)
     long long node_limit;       // 0 = none
     long long inst_node_limit;  // 0 = none: nodes per instance before it is abandoned
