@@ -118,6 +118,8 @@ def _load(path):
     L.orc_solve_timed.argtypes = [C.POINTER(MP), C.c_int32, C.c_int32, C.c_int32, C.c_int64,
                                   C.c_int32, C.POINTER(C.c_int64), PD, _P32, _P32, PD]
     L.orc_solve_timed.restype = C.c_int32
+    L.orc_adam_step.argtypes = [PD, PD, PD, PD, C.c_int32, C.c_double, C.c_int32]
+    L.orc_adam_step.restype = C.c_int32
     FP = C.POINTER(_FModel)
     L.orc_fvalidate.argtypes = [FP]
     L.orc_fvalidate.restype = C.c_int32
@@ -353,6 +355,18 @@ def mlp_loss_grad(params, x, node_off, target):
     lib().orc_mlp_loss_grad(_pd(p), _pd(x), _ptr(off), _pd(t), int(off.shape[0] - 1),
                             C.byref(loss), _pd(g))
     return float(loss.value), g
+
+
+def adam_step(p, g, m, v, lr, step):
+    """One Adam step; returns new (p, m, v) as float64 arrays."""
+    p = np.array(p, dtype=np.float64, copy=True)
+    m = np.array(m, dtype=np.float64, copy=True)
+    v = np.array(v, dtype=np.float64, copy=True)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    rc = lib().orc_adam_step(_pd(p), _pd(g), _pd(m), _pd(v), int(p.shape[0]), float(lr), int(step))
+    if rc < 0:
+        raise ValueError(f"orc_adam_step error {rc}")
+    return p, m, v
 
 
 def trace(model, node_limit, mode=None, cap_nodes=100000, cap_cand=4000000):

@@ -446,3 +446,22 @@ int64_t orc_trace(const orc_model *m, int32_t mode, int64_t node_limit, float *f
     if (ncand) *ncand = T.ncand_tot;
     return T.nrec;
 }
+
+/* One step of Adam (Kingma and Ba 2015), the optimiser of the training
+ * loop, in double precision: with beta1 = 0.9, beta2 = 0.999, eps = 1e-8,
+ *   m <- beta1 m + (1 - beta1) g,   v <- beta2 v + (1 - beta2) g^2,
+ *   p <- p - lr * (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps)
+ * for step t >= 1 (m and v start at 0). */
+int32_t orc_adam_step(double *p, const double *g, double *m, double *v, int32_t n, double lr,
+                      int32_t step)
+{
+    if (!p || !g || !m || !v || n < 0 || step < 1) return -1;
+    const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+    const double c1 = 1.0 - pow(b1, (double)step), c2 = 1.0 - pow(b2, (double)step);
+    for (int32_t i = 0; i < n; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        p[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
+    return 0;
+}

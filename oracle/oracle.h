@@ -192,6 +192,10 @@ int32_t orc_mlp_loss_grad(const double *p, const double *x, const int32_t *node_
  * the earliest), or -1 if every decision variable is fixed. */
 int32_t orc_mlp_choice(const orc_model *m, const double *p, const int32_t *lb, const int32_t *ub);
 
+/* One Adam step in place (beta1 0.9, beta2 0.999, eps 1e-8; step >= 1). */
+int32_t orc_adam_step(double *p, const double *g, double *m, double *v, int32_t n, double lr,
+                      int32_t step);
+
 /* Search traces with expert labels (see learn.c). */
 int64_t orc_trace(const orc_model *m, int32_t mode, int64_t node_limit, float *feat,
                   double *score, int32_t *cand, int32_t *off, int32_t *label, int64_t cap_nodes,

@@ -109,6 +109,46 @@ def test_gradient_matches_oracle(P, small_traces):
     assert np.array_equal(mlp.params(), p.astype(np.float32))
 
 
+def test_adam_steps_match_oracle(P, small_traces):
+    """Two training steps (forward, cross-entropy, backward, Adam) from the
+    same parameters: the GPU's parameters after each step equal the FP64
+    reference - the oracle's gradient at the current parameters fed to the
+    oracle's Adam step with the same moments - up to FP32 rounding of the
+    update (the gradient itself agrees to 1e-4 of its norm)."""
+    import torch
+    tr = small_traces
+    mlp = P.MLP(seed=5)
+    p = mlp.params().astype(np.float64)
+    feat = torch.tensor(tr["feat"], device="cuda")
+    off = torch.tensor(tr["off"], device="cuda")
+    t = torch.tensor(tr["target"].astype(np.float32), device="cuda")
+    maxc = int(np.max(np.diff(tr["off"])))
+    x64 = tr["feat"].astype(np.float64)
+    t64 = tr["target"].astype(np.float32).astype(np.float64)
+    m = np.zeros(O.NPARAM)
+    v = np.zeros(O.NPARAM)
+    lr = 1e-2
+    for step in (1, 2):
+        _, g = O.mlp_loss_grad(p, x64, tr["off"], t64)
+        want, m, v = O.adam_step(p, g, m, v, lr, step)
+        mlp.train_step(feat, off, t, maxc, lr)
+        got = mlp.params().astype(np.float64)
+        du_got, du_want = got - p, want - p
+        # where the gradient is far above the FP32 gradient's error (1e-4 of
+        # its norm), the update is well conditioned: the FP32 update is
+        # within 2 % of lr and the parameters' rounding (1e-6 of their
+        # size) of the reference; where it is not (e.g. the output bias,
+        # whose exact gradient is zero), Adam moves a parameter by about lr
+        # at most, whatever the sign of the noise
+        ok = np.abs(g) > 1e-2 * np.abs(g).max()
+        say("adam step", step, "well-conditioned", int(ok.sum()), "max update",
+            np.abs(du_want).max(), "max diff", np.abs(du_got - du_want)[ok].max())
+        assert ok.sum() > 100
+        assert np.all(np.abs(du_got - du_want)[ok] <= 0.02 * lr + 1e-6 * np.abs(p[ok]))
+        assert np.all(np.abs(du_got) <= 1.5 * lr + 1e-6 * np.abs(p))
+        p = got
+
+
 def test_training_lowers_loss_and_beats_chance(P, small_traces):
     from paper_2207_12116_amd import learn
     mlp, info = learn.train(small_traces, steps=300, lr=1e-2, seed=1, val_frac=0.0)

@@ -108,3 +108,29 @@ def test_trace_labels_are_the_strong_branching_argmax():
     assert np.allclose(tr["feat"][:len(cands)], f[cands], atol=1e-6)
     for i in range(len(tr["label"])):
         assert 0 <= tr["label"][i] < tr["off"][i + 1] - tr["off"][i]
+
+
+def test_adam_closed_forms():
+    """Adam (the optimiser of the training kernels) from m = v = 0: the bias
+    corrections make the first step move every parameter by exactly
+    lr * g / (|g| + eps), and so does every step of a constant gradient;
+    a zero gradient leaves the parameter; a restatement without the bias
+    corrections (a planted mistake) moves the first step by about
+    lr * 0.1 / sqrt(0.001) = 3.16 lr instead."""
+    rng = np.random.default_rng(7)
+    n, lr, eps = 200, 3e-3, 1e-8
+    p0 = rng.normal(size=n)
+    g = rng.normal(size=n) * np.exp(rng.uniform(-8, 2, size=n))
+    g[:5] = 0.0
+    p1, m, v = O.adam_step(p0, g, np.zeros(n), np.zeros(n), lr, 1)
+    want = p0 - lr * g / (np.abs(g) + eps)
+    assert np.allclose(p1, want, rtol=0, atol=1e-15)
+    assert np.array_equal(p1[:5], p0[:5])
+    p, mm, vv = p1, m, v
+    for t in range(2, 6):
+        q, mm, vv = O.adam_step(p, g, mm, vv, lr, t)
+        assert np.allclose(p - q, lr * g / (np.abs(g) + eps), rtol=1e-12, atol=1e-16)
+        p = q
+    # the planted mistake: no bias correction
+    planted = p0 - lr * (0.1 * g) / (np.sqrt(0.001 * g * g) + eps)
+    assert not np.allclose(planted[5:], p1[5:], rtol=0, atol=1e-4)
