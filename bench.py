@@ -55,14 +55,21 @@ BYTES_DIFF, BYTES_REIF, BYTES_TERM = 16, 24, 8
 
 # HBM traffic of the search kernel from rocprofv3 counter runs (FETCH_SIZE and
 # WRITE_SIZE in separate passes), per search node, for one kernel source and
-# launch shape on the headline workload.  FETCH_SIZE is scaled by 2.0 and
+# launch shape on one workload (the headline batch, or the 120-task instance).  FETCH_SIZE is scaled by 2.0 and
 # WRITE_SIZE by 1.0: what a 2 GiB device copy (`--copy-calibration`) reads
 # back as 1 GiB fetched and 2 GiB written.  A run whose kernel source or
 # shape differs reports null.
 PROFILED_TRAFFIC = [
-    # {"kernel_sha256": ..., "block": ..., "desc_lds": ..., "root_lds": ..., "live": ...,
-    #  "occupancy": ..., "dep": ..., "fetch_bytes_per_node": ..., "write_bytes_per_node": ...,
-    #  "profile": "profiles/..."}
+    {"workload": "rcpsp_mixed_30_60_90tasks_4res_batch256",
+     "kernel_sha256": "6b246f4230f84a5fcbdd0dd9dc5750424b1cb5e15530a13c13425308db25fe0b",
+     "block": 128, "desc_lds": 0, "root_lds": 0, "live": 0, "occupancy": 2, "dep": 1,
+     "fetch_bytes_per_node": 1165.0, "write_bytes_per_node": 295.6,
+     "profile": "profiles/search_kernel_rcpsp_mixed256_wg128.md"},
+    {"workload": "rcpsp_120tasks_4res_single",
+     "kernel_sha256": "6b246f4230f84a5fcbdd0dd9dc5750424b1cb5e15530a13c13425308db25fe0b",
+     "block": 256, "desc_lds": 0, "root_lds": 0, "live": 0, "occupancy": 1, "dep": 1,
+     "fetch_bytes_per_node": 52.3, "write_bytes_per_node": 1728.0,
+     "profile": "profiles/search_kernel_rcpsp120_single.md"},
 ]
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
@@ -77,11 +84,11 @@ def kernel_sha256():
     return h.hexdigest()
 
 
-def profiled_traffic(st, nodes_per_launch):
+def profiled_traffic(st, nodes_per_launch, workload):
     sha = kernel_sha256()
     for e in PROFILED_TRAFFIC:
-        if (e["kernel_sha256"], e["block"], e["desc_lds"], e["root_lds"], e["live"],
-                e["occupancy"], e["dep"]) == (sha, st["block"], st["desc_lds"], st["root_lds"],
+        if (e["workload"], e["kernel_sha256"], e["block"], e["desc_lds"], e["root_lds"], e["live"],
+                e["occupancy"], e["dep"]) == (workload, sha, st["block"], st["desc_lds"], st["root_lds"],
                                               st["live"], st["occupancy"], st["dep"]):
             return round((e["fetch_bytes_per_node"] + e["write_bytes_per_node"]) * nodes_per_launch)
     return None
@@ -136,7 +143,7 @@ def host_info():
 
 # nodes per instance of the CPU sample, by task count: about one second of
 # the oracle's sequential search each on a current server core
-CPU_NODES = {30: 8000, 60: 2000, 90: 1000}
+CPU_NODES = {30: 8000, 60: 2000, 90: 1000, 120: 500}
 
 
 def cpu_baseline(models_by_size, threads, label, scale=1.0):
@@ -196,6 +203,27 @@ def plain_leg(models, limit, cfg, peaks):
     return {"nodes_per_s": round(nodes / wall, 1), "propagations_per_s": round(props / wall, 1),
             "roofline": roofline(byt, atom, kern, peaks), "grid": st["grid"], "block": st["block"],
             "per_instance": rows}
+
+
+def enumerate_leg(seeds, limit):
+    """The tiny CSP (8 variables over [0, 20], 12 precedences, one weighted
+    sum; every solution enumerated), each seed alone on the whole GPU with
+    the library's default launch: nodes/s and time to exhaust the tree."""
+    from paper_2207_12116_amd import instances as I, pccp
+    rows, nodes, wall = [], 0, 0.0
+    for sd in seeds:
+        s = pccp.Solver(I.tiny_csp(sd))
+        t0 = time.perf_counter()
+        out = s.solve(pccp.ENUMERATE, time_limit=limit)
+        dt = time.perf_counter() - t0
+        st = s.stats()
+        nodes += st["nodes"]
+        wall += dt
+        rows.append({"seed": sd, "outcome": pccp.OUTCOME_NAMES[out], "nodes": st["nodes"],
+                     "solutions": st["solutions"], "sol_hash": st["sol_hash"],
+                     "ttpo_ms": round(st["ttpo_ms"], 3) if out == pccp.OUT_ALL else None})
+    return {"nodes_per_s": round(nodes / wall, 1), "per_instance": rows,
+            "grid": st["grid"], "block": st["block"]}
 
 
 def jobshop_leg(models, limit, cfg):
@@ -326,6 +354,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=("mixed", "single120"), default="mixed",
+                    help="mixed: the 256-instance 30/60/90-task batch (the headline); single120: "
+                         "one 120-task instance (seed 0) on the whole GPU per step, for profiles")
     ap.add_argument("--batch", type=int, default=256, help="instances (seeds 0..batch-1)")
     ap.add_argument("--step-time", type=float, default=3.0)
     ap.add_argument("--wg", type=int, default=0)
@@ -352,7 +383,7 @@ def main():
     ap.add_argument("--no-ttpo", action="store_true")
     ap.add_argument("--ttpo-n", type=int, default=30)
     ap.add_argument("--ttpo-seeds", type=int, default=16)
-    ap.add_argument("--ttpo-limit", type=float, default=2.0,
+    ap.add_argument("--ttpo-limit", type=float, default=1.0,
                     help="device seconds per instance in the TTPO comparison (the paper's "
                          "protocol for 30-task instances is 30)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -377,14 +408,21 @@ def main():
 
     peaks = pccp.lds_peaks()
     log(f"measured LDS peaks: {peaks}")
-    seeds = list(range(args.batch))
-    log(f"building {args.batch} instances of 30/60/90 tasks")
-    models = [I.rcpsp(I.batch_sizes(s), s) for s in seeds]
+    if args.workload == "single120":
+        seeds = [0]
+        log("building the 120-task instance, seed 0")
+        models = [I.rcpsp(120, 0)]
+    else:
+        seeds = list(range(args.batch))
+        log(f"building {args.batch} instances of 30/60/90 tasks")
+        models = [I.rcpsp(I.batch_sizes(s), s) for s in seeds]
     tuned = None
     if args.wg == 0 and not args.no_autotune:
         # tuned on every 16th instance (the three sizes in proportion)
         cfg, rep = autotune.tune(models[::16], pccp.MINIMIZE, budget_s=0.3, cache_path=None,
-                                 wg_sizes=(256, 512, 1024), max_depth=args.max_depth, log=log)
+                                 wg_sizes=(128, 256, 512), max_depth=args.max_depth, log=log)
+        if args.workload == "single120":
+            log("the 120-task instance is tuned alone")
         tuned = {"wg_size": cfg.wg_size, "desc_lds": cfg.desc_lds, "root_lds": cfg.root_lds,
                  "prop": rep["prop"], "occupancy": cfg.occupancy,
                  "candidates": len(rep["candidates"])}
@@ -427,7 +465,8 @@ def main():
     proven = [s["ttpo_ms"] for o, s in zip(outs, sts) if o in solved]
     by_size = {}
     for sd, o, s in zip(seeds, outs, sts):
-        b = by_size.setdefault(str(I.batch_sizes(sd)), {"instances": 0, "proven": 0, "nodes": 0})
+        size = 120 if args.workload == "single120" else I.batch_sizes(sd)
+        b = by_size.setdefault(str(size), {"instances": 0, "proven": 0, "nodes": 0})
         b["instances"] += 1
         b["proven"] += o in solved
         b["nodes"] += s["nodes"]
@@ -439,8 +478,10 @@ def main():
             "by_size": by_size,
             "with_incumbent": sum(s["best"] is not None for s in sts)}
     kernel_s = tot_kernel_ms / 1e3
+    workload = (f"rcpsp_mixed_30_60_90tasks_4res_batch{args.batch}" if args.workload == "mixed"
+                else "rcpsp_120tasks_4res_single")
     roof = roofline(tot_bytes, tot_atom, kernel_s, peaks)
-    roof.update({"traffic": profiled_traffic(sts[0], tot_nodes / args.steps),
+    roof.update({"traffic": profiled_traffic(sts[0], tot_nodes / args.steps, workload),
                  "kernel": "search_kernel", "kernel_ms_avg": round(tot_kernel_ms / args.steps, 3),
                  "bytes_per_launch": tot_bytes // args.steps,
                  "atomics_per_launch": tot_atom // args.steps,
@@ -459,10 +500,13 @@ def main():
         legs["c2_plain_30tasks"]["config"] = {"wg_size": c2cfg.wg_size, "prop": c2rep["prop"],
                                               "seeds": "0-3", "limit_s": 1.5}
         log(f"c2: {legs['c2_plain_30tasks']}")
+        log("tiny CSP, every solution, whole GPU")
+        legs["c1_enumerate"] = enumerate_leg([0, 1, 2, 3], 30.0)
+        log(f"c1: {legs['c1_enumerate']}")
         log("120-task instance, whole GPU")
         c3m = [I.rcpsp(120, 0)]
         c3cfg, c3rep = autotune.tune(c3m, pccp.MINIMIZE, budget_s=0.3, cache_path=None,
-                                     wg_sizes=(256, 512, 1024), max_depth=args.max_depth, log=log)
+                                     wg_sizes=(128, 256, 512), max_depth=args.max_depth, log=log)
         legs["c3_120tasks"] = plain_leg(c3m, 2.0, c3cfg, peaks)
         legs["c3_120tasks"]["config"] = {"wg_size": c3cfg.wg_size, "prop": c3rep["prop"],
                                          "seed": 0, "limit_s": 2.0}
@@ -487,23 +531,31 @@ def main():
     forms = None
     if not args.no_ttpo:
         from paper_2207_12116_amd import learn
-        log(f"time to proven optimum: {args.ttpo_seeds} instances of {args.ttpo_n} tasks")
-        tm = [I.rcpsp(args.ttpo_n, s) for s in range(args.ttpo_seeds)]
-        tcfg, _ = autotune.tune(tm, pccp.MINIMIZE, budget_s=0.2, cache_path=None,
-                                wg_sizes=(128, 256), log=log, steady=False,
-                                max_depth=args.max_depth)
-        forms = ttpo_forms(tm, args.ttpo_limit, tcfg, learn.DEFAULT_WEIGHTS,
-                           f"{args.ttpo_n} tasks, seeds 0-{args.ttpo_seeds - 1}")
-        forms["config"] = {"wg_size": tcfg.wg_size, "desc_lds": tcfg.desc_lds,
+        forms = {}
+        # the 30-task configuration itself, and a set of smaller held-out
+        # instances where proofs take milliseconds to seconds (training used
+        # 30- and 60-task seeds, the recipe choice 12-16 tasks seeds 0-5)
+        for key, n, first, limit in (("c2_30tasks", args.ttpo_n, 0, args.ttpo_limit),
+                                     ("held_out_16tasks", 16, 200, 2.0)):
+            log(f"time to proven optimum: {args.ttpo_seeds} instances of {n} tasks from seed {first}")
+            tm = [I.rcpsp(n, s) for s in range(first, first + args.ttpo_seeds)]
+            tcfg, _ = autotune.tune(tm, pccp.MINIMIZE, budget_s=0.2, cache_path=None,
+                                    wg_sizes=(128, 256), log=log, steady=False,
+                                    max_depth=args.max_depth)
+            f = ttpo_forms(tm, limit, tcfg, learn.DEFAULT_WEIGHTS,
+                           f"{n} tasks, seeds {first}-{first + args.ttpo_seeds - 1}")
+            f["config"] = {"wg_size": tcfg.wg_size, "desc_lds": tcfg.desc_lds,
                            "root_lds": tcfg.root_lds, "occupancy": tcfg.occupancy, "dep": tcfg.dep}
-        log(f"ttpo forms: {json.dumps(forms)}")
+            forms[key] = f
+            log(f"ttpo forms {key}: {json.dumps(f)}")
 
     cpu = None
     if not args.no_cpu:
         threads = args.cpu_threads or host_cores()
         by_size = {}
         for sd, m in zip(seeds, models):
-            lst = by_size.setdefault(I.batch_sizes(sd), [])
+            size = 120 if args.workload == "single120" else I.batch_sizes(sd)
+            lst = by_size.setdefault(size, [])
             if len(lst) < threads:
                 lst.append(m)
         log(f"cpu baseline (oracle, {threads} threads)")
@@ -516,10 +568,12 @@ def main():
         "ms_per_step": round(wall / args.steps * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32", "data": "synthetic",
-        "config": {"workload": f"rcpsp_mixed_30_60_90tasks_4res_batch{args.batch}",
-                   "tasks": "30/60/90 by seed mod 3", "resources": 4, "capacity": 10,
-                   "instances": args.batch, "seeds": f"0-{args.batch - 1}",
-                   "form": "batched", "branching": "first-fail",
+        "config": {"workload": workload,
+                   "tasks": "30/60/90 by seed mod 3" if args.workload == "mixed" else 120,
+                   "resources": 4, "capacity": 10,
+                   "instances": len(models), "seeds": f"{seeds[0]}-{seeds[-1]}",
+                   "form": "batched" if args.workload == "mixed" else "plain",
+                   "branching": "first-fail",
                    "step_time_limit_s": args.step_time,
                    "grid": sts[0]["grid"], "block": sts[0]["block"],
                    "desc_lds": sts[0]["desc_lds"], "root_lds": sts[0]["root_lds"],

@@ -1916,8 +1916,14 @@ __device__ __forceinline__ void flush_counters(Lane0 &z, InstState *is, int mode
 // state spills more at 72 and measured fastest at 6): more resident
 // subproblems per CU to hide the latency of the dependent loads, with
 // leaner unrolling.
+#ifndef PCCP_HI_DEP_WAVES
+#define PCCP_HI_DEP_WAVES 6
+#endif
+#ifndef PCCP_HI_WAVES
+#define PCCP_HI_WAVES 7
+#endif
 template <bool DL, bool RL, bool LEARN, int PM, bool HI>
-__global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? 6 : 7) : 1) void search_kernel(SearchParams P)
+__global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? PCCP_HI_DEP_WAVES : PCCP_HI_WAVES) : 1) void search_kernel(SearchParams P)
 {
     constexpr bool LIVE = PM == 1, DEP = PM == 2;
     extern __shared__ __align__(16) char smem[];

@@ -23,14 +23,20 @@ def test_bench_helpers():
     assert bench.algorithmic_bytes(st) == 3 * 16 + 5 * 24 + 7 * 8
     sha = bench.kernel_sha256()
     assert len(sha) == 64
-    keys = {"kernel_sha256", "block", "desc_lds", "root_lds", "live", "occupancy", "dep",
-            "fetch_bytes_per_node", "write_bytes_per_node", "profile"}
+    keys = {"workload", "kernel_sha256", "block", "desc_lds", "root_lds", "live", "occupancy",
+            "dep", "fetch_bytes_per_node", "write_bytes_per_node", "profile"}
     for e in bench.PROFILED_TRAFFIC:
         assert set(e) == keys
         assert os.path.exists(os.path.join(ROOT, e["profile"]))
+        st = {k: e[k] for k in ("block", "desc_lds", "root_lds", "live", "occupancy", "dep")}
+        want = round((e["fetch_bytes_per_node"] + e["write_bytes_per_node"]) * 1000)
+        if e["kernel_sha256"] == sha:
+            assert bench.profiled_traffic(st, 1000, e["workload"]) == want
+        # the same shape on another workload was not profiled
+        assert bench.profiled_traffic(st, 1000, "another_workload") is None
     # a shape that was never profiled reports no traffic
     st = {"block": 96, "desc_lds": 0, "root_lds": 0, "live": 0, "occupancy": 2, "dep": 0}
-    assert bench.profiled_traffic(st, 1000) is None
+    assert bench.profiled_traffic(st, 1000, "rcpsp_mixed_30_60_90tasks_4res_batch256") is None
 
 
 def test_bench_roofline_and_cpu_baseline():
