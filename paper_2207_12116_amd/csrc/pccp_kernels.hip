@@ -249,8 +249,10 @@ enum : int {
     C_SKIP = 27,                            // the record taken was dropped
     C_CNT = 12,                             // item-list counts: 5 words per list
                                             // (R, A, B) = 4 kinds, row terms
-    C_DCNT = 12,                            // or work-list counts: 7 words per set
-                                            // (2 sets) = 5 kinds, terms of kinds 3, 4
+    C_DCNT = 12,                            // or work-list counts: 5 words per set
+                                            // (2 sets), one per kind
+    C_DTERMS = 22,                          // row terms the node's sweeps visited
+                                            // (dependency-driven mode)
     C_TTOP = 26,                            // entries pushed on the trail (dependency-driven
     C_THI = 31,                             // deepest path level without a whole trail  only)
     C_JCNT = 28,                            // entries of the expansion's job list
@@ -683,7 +685,8 @@ __device__ __forceinline__ void term_tell(const Store st, const Dep &dp, int x, 
 // terms' largest values is at most rhs.
 template <bool DL, int RR, bool MK = false>
 __device__ __forceinline__ void sweep_rows(const View<DL> &v, const Store st, const ListIO &io,
-                                           const Dep &dp, bool &chg, bool &bad, uint32_t &nat)
+                                           const Dep &dp, bool &chg, bool &bad, uint32_t &nat,
+                                           uint32_t &nterm)
 {
     constexpr int TK = 2;
     const int tid = threadIdx.x, W = blockDim.x, n = io.n;
@@ -706,6 +709,8 @@ __device__ __forceinline__ void sweep_rows(const View<DL> &v, const Store st, co
         }
 #pragma unroll
         for (int q = 0; q < RR; ++q) rd[q] = v.rows(ri[q]);
+#pragma unroll
+        for (int q = 0; q < RR; ++q) nterm += rok[q] && gl == 0 ? (uint32_t)rd[q].y : 0u;
         int S[RR], Smax[RR];
         if (KC <= TK) {
             uint32_t tv[RR][TK];
@@ -822,7 +827,8 @@ __device__ __forceinline__ void sweep_rows(const View<DL> &v, const Store st, co
 // most rhs.
 template <bool DL, int RB, bool MK = false>
 __device__ __forceinline__ void sweep_brows(const View<DL> &v, const Store st, const ListIO &io,
-                                            const Dep &dp, bool &chg, bool &bad, uint32_t &nat)
+                                            const Dep &dp, bool &chg, bool &bad, uint32_t &nat,
+                                            uint32_t &nterm)
 {
     constexpr int TB = 4;                   // term slots per lane held in registers
     const int tid = threadIdx.x, W = blockDim.x, n = io.n;
@@ -853,6 +859,8 @@ __device__ __forceinline__ void sweep_brows(const View<DL> &v, const Store st, c
                     tv[q][k] = k < KC ? v.bterms(ri[q] * SL + gl + k * G) : 0u;
 #pragma unroll
             for (int q = 0; q < RB; ++q) rd[q] = v.brows(ri[q]);
+#pragma unroll
+            for (int q = 0; q < RB; ++q) nterm += rok[q] && gl == 0 ? (uint32_t)rd[q].y : 0u;
             // per slot only a (open term) or 0 (fixed term) survives the sums;
             // products with a 0/1 bound are 24-bit multiply-adds (a store
             // where a bound left [0, 1] has already failed)
@@ -899,6 +907,7 @@ __device__ __forceinline__ void sweep_brows(const View<DL> &v, const Store st, c
             for (int q = 0; q < RB; ++q) {
                 rd[q] = v.brows(ri[q]);
                 S[q] = Smax[q] = 0;
+                nterm += rok[q] && gl == 0 ? (uint32_t)rd[q].y : 0u;
             }
             for (int k = 0; k < KC; ++k) {
 #pragma unroll
@@ -1022,12 +1031,13 @@ __device__ __forceinline__ void sweep_cmd(const View<DL> &v, const Store st, con
 // run the kept lists.
 constexpr int kKinds = 4;
 constexpr int kKindsDep = kDepKinds;
-constexpr int kDepSetWords = kDepKinds + 2;  // per set: the kinds' list lengths, then row terms
+constexpr int kDepSetWords = kDepKinds;  // per set: the kinds' list lengths
 constexpr int kListWords = kKinds + 1;
 // Item lists (the live mode) and work lists (the dependency-driven mode) are
 // never used together; each must stay clear of the words every mode uses.
 static_assert(C_CNT + 3 * kListWords <= C_SKIP, "item-list counts overlap C_SKIP");
-static_assert(C_DCNT + 2 * kDepSetWords <= C_TTOP, "work-list counts overlap the trail words");
+static_assert(C_DCNT + 2 * kDepSetWords <= C_DTERMS && C_DTERMS < C_TTOP,
+              "work-list counts overlap the term count or the trail words");
 static_assert(C_TTOP != C_SKIP && C_TTOP != C_JCNT && C_TTOP != C_MAXW && C_TTOP != C_ATOM &&
                   C_THI != C_SKIP && C_THI != C_JCNT && C_THI != C_MAXW && C_THI != C_ATOM &&
                   C_THI < 32 && C_THI >= C_DCNT + 2 * kDepSetWords,
@@ -1080,8 +1090,9 @@ __device__ __forceinline__ int propagate_wg(const View<DL> &v, const Store st, i
         bool chg = false, bad = false;
         sweep_diff(v, st, d, nodep, chg, bad, nat);
         sweep_reif<DL, LEAN ? 2 : 4>(v, st, r, nodep, chg, bad, nat);
-        sweep_rows<DL, LEAN ? 2 : 4>(v, st, w, nodep, chg, bad, nat);
-        sweep_brows<DL, LEAN ? 1 : 2>(v, st, b, nodep, chg, bad, nat);
+        uint32_t unused_terms = 0;   // the tables' term counts are known
+        sweep_rows<DL, LEAN ? 2 : 4>(v, st, w, nodep, chg, bad, nat, unused_terms);
+        sweep_brows<DL, LEAN ? 1 : 2>(v, st, b, nodep, chg, bad, nat, unused_terms);
         if (v.ncmd) sweep_cmd(v, st, ListIO{nullptr, v.ncmd, nullptr, nullptr, nullptr}, nodep, chg, bad, nat);
         ex[0] += (unsigned)d.n;
         ex[1] += (unsigned)r.n;
@@ -1112,17 +1123,15 @@ __device__ __forceinline__ int propagate_wg(const View<DL> &v, const Store st, i
 
 // Work lists of the next sweep from the change bitmaps of the last one:
 // every propagator that reads a tightened bound (rows once: the queued bit
-// qm of a row is set when it is listed; see dep_queue).  Clears the bitmaps.  cnt: list
-// counts of the 5 kinds, then the terms of the listed rows of kinds 3 and
-// 4; zeroed by the caller before a barrier.  A count past its list's
-// capacity means the next sweep runs that kind's whole table.
+// qm of a row is set when it is listed; see dep_queue).  Clears the bitmaps.
+// cnt: list counts of the 5 kinds, zeroed by the caller before a barrier.
+// A count past its list's capacity means the next sweep runs that kind's
+// whole table.
 // Bitmap word w is read by wavefront w % nw, so the variables of one
 // region of the store (the start times, say) spread over all wavefronts.
 // one chunk of adjacency entries (0 = none): queue the propagators that read
 // a bound in `reads`
-template <bool DL>
-__device__ __forceinline__ void dep_queue(const View<DL> &v, const Dep &dp, int32_t *cnt,
-                                          uint32_t e, uint32_t reads)
+__device__ __forceinline__ void dep_queue(const Dep &dp, int32_t *cnt, uint32_t e, uint32_t reads)
 {
     const int lane = threadIdx.x & 63;
     const int k = (int)((e >> 16) & 7u), idx = (int)(e & 0xffffu);
@@ -1150,13 +1159,19 @@ __device__ __forceinline__ void dep_queue(const View<DL> &v, const Dep &dp, int3
             const int r = pos + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
             if (r < dp.wcap[kk]) dp.wl[dp.woff[kk] + r] = (uint16_t)idx;
-            if (kk == 2 || kk == 3)
-                __hip_atomic_fetch_add(cnt + kDepKinds + kk - 2, kk == 2 ? v.rows(idx).y : v.brows(idx).y,
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
 }
 
+// One-phase expansion: each wavefront takes the bitmap words w with
+// w % nw == its index (64 words a round, one per lane).  The changed
+// variables of a round are taken in batches of one per lane (the lowest
+// bit left in the lane's word): every lane loads its variable's adjacency
+// range at once, a prefix sum over the lanes lays the batch's entries end
+// to end, and the wavefront queues them 64 at a time.  A batch of
+// variables with few readers each (a Boolean is read by its reified item
+// and its rows) thus costs one round trip for the ranges and one per 64
+// entries, instead of two per variable.
 template <bool DL>
 __device__ __forceinline__ void dep_expand(const View<DL> &v, const Dep &dp, int32_t *cnt)
 {
@@ -1172,22 +1187,46 @@ __device__ __forceinline__ void dep_expand(const View<DL> &v, const Dep &dp, int
                 dp.um[w] = 0;
             }
         }
-        unsigned long long act = __ballot((bl | bu) != 0);
-        while (act) {
-            const int L = __builtin_ctzll(act);
-            act &= act - 1;
-            const uint32_t ml = (uint32_t)__builtin_amdgcn_readlane((int)bl, L);
-            const uint32_t mu = (uint32_t)__builtin_amdgcn_readlane((int)bu, L);
-            const int wl = base + wid + nw * L;
-            uint32_t bits = ml | mu;
-            while (bits) {
+        uint32_t bits = bl | bu;
+        while (__ballot(bits != 0)) {
+            int a0 = 0, n = 0;
+            uint32_t reads = 0;
+            if (bits) {
                 const int b = __builtin_ctz(bits);
                 bits &= bits - 1;
-                const int x = (b << dp.vshift) | wl;
-                const uint32_t reads = (((ml >> b) & 1u) ? kAdjLb : 0u) | (((mu >> b) & 1u) ? kAdjUb : 0u);
-                const int a0 = uni(v.adjp(x)), a1 = uni(v.adjp(x + 1));
-                for (int a = a0; a < a1; a += 64)
-                    dep_queue(v, dp, cnt, a + lane < a1 ? v.adj(a + lane) : 0u, reads);
+                const int x = (b << dp.vshift) | w;
+                reads = (((bl >> b) & 1u) ? kAdjLb : 0u) | (((bu >> b) & 1u) ? kAdjUb : 0u);
+                a0 = v.adjp(x);
+                n = v.adjp(x + 1) - a0;
+            }
+            // lane i's entries take positions [excl, incl) of the batch
+            int incl = n;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int t = __shfl_up(incl, d, 64);
+                if (lane >= d) incl += t;
+            }
+            const int excl = incl - n;
+            const int total = __shfl(incl, 63, 64);
+            const unsigned long long has = __ballot(n > 0);
+            for (int lo = 0; lo < total; lo += 64) {
+                const int g = lo + lane;
+                // the lanes whose ranges meet [lo, lo + 64), in lane order:
+                // entry g belongs to the last of them that starts at or
+                // before g
+                unsigned long long meet = has & __ballot(excl < lo + 64) & __ballot(incl > lo);
+                int off = 0;
+                uint32_t rd = 0;
+                while (meet) {
+                    const int L = __builtin_ctzll(meet);
+                    meet &= meet - 1;
+                    const int se = __builtin_amdgcn_readlane(excl, L);
+                    if (g >= se) {
+                        off = __builtin_amdgcn_readlane(a0, L) + (g - se);
+                        rd = (uint32_t)__builtin_amdgcn_readlane((int)reads, L);
+                    }
+                }
+                dep_queue(dp, cnt, g < total ? v.adj(off) : 0u, rd);
             }
         }
     }
@@ -1264,7 +1303,7 @@ __device__ __forceinline__ void dep_expand_jobs(const View<DL> &v, const Dep &dp
             const uint32_t e0 = (uint32_t)__shfl((int)ent, L, 64);
             const uint32_t reads = ((e0 >> 30) & 1u ? kAdjLb : 0u) | ((e0 >> 31) & 1u ? kAdjUb : 0u);
             const int a = b0 + 64 * (j - __shfl(first, L, 64));
-            dep_queue(v, dp, cnt, a + lane < b1 ? v.adj(a + lane) : 0u, reads);
+            dep_queue(dp, cnt, a + lane < b1 ? v.adj(a + lane) : 0u, reads);
         }
     }
 }
@@ -1274,7 +1313,8 @@ __device__ __forceinline__ void dep_expand_jobs(const View<DL> &v, const Dep &dp
 // marks left by an earlier node are cleared); otherwise the store is a
 // fixed point joined with the tells marked since (a decision, the objective
 // bound), and the first sweep runs what they make ready.  Returns as
-// propagate_wg; ex[] counts the items and row terms run.
+// propagate_wg; ex[0..2] count the items run, and the terms of the rows run
+// are summed into ctl[C_DTERMS] (complete after the caller's next barrier).
 // TWO: the build may run the two-phase expansion (workgroups of 8 or more
 // wavefronts, dp.jcap > 0); the high-occupancy build never does.
 template <bool DL, bool LEAN, bool TWO>
@@ -1290,6 +1330,7 @@ __device__ __forceinline__ int propagate_dep(const View<DL> &v, const Store st, 
         *reinterpret_cast<unsigned long long *>(ctl + C_KEY) = ~0ull;
         for (int k = 0; k < 2 * kDepSetWords; ++k) ctl[C_DCNT + k] = 0;
         ctl[C_JCNT] = 0;
+        ctl[C_DTERMS] = 0;
     }
     if (full)
         for (int w = tid; w < dp.vw; w += W) {
@@ -1314,6 +1355,16 @@ __device__ __forceinline__ int propagate_dep(const View<DL> &v, const Store st, 
     const int tab[kDepKinds] = {v.ndiff, v.nreif, v.nrows, v.nbrows, v.ncmd};
     int slot = 0;
     bool all = full;
+    uint32_t nterm = 0;   // terms of the rows this lane's groups ran
+    // every wavefront's term count into ctl[C_DTERMS] (read after a barrier)
+    auto publish_terms = [&]() {
+        uint32_t t = nterm;
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) t += (uint32_t)__shfl_xor((int)t, d, 64);
+        if (lane == 0 && t)
+            __hip_atomic_fetch_add(&ctl[C_DTERMS], (int32_t)t, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
     for (;;) {
         const int32_t *c = ctl + C_DCNT + kDepSetWords * set;
         ListIO io[kDepKinds];
@@ -1325,8 +1376,6 @@ __device__ __forceinline__ int propagate_dep(const View<DL> &v, const Store st, 
             io[k] = whole[k] ? ListIO{nullptr, tab[k], nullptr, nullptr, nullptr}
                              : ListIO{dp.wl + dp.woff[k], n, nullptr, nullptr, nullptr};
         }
-        const int terms = (whole[2] ? v.nterms : uni(lds_ld(&c[kDepKinds]))) +
-                          (whole[3] ? v.nbterms : uni(lds_ld(&c[kDepKinds + 1])));
         if (tid == 0) {
             for (int k = 0; k < kDepSetWords; ++k) ctl[C_DCNT + kDepSetWords * (set ^ 1) + k] = 0;
             ctl[C_JCNT] = 0;    // read by the last expansion before the barrier ending it
@@ -1336,13 +1385,12 @@ __device__ __forceinline__ int propagate_dep(const View<DL> &v, const Store st, 
         bool chg = false, bad = false;
         sweep_diff<DL, true>(v, st, io[0], dp, chg, bad, nat);
         sweep_reif<DL, LEAN ? 2 : 4, true>(v, st, io[1], dp, chg, bad, nat);
-        sweep_rows<DL, LEAN ? 2 : 4, true>(v, st, io[2], dp, chg, bad, nat);
-        sweep_brows<DL, LEAN ? 1 : 2, true>(v, st, io[3], dp, chg, bad, nat);
+        sweep_rows<DL, LEAN ? 2 : 4, true>(v, st, io[2], dp, chg, bad, nat, nterm);
+        sweep_brows<DL, LEAN ? 1 : 2, true>(v, st, io[3], dp, chg, bad, nat, nterm);
         if (io[4].n) sweep_cmd<DL, true>(v, st, io[4], dp, chg, bad, nat);
         ex[0] += (unsigned)io[0].n;
         ex[1] += (unsigned)io[1].n;
         ex[2] += (unsigned)(io[2].n + io[3].n + io[4].n);
-        ex[3] += (unsigned)terms;
         const int flags = (__any(chg) ? 1 : 0) | (__any(bad) ? 2 : 0);
         if (lane == 0 && flags)
             __hip_atomic_fetch_or(&ctl[slot], flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1359,9 +1407,13 @@ __device__ __forceinline__ int propagate_dep(const View<DL> &v, const Store st, 
                 dp.lm[w] = 0;
                 dp.um[w] = 0;
             }
+            publish_terms();
             return 1;
         }
-        if (!(f & 1)) return 0;
+        if (!(f & 1)) {
+            publish_terms();
+            return 0;
+        }
         slot = next;
         set ^= 1;
         all = false;
@@ -2197,6 +2249,7 @@ __global__ __launch_bounds__(HI ? 256 : 1024, HI ? (PM == 2 ? PCCP_HI_DEP_WAVES 
                 z.since_flush += 1;
                 z.sweeps += nsw;
                 for (int k = 0; k < 4; ++k) z.ex[k] += ex[k];
+                if constexpr (DEP) z.ex[3] += (uint32_t)lds_ld(ctl + C_DTERMS);
                 z.atom += (uint32_t)lds_ld(ctl + C_ATOM);
                 ctl[C_ATOM] = 0;
                 if ((unsigned long long)depth > z.maxd) z.maxd = depth;
