@@ -1163,6 +1163,28 @@ __device__ __forceinline__ void dep_queue(const Dep &dp, int32_t *cnt, uint32_t 
     }
 }
 
+// Inclusive prefix sum over the 64 lanes of a wavefront (every lane
+// active) with DPP moves: shifts by 1, 2, 4 and 8 within each row of 16
+// lanes, then the broadcast of lane 15 of a row into the next row (kept by
+// rows 1 and 3) and of lane 31 into rows 2 and 3.
+__device__ __forceinline__ int wave_incl_sum(int x)
+{
+    const int lane = threadIdx.x & 63, rl = lane & 15;
+    int t = __builtin_amdgcn_mov_dpp(x, 0x111, 0xf, 0xf, false);    // row_shr:1
+    if (rl >= 1) x += t;
+    t = __builtin_amdgcn_mov_dpp(x, 0x112, 0xf, 0xf, false);        // row_shr:2
+    if (rl >= 2) x += t;
+    t = __builtin_amdgcn_mov_dpp(x, 0x114, 0xf, 0xf, false);        // row_shr:4
+    if (rl >= 4) x += t;
+    t = __builtin_amdgcn_mov_dpp(x, 0x118, 0xf, 0xf, false);        // row_shr:8
+    if (rl >= 8) x += t;
+    t = __builtin_amdgcn_mov_dpp(x, 0x142, 0xf, 0xf, false);        // row_bcast:15
+    if ((lane & 31) >= 16) x += t;
+    t = __builtin_amdgcn_mov_dpp(x, 0x143, 0xf, 0xf, false);        // row_bcast:31
+    if (lane >= 32) x += t;
+    return x;
+}
+
 // One-phase expansion: each wavefront takes the bitmap words w with
 // w % nw == its index (64 words a round, one per lane).  The changed
 // variables of a round are taken in batches of one per lane (the lowest
@@ -1200,33 +1222,30 @@ __device__ __forceinline__ void dep_expand(const View<DL> &v, const Dep &dp, int
                 n = v.adjp(x + 1) - a0;
             }
             // lane i's entries take positions [excl, incl) of the batch
-            int incl = n;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const int t = __shfl_up(incl, d, 64);
-                if (lane >= d) incl += t;
-            }
+            const int incl = wave_incl_sum(n);
             const int excl = incl - n;
-            const int total = __shfl(incl, 63, 64);
+            const int total = __builtin_amdgcn_readlane(incl, 63);
             const unsigned long long has = __ballot(n > 0);
             for (int lo = 0; lo < total; lo += 64) {
                 const int g = lo + lane;
-                // the lanes whose ranges meet [lo, lo + 64), in lane order:
-                // entry g belongs to the last of them that starts at or
-                // before g
+                // the lanes whose ranges meet [lo, lo + 64): entry g is the
+                // one whose range holds it (the load stays inside that range)
                 unsigned long long meet = has & __ballot(excl < lo + 64) & __ballot(incl > lo);
                 int off = 0;
                 uint32_t rd = 0;
+                bool hit = false;
                 while (meet) {
                     const int L = __builtin_ctzll(meet);
                     meet &= meet - 1;
                     const int se = __builtin_amdgcn_readlane(excl, L);
-                    if (g >= se) {
+                    const int sn = __builtin_amdgcn_readlane(n, L);
+                    if (g >= se && g - se < sn) {
+                        hit = true;
                         off = __builtin_amdgcn_readlane(a0, L) + (g - se);
                         rd = (uint32_t)__builtin_amdgcn_readlane((int)reads, L);
                     }
                 }
-                dep_queue(dp, cnt, g < total ? v.adj(off) : 0u, rd);
+                dep_queue(dp, cnt, hit ? v.adj(off) : 0u, rd);
             }
         }
     }
