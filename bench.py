@@ -61,14 +61,14 @@ BYTES_DIFF, BYTES_REIF, BYTES_TERM = 16, 24, 8
 # shape differs reports null.
 PROFILED_TRAFFIC = [
     {"workload": "rcpsp_mixed_30_60_90tasks_4res_batch256",
-     "kernel_sha256": "6b246f4230f84a5fcbdd0dd9dc5750424b1cb5e15530a13c13425308db25fe0b",
+     "kernel_sha256": "2f0ae3f62165b9e1254b6123a20473bb44b2fa4df47e9f1510d6398740c16d03",
      "block": 128, "desc_lds": 0, "root_lds": 0, "live": 0, "occupancy": 2, "dep": 1,
-     "fetch_bytes_per_node": 1165.0, "write_bytes_per_node": 295.6,
+     "fetch_bytes_per_node": 745.6, "write_bytes_per_node": 275.7,
      "profile": "profiles/search_kernel_rcpsp_mixed256_wg128.md"},
     {"workload": "rcpsp_120tasks_4res_single",
-     "kernel_sha256": "6b246f4230f84a5fcbdd0dd9dc5750424b1cb5e15530a13c13425308db25fe0b",
+     "kernel_sha256": "2f0ae3f62165b9e1254b6123a20473bb44b2fa4df47e9f1510d6398740c16d03",
      "block": 256, "desc_lds": 0, "root_lds": 0, "live": 0, "occupancy": 1, "dep": 1,
-     "fetch_bytes_per_node": 52.3, "write_bytes_per_node": 1728.0,
+     "fetch_bytes_per_node": 20.9, "write_bytes_per_node": 756.0,
      "profile": "profiles/search_kernel_rcpsp120_single.md"},
 ]
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
