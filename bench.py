@@ -498,22 +498,24 @@ def main():
     if not args.no_legs:
         log("plain: 30-task instances, one at a time on the whole GPU")
         c2 = [I.rcpsp(30, s) for s in range(4)]
-        c2cfg, c2rep = autotune.tune(c2, pccp.MINIMIZE, budget_s=0.3, cache_path=None,
+        # tuned on one instance alone (the plain form), finalists over 2 s
+        c2cfg, c2rep = autotune.tune(c2[:1], pccp.MINIMIZE, budget_s=0.5, cache_path=None,
                                      wg_sizes=(128, 256, 512), max_depth=args.max_depth, log=log)
-        legs = {"c2_plain_30tasks": plain_leg(c2, 1.5, c2cfg, peaks)}
+        legs = {"c2_plain_30tasks": plain_leg(c2, 3.0, c2cfg, peaks)}
         legs["c2_plain_30tasks"]["config"] = {"wg_size": c2cfg.wg_size, "prop": c2rep["prop"],
-                                              "seeds": "0-3", "limit_s": 1.5}
+                                              "occupancy": c2cfg.occupancy, "seeds": "0-3",
+                                              "limit_s": 3.0}
         log(f"c2: {legs['c2_plain_30tasks']}")
         log("tiny CSP, every solution, whole GPU")
         legs["c1_enumerate"] = enumerate_leg([0, 1, 2, 3], 30.0)
         log(f"c1: {legs['c1_enumerate']}")
         log("120-task instance, whole GPU")
         c3m = [I.rcpsp(120, 0)]
-        c3cfg, c3rep = autotune.tune(c3m, pccp.MINIMIZE, budget_s=0.3, cache_path=None,
+        c3cfg, c3rep = autotune.tune(c3m, pccp.MINIMIZE, budget_s=0.5, cache_path=None,
                                      wg_sizes=(128, 256, 512), max_depth=args.max_depth, log=log)
-        legs["c3_120tasks"] = plain_leg(c3m, 2.0, c3cfg, peaks)
+        legs["c3_120tasks"] = plain_leg(c3m, 3.0, c3cfg, peaks)
         legs["c3_120tasks"]["config"] = {"wg_size": c3cfg.wg_size, "prop": c3rep["prop"],
-                                         "seed": 0, "limit_s": 2.0}
+                                         "occupancy": c3cfg.occupancy, "seed": 0, "limit_s": 3.0}
         log(f"c3: {legs['c3_120tasks']}")
         log("job shops 10x10 from the PCCP front-end, 16 in one launch")
         jsm = [I.jobshop(10, 10, s) for s in range(16)]
