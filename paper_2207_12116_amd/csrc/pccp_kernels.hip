@@ -5,15 +5,18 @@
 // Design (the paper's own GPU solver, §5, was written for a Turing laptop
 // GPU; this keeps what holds on gfx950 and changes the rest):
 //   * One workgroup per subproblem (§5: one block per subproblem).  The
-//     store of the subproblem lives in LDS as one (lb, ub) int32 pair per
-//     variable (int2), so one 64-bit LDS read fetches both bounds.
+//     store of the subproblem lives in LDS: each integer variable as one
+//     (lb, ub) int32 pair (one 64-bit LDS read fetches both bounds), each
+//     Boolean (initial domain within [0, 1]) as one byte (bit 0: lb = 1,
+//     bit 1: ub = 0), joined with an LDS atomic OR.
 //   * Two propagation modes.  Every table every sweep (eventless, §5): each
 //     lane takes descriptors t = tid, tid + W, ... of each kind in turn (§5,
 //     fixed point loop: strided loop over the propagators).  Dependency-
 //     driven (the improvement §6 names): a sweep runs only the propagators
 //     that read a bound the previous sweep tightened, found through a
-//     variable -> propagator adjacency; the same least fixed point by
-//     chaotic iteration (§3 Theorem 2).
+//     variable -> propagator adjacency, whose entries each wavefront lays
+//     out for a batch of changed variables at once; the same least fixed
+//     point by chaotic iteration (§3 Theorem 2).
 //   * A tell is a lattice join: LDS atomic max on lb, atomic min on ub
 //     (ds_max_i32 / ds_min_i32, no return).  The plain load + compare +
 //     store of the load/store compilation (§4) can lose an update when two
@@ -24,9 +27,10 @@
 //     joined value is greater).
 //   * Fixed-point detection: the change and failure bits of a sweep are
 //     OR-ed per wavefront with a ballot and published by lane 0 into one of
-//     three rotating LDS words; one barrier per sweep (§5, has_changed[3]).
-//     The barrier is an LDS-only fence + s_barrier, so global loads issued
-//     by the control lane stay in flight across sweeps.
+//     three rotating LDS words; one barrier per sweep (§5, has_changed[3]),
+//     and one more after the work-list expansion in the dependency-driven
+//     mode.  The barrier is an LDS-only fence + s_barrier, so global loads
+//     issued by the control lane stay in flight across sweeps.
 //   * Failure (an empty interval, §5) is flagged in-loop whenever a tell
 //     crosses the opposite bound it read, which bounds the number of sweeps
 //     on failing stores, and confirmed by a scan of the store at the fixed
@@ -42,8 +46,8 @@
 //     closest to its subproblem root to a bounded lock-free MPMC queue when
 //     other workgroups are idle.
 //
-// No MFMA: the work is integer lattice arithmetic, bound by LDS traffic and
-// barrier latency.
+// No MFMA: the work is integer lattice arithmetic, bound by the latency of
+// dependent LDS and L2 round trips and of barriers.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
