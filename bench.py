@@ -295,6 +295,96 @@ def ttpo_forms(models, per_limit, cfg, weights, label):
     return res
 
 
+def fixpoint_leg(peaks, nbox=4096, fbox=1024, reps=5):
+    """Fixed points of many boxes per launch, inputs resident in HBM, timed
+    with HIP events on the solvers' stream (the current one):
+      every_table  the 30-task instance's root box, every table every sweep
+      incremental  its root fixed point joined with one random decision per
+                   box (a start time split at a random point),
+                   dependency-driven
+      float        a sparse system over the reals (1000 variables, 2000 rows
+                   of 2-6 terms, built around a point that satisfies every
+                   row), its root box (random sub-boxes of such a system are
+                   nearly all empty), outward-rounded linear tells on float32
+                   bounds
+    The float kernel's algorithmic LDS bytes: every sweep runs every row,
+    and each of a row's L term tells reads the bounds of the row's L terms
+    (8 bytes each), so 8 L^2 bytes per row and sweep."""
+    import numpy as np
+    import torch
+    from paper_2207_12116_amd import instances as I, pccp
+    rng = np.random.default_rng(11)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+
+    out = {}
+    m = I.rcpsp(30, 0)
+    s = pccp.Solver(m)
+    V = m.nvars
+    lbs = torch.tensor(np.tile(m.lb, (nbox, 1)), dtype=torch.int32, device="cuda")
+    ubs = torch.tensor(np.tile(m.ub, (nbox, 1)), dtype=torch.int32, device="cuda")
+    olb, oub = torch.empty_like(lbs), torch.empty_like(ubs)
+    st = torch.zeros(nbox, dtype=torch.int32, device="cuda")
+    sw = torch.zeros(nbox, dtype=torch.int32, device="cuda")
+    t = timed(lambda: s.propagate_batch(lbs, ubs, olb, oub, st, sw))
+    out["every_table"] = {"boxes": nbox, "variables": V, "s_per_launch": round(t, 6),
+                          "boxes_per_s": round(nbox / t, 1),
+                          "sweeps_per_box": float(sw.float().mean().item())}
+    # parents: the root fixed point; decisions: random start-time splits
+    root_l, root_u = olb[:1].clone(), oub[:1].clone()
+    plb, pub = root_l.repeat(nbox, 1).contiguous(), root_u.repeat(nbox, 1).contiguous()
+    rl, ru = root_l[0].cpu().numpy(), root_u[0].cpu().numpy()
+    dec = np.asarray(m.decision)
+    xs = rng.choice(dec, size=nbox)
+    dlo, dhi = np.empty(nbox, np.int32), np.empty(nbox, np.int32)
+    for k, x in enumerate(xs):
+        lo, hi = int(rl[x]), int(ru[x])
+        mid = lo + int(rng.integers(0, max(1, hi - lo)))
+        if rng.random() < 0.5:
+            dlo[k], dhi[k] = lo, mid
+        else:
+            dlo[k], dhi[k] = mid + 1, hi
+    dv = torch.tensor(xs.astype(np.int32), device="cuda")
+    dl, dh = torch.tensor(dlo, device="cuda"), torch.tensor(dhi, device="cuda")
+    t = timed(lambda: s.propagate_batch_incr(plb, pub, dv, dl, dh, olb, oub, st, sw))
+    out["incremental"] = {"boxes": nbox, "s_per_launch": round(t, 6),
+                          "boxes_per_s": round(nbox / t, 1),
+                          "sweeps_per_box": float(sw.float().mean().item()),
+                          "failed": int((st == 1).sum().item())}
+    # float boxes
+    fm = I.float_network(1000, 2)
+    fs = pccp.FSolver(fm)
+    flb = np.tile(fm.lb, (fbox, 1)).astype(np.float32)
+    fub = np.tile(fm.ub, (fbox, 1)).astype(np.float32)
+    tl, tu = torch.tensor(flb, device="cuda"), torch.tensor(fub, device="cuda")
+    ol, ou = torch.empty_like(tl), torch.empty_like(tu)
+    fst = torch.zeros(fbox, dtype=torch.int32, device="cuda")
+    fsw = torch.zeros(fbox, dtype=torch.int32, device="cuda")
+    t = timed(lambda: fs.propagate_batch(tl, tu, ol, ou, fst, fsw))
+    L = np.diff(np.asarray(fm.row_ptr, dtype=np.int64))
+    per_sweep = int(8 * (L * L).sum())
+    sweeps = float(fsw.sum().item())
+    fb = per_sweep * sweeps
+    out["float"] = {"boxes": fbox, "variables": fm.nvars, "rows": fm.nrows,
+                    "s_per_launch": round(t, 6), "boxes_per_s": round(fbox / t, 1),
+                    "sweeps_per_box": round(sweeps / fbox, 2),
+                    "failed": int((fst == 1).sum().item()),
+                    "lds_bytes_per_launch": int(fb),
+                    "lds_GBs": round(fb / t / 1e9, 1),
+                    "lds_frac": round(fb / t / 1e9 / peaks["read_GBs"], 5)}
+    fs.close()
+    return out
+
+
 def learned_120_leg(seeds, limit, cfg, weights, scan):
     """The learned branching rule against first-fail on held-out 120-task
     instances (training used 30- and 60-task seeds), each form on the whole
@@ -386,6 +476,9 @@ def main():
     ap.add_argument("--ttpo-limit", type=float, default=1.0,
                     help="device seconds per instance in the TTPO comparison (the paper's "
                          "protocol for 30-task instances is 30)")
+    ap.add_argument("--fixpoints-only", action="store_true",
+                    help="run only the fixed-point batches (every table, incremental, float) "
+                         "and print their figures as one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 2 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -404,6 +497,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.fixpoints_only:
+        from paper_2207_12116_amd import pccp
+        print(json.dumps(fixpoint_leg(pccp.lds_peaks())), flush=True)
+        return
     from paper_2207_12116_amd import autotune, instances as I, pccp
 
     peaks = pccp.lds_peaks()
@@ -525,6 +622,9 @@ def main():
         legs["jobshop_10x10_batch16"]["config"] = {"wg_size": jscfg.wg_size, "prop": jsrep["prop"],
                                                    "occupancy": jscfg.occupancy}
         log(f"jobshop: {legs['jobshop_10x10_batch16']}")
+        log("fixed points of box batches: every table, incremental, float")
+        legs["fixpoint_batches"] = fixpoint_leg(peaks)
+        log(f"fixpoints: {legs['fixpoint_batches']}")
         from paper_2207_12116_amd import learn
         log("learned vs first-fail on held-out 120-task instances")
         legs["c5_learned_120tasks"] = learned_120_leg(
