@@ -385,6 +385,57 @@ def fixpoint_leg(peaks, nbox=4096, fbox=1024, reps=5):
     return out
 
 
+def mlp_leg(nodes=4096, cmin=10, cmax=90, steps=20):
+    """The learned rule's kernels on synthetic traces of the training shape
+    (4096 nodes, 10-90 candidates each, 6 features, a target distribution
+    per node): training steps (forward and per-node cross-entropy, backward,
+    reduce and Adam, BF16 refresh) and BF16 scoring, timed with HIP events.
+    Work per candidate: the forward pass is 2*6*64 + 64 + 2*64 = 960 flops
+    (FP32), the backward about twice that; so about 2.9 kflop per candidate
+    per training step, 0.96 kflop per scored candidate."""
+    import numpy as np
+    import torch
+    from paper_2207_12116_amd import pccp
+    rng = np.random.default_rng(5)
+    cnt = rng.integers(cmin, cmax + 1, size=nodes)
+    off = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int32)
+    C = int(off[-1])
+    feat = rng.random((C, 6), dtype=np.float32)
+    tgt = np.empty(C, np.float32)
+    for i in range(nodes):
+        z = rng.random(cnt[i]).astype(np.float32)
+        tgt[off[i]:off[i + 1]] = z / z.sum()
+    f = torch.tensor(feat, device="cuda")
+    o = torch.tensor(off, device="cuda")
+    t = torch.tensor(tgt, device="cuda")
+    sc = torch.empty(C, dtype=torch.float32, device="cuda")
+    mlp = pccp.MLP(seed=1)
+    mlp.train_step(f, o, t, cmax, 1e-3)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        mlp.train_step(f, o, t, cmax, 1e-3)
+    e1.record()
+    torch.cuda.synchronize()
+    ts = e0.elapsed_time(e1) / 1e3 / steps
+    mlp.scores(f, sc)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        mlp.scores(f, sc)
+    e1.record()
+    torch.cuda.synchronize()
+    tsc = e0.elapsed_time(e1) / 1e3 / steps
+    mlp.close()
+    return {"nodes": nodes, "candidates": C,
+            "train_step_ms": round(ts * 1e3, 3), "train_candidates_per_s": round(C / ts, 1),
+            "train_TFLOPs": round(2.88e3 * C / ts / 1e12, 3),
+            "score_ms": round(tsc * 1e3, 3), "score_candidates_per_s": round(C / tsc, 1),
+            "score_TFLOPs": round(0.96e3 * C / tsc / 1e12, 3),
+            "fp32_vector_peak_TFLOPs": 157.3}
+
+
 def learned_120_leg(seeds, limit, cfg, weights, scan):
     """The learned branching rule against first-fail on held-out 120-task
     instances (training used 30- and 60-task seeds), each form on the whole
@@ -478,7 +529,7 @@ def main():
                          "protocol for 30-task instances is 30)")
     ap.add_argument("--fixpoints-only", action="store_true",
                     help="run only the fixed-point batches (every table, incremental, float) "
-                         "and print their figures as one JSON line")
+                         "and the learned rule's kernels; print their figures as one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 2 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -499,7 +550,8 @@ def main():
         sys.exit(1)
     if args.fixpoints_only:
         from paper_2207_12116_amd import pccp
-        print(json.dumps(fixpoint_leg(pccp.lds_peaks())), flush=True)
+        print(json.dumps({"fixpoint_batches": fixpoint_leg(pccp.lds_peaks()),
+                          "mlp_train_score": mlp_leg()}), flush=True)
         return
     from paper_2207_12116_amd import autotune, instances as I, pccp
 
@@ -625,6 +677,9 @@ def main():
         log("fixed points of box batches: every table, incremental, float")
         legs["fixpoint_batches"] = fixpoint_leg(peaks)
         log(f"fixpoints: {legs['fixpoint_batches']}")
+        log("learned rule: training steps and scoring on synthetic traces")
+        legs["mlp_train_score"] = mlp_leg()
+        log(f"mlp: {legs['mlp_train_score']}")
         from paper_2207_12116_amd import learn
         log("learned vs first-fail on held-out 120-task instances")
         legs["c5_learned_120tasks"] = learned_120_leg(

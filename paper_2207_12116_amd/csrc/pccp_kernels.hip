@@ -2522,8 +2522,10 @@ __global__ void init_search_kernel(SearchParams P)
 // the features, fixed-order wave sum).  Loss: mean over nodes of the
 // cross-entropy between the target distribution over the node's candidates
 // and the softmax of their scores.  Gradients are summed
-// per wave into a partial row, then reduced in wave order (deterministic),
-// fused with the Adam update and the bf16 copy the search reads.
+// per wave into a partial row, then reduced in a fixed order (32 groups of
+// consecutive waves in parallel, then the groups in order: deterministic),
+// the last step fused with the Adam update and the bf16 copy the search
+// reads.
 constexpr int kPartW = 520;        // partial row: 513 gradients, loss at 513
 constexpr int kMaxCand = 256;      // candidates per node in training data
 
@@ -2650,7 +2652,22 @@ __device__ __forceinline__ uint16_t f2bf(float x)
     return (uint16_t)(u >> 16);
 }
 
-// thread p: gradient p summed over the waves in order, then Adam
+// Deterministic two-level sum of the per-wave partial rows: block (x, g)
+// sums rows [g * NW / G, (g + 1) * NW / G) in order into row g of `out`;
+// mlp_reduce_adam_kernel then sums the G rows in order.
+constexpr int kMlpGroups = 32;
+__global__ __launch_bounds__(256) void mlp_reduce_groups_kernel(const float *partial, int NW,
+                                                                float *out)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > kNumParams) return;
+    const int g = blockIdx.y, w0 = g * NW / kMlpGroups, w1 = (g + 1) * NW / kMlpGroups;
+    float acc = 0.f;
+    for (int w = w0; w < w1; ++w) acc += partial[(size_t)w * kPartW + p];
+    out[(size_t)g * kPartW + p] = acc;
+}
+
+// thread p: gradient p summed over the rows in order, then Adam
 __global__ void mlp_reduce_adam_kernel(const float *partial, int NW, float *grad, float *params,
                                        float *m1, float *v1, uint16_t *wbf, float lr, int step,
                                        float *loss_out)
@@ -2704,7 +2721,8 @@ __global__ __launch_bounds__(256) void mlp_scores_kernel(const float *params, co
     }
 }
 
-int mlp_partial_rows() { return 256 * 4; }   // waves of the training launches (256 x 256 threads)
+// waves of the training launches (256 x 256 threads), then the group sums
+int mlp_partial_rows() { return 256 * 4 + kMlpGroups; }
 
 hipError_t launch_mlp_train(const float *feat, const int32_t *off, const float *target, int nnodes,
                             int ncand, float *params, float *m1, float *v1, uint16_t *wbf,
@@ -2716,8 +2734,11 @@ hipError_t launch_mlp_train(const float *feat, const int32_t *off, const float *
                        target, nnodes, g, partial);
     hipLaunchKernelGGL(mlp_bwd_kernel, dim3(blocks), dim3(256), 0, stream, params, feat, g, ncand,
                        partial);
+    float *groups = partial + (size_t)blocks * 4 * kPartW;
+    hipLaunchKernelGGL(mlp_reduce_groups_kernel, dim3((kNumParams + 1 + 255) / 256, kMlpGroups),
+                       dim3(256), 0, stream, partial, blocks * 4, groups);
     hipLaunchKernelGGL(mlp_reduce_adam_kernel, dim3((kNumParams + 1 + 255) / 256), dim3(256), 0,
-                       stream, partial, blocks * 4, grad, params, m1, v1, wbf, lr, step, loss_dev);
+                       stream, groups, kMlpGroups, grad, params, m1, v1, wbf, lr, step, loss_dev);
     return hipGetLastError();
 }
 
