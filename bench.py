@@ -61,12 +61,12 @@ BYTES_DIFF, BYTES_REIF, BYTES_TERM = 16, 24, 8
 # shape differs reports null.
 PROFILED_TRAFFIC = [
     {"workload": "rcpsp_mixed_30_60_90tasks_4res_batch256",
-     "kernel_sha256": "4e501505c755ef65041bc50cad86c9a3bee3792c5d8e6a7ffc61f9dacc75f5e3",
+     "kernel_sha256": "7197025a878158d14d2299204c0a556c7ce0fa4e08ebd26d4bb648579002a030",
      "block": 128, "desc_lds": 0, "root_lds": 0, "live": 0, "occupancy": 2, "dep": 1,
      "fetch_bytes_per_node": 745.6, "write_bytes_per_node": 275.7,
      "profile": "profiles/search_kernel_rcpsp_mixed256_wg128.md"},
     {"workload": "rcpsp_120tasks_4res_single",
-     "kernel_sha256": "4e501505c755ef65041bc50cad86c9a3bee3792c5d8e6a7ffc61f9dacc75f5e3",
+     "kernel_sha256": "7197025a878158d14d2299204c0a556c7ce0fa4e08ebd26d4bb648579002a030",
      "block": 256, "desc_lds": 0, "root_lds": 0, "live": 0, "occupancy": 1, "dep": 1,
      "fetch_bytes_per_node": 20.9, "write_bytes_per_node": 756.0,
      "profile": "profiles/search_kernel_rcpsp120_single.md"},
