@@ -308,8 +308,8 @@ def fixpoint_leg(peaks, nbox=4096, fbox=1024, reps=5):
                    nearly all empty), outward-rounded linear tells on float32
                    bounds
     The float kernel's algorithmic LDS bytes: every sweep runs every row,
-    and each of a row's L term tells reads the bounds of the row's L terms
-    (8 bytes each), so 8 L^2 bytes per row and sweep."""
+    and a row reads the bounds of each of its L terms once (8 bytes each),
+    so 8 L bytes per row and sweep; the tells' atomics are not counted."""
     import numpy as np
     import torch
     from paper_2207_12116_amd import instances as I, pccp
@@ -371,7 +371,7 @@ def fixpoint_leg(peaks, nbox=4096, fbox=1024, reps=5):
     fsw = torch.zeros(fbox, dtype=torch.int32, device="cuda")
     t = timed(lambda: fs.propagate_batch(tl, tu, ol, ou, fst, fsw))
     L = np.diff(np.asarray(fm.row_ptr, dtype=np.int64))
-    per_sweep = int(8 * (L * L).sum())
+    per_sweep = int(8 * L.sum())
     sweeps = float(fsw.sum().item())
     fb = per_sweep * sweeps
     out["float"] = {"boxes": fbox, "variables": fm.nvars, "rows": fm.nrows,

@@ -39,6 +39,7 @@ CFG_PREC_ONLY = 4
 CFG_JOBSHOP = 5
 CFG_FLOAT_CSP = 6
 CFG_FLOAT_NET = 7
+CFG_FLOAT_EXTREME = 8
 
 
 class SplitMix64:
@@ -538,3 +539,45 @@ def float_network(n: int, seed: int, rows_per_var: int = 2, kmax: int = 6,
         val = sum(ai * pt[x] for ai, x in zip(a, xs))
         rows.append((a, xs, _f32(val + dom / 4.0 * _unit(rng))))
     return _fmodel([-dom] * n, [dom] * n, rows, dict(kind="float_network", n=n, seed=seed))
+
+
+# magnitudes for float_extreme: subnormal, tiny, ordinary, huge and the top
+# of the float32 range
+_EXT_COEF = (1.4e-45, 3e-39, 1e-30, 0.5, 1.0, 3.0, 7e5, 1e30, 3.4e38)
+_EXT_BOUND = (-3.4e38, -1e30, -1e5, -1.0, -1e-40, 0.0, 1e-40, 1.0, 1e5, 1e30, 3.4e38)
+_EXT_SLACK = (0.0, 1e-42, 1e-20, 1.0, 1e10, 1e30)
+
+
+def float_extreme(seed: int, n: int = 30, nrows: int = 50, kmax: int = 10) -> FModel:
+    """A small system over the reals whose bounds, coefficients and
+    right-hand sides span the float32 range, from subnormals to 3.4e38, so
+    that products and sums overflow, underflow and cancel: n variables with
+    bounds drawn from a fixed ladder of magnitudes, up to nrows rows of
+    1..kmax distinct variables, each row's right-hand side the float at or
+    above what a random point of the box gives it plus a slack (rows whose
+    right-hand side would leave the float range are dropped)."""
+    rng = stream(CFG_FLOAT_EXTREME, seed)
+    pick = lambda xs: xs[rng.below(len(xs))]
+    lb, ub, pt = [], [], []
+    for _ in range(n):
+        a, b = sorted((pick(_EXT_BOUND), pick(_EXT_BOUND)))
+        lb.append(a)
+        ub.append(b)
+        pt.append(_f32(a + (b - a) * _unit(rng)))
+    rows = []
+    for _ in range(nrows):
+        k = rng.uniform(1, kmax)
+        xs = set()
+        while len(xs) < k:
+            xs.add(rng.below(n))
+        xs = sorted(xs)
+        a = [_f32(pick(_EXT_COEF) * (1.0 if rng.below(2) else -1.0)) for _ in xs]
+        val = sum(ai * pt[x] for ai, x in zip(a, xs))
+        c = val + abs(val) * pick((0.0, 1e-6, 0.5)) + pick(_EXT_SLACK)
+        if not abs(c) < 3.4e38:
+            continue
+        cf = np.float32(c)
+        if float(cf) < c:
+            cf = np.nextafter(cf, np.float32(np.inf))
+        rows.append((a, xs, float(cf)))
+    return _fmodel(lb, ub, rows, dict(kind="float_extreme", seed=seed))

@@ -65,7 +65,10 @@ def _run(P, model, boxes, wg):
 
 FMODELS = [("csp%d" % s, lambda s=s: I.float_csp(s)) for s in (0, 1, 2, 3)] + \
           [("net100", lambda: I.float_network(100, 1)), ("net1000", lambda: I.float_network(1000, 2)),
-           ("net4000", lambda: I.float_network(4000, 3, rows_per_var=1))]
+           ("net4000", lambda: I.float_network(4000, 3, rows_per_var=1)),
+           # rows of 2..12 terms: rows longer than the kernel's register rows,
+           # and wavefronts whose rows differ in length
+           ("net300k12", lambda: I.float_network(300, 4, kmax=12))]
 
 
 @pytest.mark.parametrize("name,mk", FMODELS, ids=[m[0] for m in FMODELS])
@@ -89,6 +92,39 @@ def test_float_fixpoints_bit_exact(P, name, mk, wg):
             nfail += 1
     assert (gsw >= 1).all()
     say("float fixpoints", name, wg, "failed", nfail, "of", nbox)
+
+
+# Bounds, coefficients and right-hand sides from subnormals to 3.4e38: the
+# products and sums overflow to -inf, underflow to subnormals and cancel to
+# signed zeros, and the quotients leave the float range.  Small systems
+# (rows of 1..10 terms, every code path of the row kernel in mixed
+# wavefronts) and wide ones (hundreds of rows of each length, so whole
+# wavefronts share a length).  The oracle runs first: every case here takes
+# it at most a few sweeps.
+FEXT = [("ext%d" % s, lambda s=s: I.float_extreme(s), 64, 0.3) for s in range(4)] + \
+       [("ext_wide3_%d" % s, lambda s=s: I.float_extreme(s, n=1000, nrows=500, kmax=3), 16, 0.05)
+        for s in (4, 5)] + \
+       [("ext_wide4_%d" % s, lambda s=s: I.float_extreme(s, n=600, nrows=400, kmax=4), 16, 0.05)
+        for s in (4, 5)]
+
+
+@pytest.mark.parametrize("name,mk,nbox,frac", FEXT, ids=[m[0] for m in FEXT])
+def test_float_extreme_magnitudes_bit_exact(P, name, mk, nbox, frac):
+    model = mk()
+    om = O.OracleFModel(model)
+    boxes = _subboxes(model, random.Random(sum(map(ord, name))), nbox, frac)
+    refs = [O.fpropagate(om, lb0, ub0) for lb0, ub0 in boxes]
+    assert max(r[3] for r in refs) <= 20, name
+    say("float extreme", name, model.nvars, model.nrows, nbox)
+    gst, glb, gub, _ = _run(P, model, boxes, 256)
+    nfix = 0
+    for k, (st, lb, ub, _) in enumerate(refs):
+        assert int(gst[k]) == st, (name, k)
+        if st == O.FIXPOINT:
+            nfix += 1
+            assert np.array_equal(glb[k].view(np.uint32), lb.view(np.uint32)), (name, k)
+            assert np.array_equal(gub[k].view(np.uint32), ub.view(np.uint32)), (name, k)
+    say("float extreme", name, "fixed points", nfix, "of", nbox)
 
 
 def test_float_failure_and_zeros(P):

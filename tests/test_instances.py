@@ -74,3 +74,21 @@ def test_rcpsp_demand_density():
     assert 0.45 < frac_zero < 0.55
     nz = dem[dem > 0]
     assert nz.min() == 1 and nz.max() == 10
+
+
+def test_float_extreme_models_valid_and_seeded():
+    """float_extreme: deterministic per seed; finite bounds with lb <= ub,
+    finite nonzero coefficients, distinct variables per row, finite
+    right-hand sides; magnitudes reach both ends of the float32 range."""
+    a, b = I.float_extreme(3), I.float_extreme(3)
+    assert np.array_equal(a.coef, b.coef) and np.array_equal(a.rhs, b.rhs)
+    assert not np.array_equal(I.float_extreme(4).lb, a.lb)
+    for s in range(4):
+        m = I.float_extreme(s)
+        assert np.isfinite(m.lb).all() and np.isfinite(m.ub).all() and (m.lb <= m.ub).all()
+        assert np.isfinite(m.coef).all() and (m.coef != 0).all() and np.isfinite(m.rhs).all()
+        for r in range(m.nrows):
+            xs = m.var[m.row_ptr[r]:m.row_ptr[r + 1]]
+            assert len(set(xs.tolist())) == len(xs) >= 1
+        mags = np.abs(np.concatenate([m.coef, m.lb, m.ub]))
+        assert mags.max() > 1e38 and mags[mags > 0].min() < 1e-38
