@@ -491,7 +491,9 @@ int32_t pccp_fmodel_add_vars(pccp_fmodel *m, int32_t n, const float *lb, const f
 int32_t pccp_fmodel_add_linear_le(pccp_fmodel *m, int32_t nterms, const float *coef,
                                   const int32_t *var, float rhs);
 
-/* Validate the float model and upload its tables to the current device.
+/* Validate the float model and upload its tables to the current device
+ * (the rows in order of their length, and slot-major copies of the terms of
+ * rows of up to 8 terms: about 16 bytes per term plus 128 bytes per row).
  * wg_size: threads per workgroup (multiple of 64, <= 1024; 0 = 256).
  * PCCP_E_MODEL for a non-finite bound or coefficient, a zero coefficient,
  * an index out of range or a variable repeated in a row;
@@ -500,9 +502,10 @@ int32_t pccp_fsolver_create(const pccp_fmodel *m, int32_t wg_size, void *stream,
                             pccp_fsolver **out);
 int32_t pccp_fsolver_destroy(pccp_fsolver *s);
 
-/* Fixed points of nbox float boxes, one workgroup per box, every term's
- * tell running concurrently with LDS atomic max / min on the bounds' total-
- * order keys (§5 fixed point loop on the float lattices).  The tells are
+/* Fixed points of nbox float boxes, one workgroup per box, one lane per
+ * row running its terms' tells concurrently with the other rows' (LDS
+ * atomic max / min on the bounds' total-order keys; §5 fixed point loop on
+ * the float lattices).  The tells are
  * monotone, so the result is the least fixed point (§3, Theorem 2): the
  * same store, bit for bit, as a sequential loop.  All pointers are device
  * memory: lb_in/ub_in/lb_out/ub_out are [nbox][nvars] float32 (zeros of the
