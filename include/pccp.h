@@ -493,7 +493,7 @@ int32_t pccp_fmodel_add_linear_le(pccp_fmodel *m, int32_t nterms, const float *c
 
 /* Validate the float model and upload its tables to the current device
  * (the rows in order of their length, and slot-major copies of the terms of
- * rows of up to 8 terms: about 16 bytes per term plus 128 bytes per row).
+ * rows of up to 8 terms: 8 bytes per term plus 140 bytes per row).
  * wg_size: threads per workgroup (multiple of 64, <= 1024; 0 = 256).
  * PCCP_E_MODEL for a non-finite bound or coefficient, a zero coefficient,
  * an index out of range or a variable repeated in a row;
