@@ -68,7 +68,9 @@ FMODELS = [("csp%d" % s, lambda s=s: I.float_csp(s)) for s in (0, 1, 2, 3)] + \
            ("net4000", lambda: I.float_network(4000, 3, rows_per_var=1)),
            # rows of 2..12 terms: rows longer than the kernel's register rows,
            # and wavefronts whose rows differ in length
-           ("net300k12", lambda: I.float_network(300, 4, kmax=12))]
+           ("net300k12", lambda: I.float_network(300, 4, kmax=12)),
+           # a store of 120 KB: most of a workgroup's LDS
+           ("net15000", lambda: I.float_network(15000, 5, rows_per_var=1))]
 
 
 @pytest.mark.parametrize("name,mk", FMODELS, ids=[m[0] for m in FMODELS])
